@@ -1,0 +1,213 @@
+/*
+ * sapmi.h - C ABI of the MI355X (gfx950) library for the hot path of the
+ * Schwarz-preconditioned two-flavour HMC with a one-dimensional (x0-only) domain
+ * decomposition (M. Hasenbusch, Lattice 2007, arXiv:0710.0066).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice (Sec. 1): sites x = (x0, x1, x2, x3), 0 <= x_mu < L_mu, lexicographic index
+ *   i = ((x0*L1 + x1)*L2 + x2)*L3 + x3 (x0 slowest), parity p(x) = (x0+x1+x2+x3) mod 2.
+ *   Gauge links periodic; fermion hops periodic in space and antiperiodic in x0.
+ *   All L_mu must be even.
+ * Gamma matrices (Sec. 1, eq. 2 leaves the representation open): chiral basis,
+ *   gamma_0 = [[0,-1],[-1,0]], gamma_k = [[0,-i sigma_k],[i sigma_k,0]] (2x2 blocks),
+ *   gamma_5 = diag(1,1,-1,-1).
+ * x0 blocks (Sec. 1, one-dimensional decomposition): level 1 has blocks of l0 slices,
+ *   level 2 of l0_sub slices; block b = floor(x0 / l). Colours: black = odd b.
+ *   Requires L0 % (2*l0) == 0 and l0 >= 2; level 2 requires l0 % (2*l0_sub) == 0 and
+ *   l0_sub >= 2.
+ *
+ * Canonical interchange layout (device memory, complex128 = two float64):
+ *   gauge   U[i][mu][row][col]                 9 complex per link
+ *   spinor  psi[rhs][i][spin][colour]          12 complex per site and rhs
+ *   force   F[i][mu][a] (float64, a = 0..7)    coefficients on T^a = lambda^a / 2
+ * Library field layout ("sap layout"), used by every hot entry point:
+ *   spinor  [rhs][parity][12][V/2] of complex at the field precision, component
+ *           c = 3*spin + colour, site index j = i / 2 within its parity.
+ *   sap_field_bytes() gives the size; sap_pack_spinor / sap_unpack_spinor convert.
+ *   momentum / force fields in the sap layout: [mu][parity][8][V/2] float64.
+ *
+ * Ownership and streams: every array argument is a DEVICE pointer allocated and freed
+ * by the caller unless its comment says "host". The library never keeps a caller
+ * pointer past the call. A context owns its gauge copies and workspace (allocated by
+ * sap_create / sap_set_gauge; hot calls do not allocate). All work is queued on the
+ * caller's HIP stream (passed as void*, NULL = default stream); calls that return
+ * host scalars synchronise that stream before returning. A context is not
+ * thread-safe; use one per stream.
+ *
+ * Errors: every call returns a sap_status; nothing aborts or throws across the ABI.
+ * Argument checks run on the host before any HIP call. sap_last_error() describes
+ * the last failure of a context.
+ */
+#ifndef SAPMI_H
+#define SAPMI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sap_ctx sap_ctx;
+
+typedef enum {
+  SAP_OK = 0,
+  SAP_E_ARG = -1,        /* invalid argument or geometry */
+  SAP_E_NOMEM = -2,      /* device allocation failed */
+  SAP_E_HIP = -3,        /* a HIP runtime call failed */
+  SAP_E_NOCONV = -4,     /* solver stopped at max_iter / max_outer; info is filled */
+  SAP_E_NONFINITE = -5,  /* NaN or Inf met in a residual */
+  SAP_E_STATE = -6       /* call out of order (e.g. no gauge field set) */
+} sap_status;
+
+typedef enum { SAP_F64 = 0, SAP_F32 = 1 } sap_prec;            /* storage and arithmetic */
+typedef enum { SAP_ALL = 0, SAP_BLACK = 1, SAP_WHITE = 2 } sap_color;
+
+typedef struct {
+  int L[4];          /* L0 (x0 extent) .. L3 */
+  int l0;            /* level-1 block length along x0 */
+  int l0_sub;        /* level-2 block length (0: level 2 unused) */
+  double kappa;      /* hopping parameter of eq. 2 */
+  int max_rhs;       /* largest nrhs any call will pass (sizes the workspace) */
+} sap_geom;
+
+typedef struct {
+  double tol;        /* stop when ||b - A x|| / ||b|| <= tol, recomputed in FP64 */
+  int max_iter;      /* cap on inner iterations summed over outer cycles */
+  sap_prec inner_prec; /* precision of the inner Krylov solve */
+  double inner_tol;  /* relative reduction asked of each inner solve (defect correction) */
+  int max_outer;     /* cap on FP64 defect-correction cycles */
+} sap_solve_opts;
+
+typedef struct {
+  int iters;            /* inner iterations in which this system was still active */
+  int outer;            /* defect-correction cycles */
+  double true_rel_res;  /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
+} sap_solve_info;
+
+typedef struct {
+  double beta;          /* gauge coupling of the Wilson plaquette action */
+  double tau;           /* trajectory length */
+  double lambda;        /* Sexton-Weingarten parameter (1/6 in the paper) */
+  int n_outer;          /* steps of the pseudo-fermion level per trajectory */
+  int n_inner;          /* gauge steps per pseudo-fermion step (even for SW) */
+  int scheme_outer;     /* 0 leap-frog, 1 Sexton-Weingarten */
+  int scheme_inner;
+  sap_solve_opts force_solve;   /* solves inside the molecular dynamics */
+  sap_solve_opts action_solve;  /* solves for the actions entering dH */
+  const double* p0;     /* momenta, sap layout [mu][parity][8][V/2] */
+  const double* xi1;    /* heat-bath noise for phi1 = W1 xi1, canonical spinor */
+  const double* xi2;    /* heat-bath noise for chi = R_hat Pi xi2, canonical spinor */
+  double u_metropolis;  /* uniform number in [0,1) for the accept step */
+} sap_hmc_params;
+
+typedef struct {
+  double dH, H0, H1;
+  double S_G0, S_G1, S_W0, S_W1, S_R0, S_R1;
+  double plaq;          /* mean plaquette of the returned field */
+  int accepted;
+  long long solver_iters; /* inner iterations of every solve in the trajectory */
+} sap_hmc_info;
+
+/* ---- context ---------------------------------------------------------------- */
+
+/* Version of this ABI (major*100 + minor). */
+int sap_version(void);
+
+/* Host-only geometry check (no HIP call): SAP_OK or SAP_E_ARG. */
+int sap_check_geom(const sap_geom* g);
+
+/* Create a context on the current HIP device; allocates its gauge copies and the
+ * solver workspace for g->max_rhs right-hand sides. *out = NULL on failure. */
+int sap_create(const sap_geom* g, sap_ctx** out);
+void sap_destroy(sap_ctx* ctx);
+const char* sap_last_error(const sap_ctx* ctx);
+
+/* Bytes of one spinor field of nrhs right-hand sides in the sap layout. */
+size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs);
+
+/* Load the gauge field from the canonical layout (device, complex128) into the
+ * context's FP64 and FP32 copies. */
+int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream);
+/* Copy the context's FP64 gauge field back to the canonical layout. */
+int sap_get_gauge(sap_ctx* ctx, double* U, void* stream);
+
+/* Canonical complex128 spinor(s) -> sap layout at precision prec, and back. */
+int sap_pack_spinor(sap_ctx* ctx, void* out, const double* in, int nrhs, sap_prec prec,
+                    void* stream);
+int sap_unpack_spinor(sap_ctx* ctx, double* out, const void* in, int nrhs, sap_prec prec,
+                      void* stream);
+/* Canonical float64 [i][mu][8] <-> sap layout [mu][parity][8][V/2]. */
+int sap_pack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream);
+int sap_unpack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream);
+
+/* ---- operators ---------------------------------------------------------------- */
+
+/* out = M in (Sec. 1, eq. 2) for nrhs fields in the sap layout at precision prec
+ * (FP64: float64 arithmetic; FP32: float32 storage and arithmetic). out and in must
+ * not overlap. */
+int apply_M(sap_ctx* ctx, void* out, const void* in, int nrhs, sap_prec prec, void* stream);
+
+/* out = W_level in: M with every hop between different x0 blocks of the given level
+ * removed (Sec. 1, block decomposition; level 1: l0, level 2: l0_sub). Only sites of
+ * the selected blocks are written with W in; every other site of out is set to zero.
+ * block >= 0 selects that single block (color is then ignored), block = -1 selects
+ * all blocks of the given colour. */
+int apply_W1_block(sap_ctx* ctx, void* out, const void* in, int nrhs, int level, int block,
+                   sap_color color, sap_prec prec, void* stream);
+
+/* ---- solvers ------------------------------------------------------------------ */
+
+/* Solve M x = b for nrhs FP64 fields (sap layout): even-odd reduced CG on the normal
+ * equations (the Schur complement of Sec. 1's W_eo construction applied to M), run in
+ * opts->inner_prec inside an FP64 defect-correction loop, until
+ * ||b - M x|| / ||b|| <= opts->tol with M applied in FP64. x is overwritten (the
+ * initial content is ignored). info: host array of nrhs entries (may be NULL).
+ * Returns SAP_E_NOCONV if a system misses tol within the caps. Synchronises. */
+int solve_full(sap_ctx* ctx, double* x, const double* b, int nrhs, const sap_solve_opts* opts,
+               sap_solve_info* info, void* stream);
+
+/* Solve W_level x = b on every selected block as an independent system (all blocks
+ * and all nrhs fields batched in each kernel launch). Sites outside the selected
+ * colour are set to zero in x. info: host array of nblocks(level)*nrhs entries
+ * ordered [rhs][block] (entries of unselected blocks are zeroed). Synchronises. */
+int solve_blocks(sap_ctx* ctx, double* x, const double* b, int nrhs, int level,
+                 sap_color color, const sap_solve_opts* opts, sap_solve_info* info,
+                 void* stream);
+
+/* ---- forces -------------------------------------------------------------------- */
+
+/* F += coef * dS/dw for S = ||W1^{-1} phi||^2 (Sec. 1, eq. factorpf with W = W1) along
+ * U_mu(x) -> exp(i w T^a) U_mu(x); phi is one FP64 field (sap layout), F is a sap-layout
+ * momentum field. *S_out (host, may be NULL) receives S. Synchronises. */
+int block_pf_force(sap_ctx* ctx, double* F, double coef, const double* phi,
+                   const sap_solve_opts* opts, double* S_out, void* stream);
+
+/* F += coef * dS_R/dw for the Schwarz boundary action S_R = ||R_hat^{-1} chi||^2 of
+ * det^2(W1^{-1} M) on the black-block boundaries (Sec. 1). chi: one FP64 field (sap
+ * layout) that vanishes off the first/last slices of black level-1 blocks and lies in
+ * the range of the spin projector (1 -/+ gamma_0)/2 there (checked: SAP_E_ARG).
+ * *S_R_out (host, may be NULL) receives S_R. Needs two full solves. Synchronises. */
+int schwarz_boundary_force(sap_ctx* ctx, double* F, double coef, const double* chi,
+                           const sap_solve_opts* opts, double* S_R_out, void* stream);
+
+/* Gauge force of the Wilson plaquette action S_G (Sec. 1): F += coef * dS_G/dw.
+ * *S_G_out (host, may be NULL) receives S_G. */
+int gauge_force(sap_ctx* ctx, double* F, double coef, double beta, double* S_G_out,
+                void* stream);
+
+/* ---- HMC ------------------------------------------------------------------------ */
+
+/* One HMC trajectory (Sec. 2) with two time scales: the outer level integrates
+ * S_pf = ||W1^{-1} phi1||^2 + ||R_hat^{-1} chi||^2, the inner level the gauge action;
+ * steps T_U: U -> exp(i dt P) U (FP64 exponential + reunitarisation) and
+ * T_P: p -> p - dt F; leap-frog or Sexton-Weingarten per level; Metropolis with
+ * p->u_metropolis. U: canonical gauge field, replaced by the new field if accepted
+ * (left unchanged otherwise); the context's gauge copies end equal to U. info: host. */
+int hmc_trajectory(sap_ctx* ctx, double* U, const sap_hmc_params* p, sap_hmc_info* info,
+                   void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAPMI_H */

@@ -1,0 +1,247 @@
+"""Python binding of libsapmi (include/sapmi.h): argument marshalling only.
+
+Every operator, solve, force and trajectory runs in the library's HIP kernels on the
+current HIP device; PyTorch only allocates device memory and supplies the stream. There
+is no CPU fallback: if the shared library has not been built this module raises on
+import.
+
+The module-level functions carry the C names (apply_M, apply_W1_block, solve_full,
+solve_blocks, block_pf_force, schwarz_boundary_force, gauge_force, hmc_trajectory,
+sap_*); ``Context`` wraps a ``sap_ctx*`` and allocates fields with torch.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from .build import LIB as _LIB_PATH
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_0710_0066_amd.build`")
+
+_lib = ctypes.CDLL(_LIB_PATH)
+
+SAP_OK, SAP_E_ARG, SAP_E_NOMEM, SAP_E_HIP, SAP_E_NOCONV, SAP_E_NONFINITE, SAP_E_STATE = \
+    0, -1, -2, -3, -4, -5, -6
+SAP_F64, SAP_F32 = 0, 1
+SAP_ALL, SAP_BLACK, SAP_WHITE = 0, 1, 2
+_STATUS = {0: "SAP_OK", -1: "SAP_E_ARG", -2: "SAP_E_NOMEM", -3: "SAP_E_HIP", -4: "SAP_E_NOCONV",
+           -5: "SAP_E_NONFINITE", -6: "SAP_E_STATE"}
+
+
+class SapError(RuntimeError):
+    def __init__(self, code, msg, info=None):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.info = info
+
+
+class sap_geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 4), ("l0", ctypes.c_int), ("l0_sub", ctypes.c_int),
+                ("kappa", ctypes.c_double), ("max_rhs", ctypes.c_int)]
+
+
+class sap_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("inner_prec", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int)]
+
+
+class sap_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("true_rel_res", ctypes.c_double)]
+
+
+class sap_hmc_params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("tau", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("n_outer", ctypes.c_int), ("n_inner", ctypes.c_int),
+                ("scheme_outer", ctypes.c_int), ("scheme_inner", ctypes.c_int),
+                ("force_solve", sap_solve_opts), ("action_solve", sap_solve_opts),
+                ("p0", ctypes.c_void_p), ("xi1", ctypes.c_void_p), ("xi2", ctypes.c_void_p),
+                ("u_metropolis", ctypes.c_double)]
+
+
+class sap_hmc_info(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_double), ("H0", ctypes.c_double), ("H1", ctypes.c_double),
+                ("S_G0", ctypes.c_double), ("S_G1", ctypes.c_double),
+                ("S_W0", ctypes.c_double), ("S_W1", ctypes.c_double),
+                ("S_R0", ctypes.c_double), ("S_R1", ctypes.c_double),
+                ("plaq", ctypes.c_double), ("accepted", ctypes.c_int),
+                ("solver_iters", ctypes.c_longlong)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    "sap_version": ([], _I),
+    "sap_check_geom": ([ctypes.POINTER(sap_geom)], _I),
+    "sap_create": ([ctypes.POINTER(sap_geom), ctypes.POINTER(_P)], _I),
+    "sap_destroy": ([_P], None),
+    "sap_last_error": ([_P], ctypes.c_char_p),
+    "sap_field_bytes": ([_P, _I, _I], ctypes.c_size_t),
+    "sap_set_gauge": ([_P, _P, _P], _I),
+    "sap_get_gauge": ([_P, _P, _P], _I),
+    "sap_pack_spinor": ([_P, _P, _P, _I, _I, _P], _I),
+    "sap_unpack_spinor": ([_P, _P, _P, _I, _I, _P], _I),
+    "sap_pack_momenta": ([_P, _P, _P, _P], _I),
+    "sap_unpack_momenta": ([_P, _P, _P, _P], _I),
+    "apply_M": ([_P, _P, _P, _I, _I, _P], _I),
+    "apply_W1_block": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
+    "solve_full": ([_P, _P, _P, _I, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
+    "solve_blocks": ([_P, _P, _P, _I, _I, _I, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
+    "block_pf_force": ([_P, _P, _D, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
+    "schwarz_boundary_force": ([_P, _P, _D, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
+    "gauge_force": ([_P, _P, _D, _D, _P, _P], _I),
+    "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
+}
+for _name, (_args, _ret) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _ret
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(ctx_ptr, rc, info=None):
+    if rc != SAP_OK:
+        msg = _lib.sap_last_error(ctx_ptr)
+        raise SapError(rc, msg.decode() if msg else "", info)
+
+
+def sap_version() -> int:
+    return _lib.sap_version()
+
+
+def sap_check_geom(L, l0, l0_sub=0, kappa=0.1, max_rhs=1) -> int:
+    g = sap_geom((ctypes.c_int * 4)(*L), l0, l0_sub, kappa, max_rhs)
+    return _lib.sap_check_geom(ctypes.byref(g))
+
+
+def solve_opts(tol=1e-10, max_iter=100000, inner_prec=SAP_F32, inner_tol=1e-5, max_outer=50):
+    return sap_solve_opts(tol, max_iter, inner_prec, inner_tol, max_outer)
+
+
+# ---- C entry points with their own names -------------------------------------------
+
+def apply_M(ctx, out, inp, nrhs, prec):
+    _check(ctx.ptr, _lib.apply_M(ctx.ptr, _ptr(out), _ptr(inp), nrhs, prec, _stream()))
+
+
+def apply_W1_block(ctx, out, inp, nrhs, level=1, block=-1, color=SAP_ALL, prec=SAP_F64):
+    _check(ctx.ptr, _lib.apply_W1_block(ctx.ptr, _ptr(out), _ptr(inp), nrhs, level, block, color,
+                                        prec, _stream()))
+
+
+def solve_full(ctx, x, b, nrhs, opts):
+    info = (sap_solve_info * nrhs)()
+    rc = _lib.solve_full(ctx.ptr, _ptr(x), _ptr(b), nrhs, ctypes.byref(opts), info, _stream())
+    _check(ctx.ptr, rc, info)
+    return list(info)
+
+
+def solve_blocks(ctx, x, b, nrhs, level, color, opts):
+    nb = ctx.nblocks(level)
+    info = (sap_solve_info * (nb * nrhs))()
+    rc = _lib.solve_blocks(ctx.ptr, _ptr(x), _ptr(b), nrhs, level, color, ctypes.byref(opts), info,
+                           _stream())
+    _check(ctx.ptr, rc, info)
+    return list(info)
+
+
+def block_pf_force(ctx, F, coef, phi, opts):
+    S = ctypes.c_double(0.0)
+    _check(ctx.ptr, _lib.block_pf_force(ctx.ptr, _ptr(F), coef, _ptr(phi), ctypes.byref(opts),
+                                        ctypes.byref(S), _stream()))
+    return S.value
+
+
+def schwarz_boundary_force(ctx, F, coef, chi, opts):
+    S = ctypes.c_double(0.0)
+    _check(ctx.ptr, _lib.schwarz_boundary_force(ctx.ptr, _ptr(F), coef, _ptr(chi),
+                                                ctypes.byref(opts), ctypes.byref(S), _stream()))
+    return S.value
+
+
+def gauge_force(ctx, F, coef, beta):
+    S = ctypes.c_double(0.0)
+    _check(ctx.ptr, _lib.gauge_force(ctx.ptr, _ptr(F), coef, beta, ctypes.byref(S), _stream()))
+    return S.value
+
+
+def hmc_trajectory(ctx, U, params):
+    info = sap_hmc_info()
+    _check(ctx.ptr, _lib.hmc_trajectory(ctx.ptr, _ptr(U), ctypes.byref(params), ctypes.byref(info),
+                                        _stream()))
+    return info
+
+
+# ---- context ------------------------------------------------------------------------
+
+class Context:
+    """Owns one ``sap_ctx``: geometry, gauge copies and solver workspace on the current
+    HIP device. Fields are torch tensors in the library layout (see ``include/sapmi.h``)."""
+
+    def __init__(self, L, l0, kappa, l0_sub=0, max_rhs=1):
+        self.L = tuple(int(v) for v in L)
+        self.l0, self.l0_sub, self.kappa, self.max_rhs = int(l0), int(l0_sub), float(kappa), int(max_rhs)
+        self.V = self.L[0] * self.L[1] * self.L[2] * self.L[3]
+        self.Vh = self.V // 2
+        g = sap_geom((ctypes.c_int * 4)(*self.L), self.l0, self.l0_sub, self.kappa, self.max_rhs)
+        p = ctypes.c_void_p()
+        rc = _lib.sap_create(ctypes.byref(g), ctypes.byref(p))
+        _check(None, rc)
+        self.ptr = p
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            _lib.sap_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def nblocks(self, level):
+        return self.L[0] // (self.l0 if level == 1 else self.l0_sub)
+
+    # allocation helpers (torch is only the allocator here)
+    def new_field(self, nrhs=1, prec=SAP_F64):
+        import torch
+        n = self.V * 12 * 2 * nrhs
+        dt = torch.float64 if prec == SAP_F64 else torch.float32
+        return torch.zeros(n, dtype=dt, device="cuda")
+
+    def new_momenta(self):
+        import torch
+        return torch.zeros(self.V * 4 * 8, dtype=torch.float64, device="cuda")
+
+    def set_gauge(self, U):
+        """U: canonical complex128 gauge field on the device (any shape with V*4*9 entries)."""
+        _check(self.ptr, _lib.sap_set_gauge(self.ptr, _ptr(U), _stream()))
+
+    def get_gauge(self, U):
+        _check(self.ptr, _lib.sap_get_gauge(self.ptr, _ptr(U), _stream()))
+
+    def pack_spinor(self, out, psi, nrhs, prec=SAP_F64):
+        _check(self.ptr, _lib.sap_pack_spinor(self.ptr, _ptr(out), _ptr(psi), nrhs, prec, _stream()))
+
+    def unpack_spinor(self, out, f, nrhs, prec=SAP_F64):
+        _check(self.ptr, _lib.sap_unpack_spinor(self.ptr, _ptr(out), _ptr(f), nrhs, prec, _stream()))
+
+    def pack_momenta(self, out, p):
+        _check(self.ptr, _lib.sap_pack_momenta(self.ptr, _ptr(out), _ptr(p), _stream()))
+
+    def unpack_momenta(self, out, f):
+        _check(self.ptr, _lib.sap_unpack_momenta(self.ptr, _ptr(out), _ptr(f), _stream()))

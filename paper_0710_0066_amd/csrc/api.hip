@@ -1,0 +1,233 @@
+// extern "C" entry points of libsapmi: argument checks (host only, before any HIP
+// call), context lifetime, layout conversions and the operator calls. Solver, force
+// and HMC entry points live in solver.hip, force.hip and hmc.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include "internal.h"
+
+using namespace sap;
+
+static thread_local std::string g_noctx_err;
+
+int sap_fail(sap_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_noctx_err = msg;
+  return code;
+}
+
+static std::string geom_problem(const sap_geom* g) {
+  if (!g) return "geometry pointer is NULL";
+  for (int mu = 0; mu < 4; ++mu) {
+    if (g->L[mu] < 2 || (g->L[mu] & 1))
+      return "L[" + std::to_string(mu) + "] = " + std::to_string(g->L[mu]) + " must be even and >= 2";
+    if (g->L[mu] > (1 << 16)) return "L[" + std::to_string(mu) + "] too large";
+  }
+  if (g->l0 < 2) return "l0 must be >= 2 (a black block needs distinct first and last slices)";
+  if (g->L[0] % (2 * g->l0) != 0) return "L0 must be a multiple of 2*l0 (red/black blocks)";
+  if (g->l0_sub != 0) {
+    if (g->l0_sub < 2) return "l0_sub must be 0 (unused) or >= 2";
+    if (g->l0 % (2 * g->l0_sub) != 0) return "l0 must be a multiple of 2*l0_sub";
+  }
+  if (!std::isfinite(g->kappa)) return "kappa must be finite";
+  if (g->max_rhs < 1 || g->max_rhs > 64) return "max_rhs must be in [1, 64]";
+  const long long V = (long long)g->L[0] * g->L[1] * g->L[2] * g->L[3];
+  if (V / 2 / 128 * g->max_rhs > (1LL << 30)) return "lattice too large for one launch";
+  return "";
+}
+
+extern "C" {
+
+int sap_version(void) { return 100; }
+
+int sap_check_geom(const sap_geom* g) {
+  std::string p = geom_problem(g);
+  if (!p.empty()) return sap_fail(nullptr, SAP_E_ARG, p);
+  return SAP_OK;
+}
+
+const char* sap_last_error(const sap_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_noctx_err.c_str();
+}
+
+size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs) {
+  if (!ctx || nrhs < 1) return 0;
+  const size_t per = prec == SAP_F64 ? sizeof(double2) : sizeof(float2);
+  return (size_t)ctx->V * 12 * per * (size_t)nrhs;
+}
+
+void sap_solver_destroy(sap_ctx* ctx);   // solver.hip
+int sap_solver_create(sap_ctx* ctx);     // solver.hip
+
+int sap_create(const sap_geom* g, sap_ctx** out) {
+  if (!out) return sap_fail(nullptr, SAP_E_ARG, "out pointer is NULL");
+  *out = nullptr;
+  std::string p = geom_problem(g);
+  if (!p.empty()) return sap_fail(nullptr, SAP_E_ARG, p);
+  sap_ctx* c = new sap_ctx();
+  c->geom = *g;
+  c->g = make_geo(g->L);
+  c->V = 2 * c->g.Vh;
+  c->Vh = c->g.Vh;
+  c->have_gauge = false;
+  c->U64 = nullptr;
+  c->U32 = nullptr;
+  c->solver = nullptr;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return sap_fail(nullptr, SAP_E_HIP, "hipGetDevice failed (no HIP device?)");
+  }
+  const size_t nlink = (size_t)4 * 9 * c->V;
+  if (hipMalloc((void**)&c->U64, nlink * sizeof(double2)) != hipSuccess ||
+      hipMalloc((void**)&c->U32, nlink * sizeof(float2)) != hipSuccess) {
+    sap_destroy(c);
+    return sap_fail(nullptr, SAP_E_NOMEM, "cannot allocate the gauge copies");
+  }
+  int rc = sap_solver_create(c);
+  if (rc != SAP_OK) {
+    std::string m = c->err;
+    sap_destroy(c);
+    return sap_fail(nullptr, rc, m);
+  }
+  *out = c;
+  return SAP_OK;
+}
+
+void sap_destroy(sap_ctx* ctx) {
+  if (!ctx) return;
+  sap_solver_destroy(ctx);
+  if (ctx->U64) (void)hipFree(ctx->U64);
+  if (ctx->U32) (void)hipFree(ctx->U32);
+  delete ctx;
+}
+
+int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream) {
+  if (!ctx) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!U) return sap_fail(ctx, SAP_E_ARG, "U is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  launch_pack_gauge(ctx->g, ctx->U64, ctx->U32, (const double2*)U, s);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  ctx->have_gauge = true;
+  return SAP_OK;
+}
+
+int sap_get_gauge(sap_ctx* ctx, double* U, void* stream) {
+  if (!ctx) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!U) return sap_fail(ctx, SAP_E_ARG, "U is NULL");
+  if (!ctx->have_gauge) return sap_fail(ctx, SAP_E_STATE, "no gauge field set");
+  launch_unpack_gauge(ctx->g, (double2*)U, ctx->U64, (hipStream_t)stream);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  return SAP_OK;
+}
+
+static int check_fields(sap_ctx* ctx, const void* a, const void* b, int nrhs, int prec) {
+  if (!ctx) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!a || !b) return sap_fail(ctx, SAP_E_ARG, "field pointer is NULL");
+  if (nrhs < 1 || nrhs > ctx->geom.max_rhs)
+    return sap_fail(ctx, SAP_E_ARG, "nrhs must be in [1, max_rhs]");
+  if (prec != SAP_F64 && prec != SAP_F32) return sap_fail(ctx, SAP_E_ARG, "unknown precision");
+  return SAP_OK;
+}
+
+int sap_pack_spinor(sap_ctx* ctx, void* out, const double* in, int nrhs, sap_prec prec, void* stream) {
+  int rc = check_fields(ctx, out, in, nrhs, prec);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == SAP_F64) launch_pack_spinor<double>(ctx->g, (double2*)out, (const double2*)in, nrhs, s);
+  else launch_pack_spinor<float>(ctx->g, (float2*)out, (const double2*)in, nrhs, s);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  return SAP_OK;
+}
+
+int sap_unpack_spinor(sap_ctx* ctx, double* out, const void* in, int nrhs, sap_prec prec, void* stream) {
+  int rc = check_fields(ctx, out, in, nrhs, prec);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == SAP_F64) launch_unpack_spinor<double>(ctx->g, (double2*)out, (const double2*)in, nrhs, s);
+  else launch_unpack_spinor<float>(ctx->g, (double2*)out, (const float2*)in, nrhs, s);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  return SAP_OK;
+}
+
+int sap_pack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream) {
+  if (!ctx) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!out || !in) return sap_fail(ctx, SAP_E_ARG, "pointer is NULL");
+  launch_pack_momenta(ctx->g, out, in, (hipStream_t)stream);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  return SAP_OK;
+}
+
+int sap_unpack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream) {
+  if (!ctx) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!out || !in) return sap_fail(ctx, SAP_E_ARG, "pointer is NULL");
+  launch_unpack_momenta(ctx->g, out, in, (hipStream_t)stream);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  return SAP_OK;
+}
+
+}  // extern "C"
+
+namespace sap {
+
+template <class R>
+static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, int colour,
+                    int block, hipStream_t s) {
+  HopArgs<R> A;
+  typedef typename vec2<R>::type V2;
+  const long long Vh = ctx->Vh;
+  A.out = {(V2*)out, 24 * Vh, 12 * Vh};
+  A.in = {(V2*)in, 24 * Vh, 12 * Vh};
+  A.x = A.in;
+  A.U = (const V2*)(sizeof(R) == 8 ? (const void*)ctx->U64 : (const void*)ctx->U32);
+  A.g = ctx->g;
+  A.nrhs = nrhs;
+  A.parity_out = -1;
+  A.lb = lb;
+  A.colour = colour;
+  A.block = block;
+  A.a = R(1);
+  A.b = R(-ctx->geom.kappa);
+  A.g5_in = 0;
+  A.g5_out = 0;
+  launch_hop<R>(A, s);
+}
+
+int apply_op_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, int colour, int block,
+                 sap_prec prec, hipStream_t s) {
+  if (prec == SAP_F64) full_op<double>(ctx, out, in, nrhs, lb, colour, block, s);
+  else full_op<float>(ctx, out, in, nrhs, lb, colour, block, s);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  return SAP_OK;
+}
+
+}  // namespace sap
+
+extern "C" {
+
+int apply_M(sap_ctx* ctx, void* out, const void* in, int nrhs, sap_prec prec, void* stream) {
+  int rc = check_fields(ctx, out, in, nrhs, prec);
+  if (rc) return rc;
+  if (out == in) return sap_fail(ctx, SAP_E_ARG, "out and in must not alias");
+  if (!ctx->have_gauge) return sap_fail(ctx, SAP_E_STATE, "no gauge field set");
+  return apply_op_any(ctx, out, in, nrhs, 0, 0, -1, prec, (hipStream_t)stream);
+}
+
+int apply_W1_block(sap_ctx* ctx, void* out, const void* in, int nrhs, int level, int block,
+                   sap_color color, sap_prec prec, void* stream) {
+  int rc = check_fields(ctx, out, in, nrhs, prec);
+  if (rc) return rc;
+  if (out == in) return sap_fail(ctx, SAP_E_ARG, "out and in must not alias");
+  if (!ctx->have_gauge) return sap_fail(ctx, SAP_E_STATE, "no gauge field set");
+  int lb;
+  if (level == 1) lb = ctx->geom.l0;
+  else if (level == 2 && ctx->geom.l0_sub > 0) lb = ctx->geom.l0_sub;
+  else return sap_fail(ctx, SAP_E_ARG, "level must be 1, or 2 with l0_sub set");
+  const int nb = ctx->geom.L[0] / lb;
+  if (block < -1 || block >= nb) return sap_fail(ctx, SAP_E_ARG, "block out of range");
+  if (color != SAP_ALL && color != SAP_BLACK && color != SAP_WHITE)
+    return sap_fail(ctx, SAP_E_ARG, "unknown colour");
+  return apply_op_any(ctx, out, in, nrhs, lb, (int)color, block, prec, (hipStream_t)stream);
+}
+
+}  // extern "C"

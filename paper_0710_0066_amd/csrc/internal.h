@@ -1,0 +1,80 @@
+// Host-side internals of libsapmi: the context, field descriptors and the launchers
+// each translation unit provides.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <string>
+#include <vector>
+#include "../../include/sapmi.h"
+#include "device_common.h"
+
+namespace sap {
+
+// A spinor field in the library layout: element (rhs, parity, component c, site j) of
+// complex type at  ptr + rhs*rs + parity*ps + c*Vh + j  (counted in complex numbers).
+// Full fields: rs = 24*Vh, ps = 12*Vh. Single-parity fields: rs = 12*Vh, ps = 0.
+template <class R> struct Field {
+  typename vec2<R>::type* ptr;
+  long long rs;
+  long long ps;
+};
+
+template <class R> struct HopArgs {
+  Field<R> out, in, x;     // out = a*x + b*D(in); x.ptr may be null
+  const typename vec2<R>::type* U;   // gauge [mu][parity][9][Vh]
+  Geo g;
+  int nrhs;
+  int parity_out;          // -1: both parities (full operator); 0/1: that parity only
+  int lb;                  // x0 block length, 0 = no blocks
+  int colour;              // 0 all, 1 black (odd b), 2 white (even b)
+  int block;               // >= 0: only this block (colour ignored)
+  R a, b;
+  int g5_in, g5_out;       // multiply the hop input / the hop result by gamma_5
+};
+
+template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
+
+// layout conversions
+template <class R>
+void launch_pack_spinor(const Geo& g, typename vec2<R>::type* out, const double2* in, int nrhs,
+                        hipStream_t s);
+template <class R>
+void launch_unpack_spinor(const Geo& g, double2* out, const typename vec2<R>::type* in,
+                          int nrhs, hipStream_t s);
+void launch_pack_gauge(const Geo& g, double2* U64, float2* U32, const double2* in, hipStream_t s);
+void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStream_t s);
+void launch_gauge_to_f32(const Geo& g, float2* U32, const double2* U64, hipStream_t s);
+void launch_pack_momenta(const Geo& g, double* out, const double* in, hipStream_t s);
+void launch_unpack_momenta(const Geo& g, double* out, const double* in, hipStream_t s);
+
+inline Geo make_geo(const int L[4]) {
+  Geo g;
+  g.L0 = L[0]; g.L1 = L[1]; g.L2 = L[2]; g.L3 = L[3];
+  g.L3h = L[3] / 2;
+  g.V3h = L[1] * L[2] * L[3] / 2;
+  g.Vh = (long long)L[0] * L[1] * L[2] * L[3] / 2;
+  return g;
+}
+
+}  // namespace sap
+
+struct sap_ctx {
+  sap_geom geom;
+  sap::Geo g;
+  long long V, Vh;
+  int device;
+  bool have_gauge;
+  double2* U64;   // [4][2][9][Vh]
+  float2* U32;
+  std::vector<void*> allocations;
+  std::string err;
+  void* solver;   // solver workspace (solver.hip)
+};
+
+// error helpers (api.hip)
+int sap_fail(sap_ctx* ctx, int code, const std::string& msg);
+#define SAP_HIP_CHECK(ctx, call)                                                     \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return sap_fail((ctx), SAP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)

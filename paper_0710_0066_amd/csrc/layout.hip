@@ -1,0 +1,144 @@
+// Conversions between the canonical interchange layout (lexicographic sites,
+// array-of-structures complex128) and the library's even-odd structure-of-arrays
+// layout. One work-item per site (and rhs); not on the hot path.
+#include "internal.h"
+
+namespace sap {
+
+struct Lex {
+  int x0, x1, x2, x3;
+};
+
+__device__ __forceinline__ Lex lex_coords(const Geo& g, long long i) {
+  Lex c;
+  c.x3 = (int)(i % g.L3); i /= g.L3;
+  c.x2 = (int)(i % g.L2); i /= g.L2;
+  c.x1 = (int)(i % g.L1);
+  c.x0 = (int)(i / g.L1);
+  return c;
+}
+
+template <class R>
+__global__ void pack_spinor_kernel(Geo g, typename vec2<R>::type* out, const double2* in, int nrhs) {
+  const long long V = 2 * g.Vh;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V * nrhs) return;
+  const long long rhs = t / V, i = t - rhs * V;
+  const Lex c = lex_coords(g, i);
+  const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
+  const long long j = i >> 1;
+  typename vec2<R>::type* o = out + (rhs * 2 + p) * 12 * g.Vh + j;
+  const double2* src = in + (rhs * V + i) * 12;
+  for (int k = 0; k < 12; ++k) {
+    double2 v = src[k];
+    typename vec2<R>::type w;
+    w.x = (R)v.x; w.y = (R)v.y;
+    o[k * g.Vh] = w;
+  }
+}
+
+template <class R>
+__global__ void unpack_spinor_kernel(Geo g, double2* out, const typename vec2<R>::type* in, int nrhs) {
+  const long long V = 2 * g.Vh;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V * nrhs) return;
+  const long long rhs = t / V, i = t - rhs * V;
+  const Lex c = lex_coords(g, i);
+  const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
+  const long long j = i >> 1;
+  const typename vec2<R>::type* src = in + (rhs * 2 + p) * 12 * g.Vh + j;
+  double2* o = out + (rhs * V + i) * 12;
+  for (int k = 0; k < 12; ++k) {
+    typename vec2<R>::type v = src[k * g.Vh];
+    o[k] = make_double2((double)v.x, (double)v.y);
+  }
+}
+
+__global__ void pack_gauge_kernel(Geo g, double2* U64, float2* U32, const double2* in) {
+  const long long V = 2 * g.Vh;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  const Lex c = lex_coords(g, i);
+  const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
+  const long long j = i >> 1;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int e = 0; e < 9; ++e) {
+      double2 v = in[(i * 4 + mu) * 9 + e];
+      long long k = ((long long)(mu * 2 + p) * 9 + e) * g.Vh + j;
+      U64[k] = v;
+      if (U32) U32[k] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void unpack_gauge_kernel(Geo g, double2* out, const double2* U64) {
+  const long long V = 2 * g.Vh;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  const Lex c = lex_coords(g, i);
+  const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
+  const long long j = i >> 1;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int e = 0; e < 9; ++e)
+      out[(i * 4 + mu) * 9 + e] = U64[((long long)(mu * 2 + p) * 9 + e) * g.Vh + j];
+}
+
+__global__ void gauge_to_f32_kernel(long long n, float2* U32, const double2* U64) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double2 v = U64[k];
+  U32[k] = make_float2((float)v.x, (float)v.y);
+}
+
+__global__ void pack_momenta_kernel(Geo g, double* out, const double* in, int to_sap) {
+  const long long V = 2 * g.Vh;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= V) return;
+  const Lex c = lex_coords(g, i);
+  const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
+  const long long j = i >> 1;
+  for (int mu = 0; mu < 4; ++mu)
+    for (int a = 0; a < 8; ++a) {
+      long long ks = ((long long)(mu * 2 + p) * 8 + a) * g.Vh + j;
+      long long kc = (i * 4 + mu) * 8 + a;
+      if (to_sap) out[ks] = in[kc];
+      else out[kc] = in[ks];
+    }
+}
+
+static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <class R>
+void launch_pack_spinor(const Geo& g, typename vec2<R>::type* out, const double2* in, int nrhs,
+                        hipStream_t s) {
+  long long n = 2 * g.Vh * nrhs;
+  hipLaunchKernelGGL(pack_spinor_kernel<R>, dim3(nblk(n, 256)), dim3(256), 0, s, g, out, in, nrhs);
+}
+template <class R>
+void launch_unpack_spinor(const Geo& g, double2* out, const typename vec2<R>::type* in, int nrhs,
+                          hipStream_t s) {
+  long long n = 2 * g.Vh * nrhs;
+  hipLaunchKernelGGL(unpack_spinor_kernel<R>, dim3(nblk(n, 256)), dim3(256), 0, s, g, out, in, nrhs);
+}
+template void launch_pack_spinor<double>(const Geo&, double2*, const double2*, int, hipStream_t);
+template void launch_pack_spinor<float>(const Geo&, float2*, const double2*, int, hipStream_t);
+template void launch_unpack_spinor<double>(const Geo&, double2*, const double2*, int, hipStream_t);
+template void launch_unpack_spinor<float>(const Geo&, double2*, const float2*, int, hipStream_t);
+
+void launch_pack_gauge(const Geo& g, double2* U64, float2* U32, const double2* in, hipStream_t s) {
+  hipLaunchKernelGGL(pack_gauge_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, U64, U32, in);
+}
+void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStream_t s) {
+  hipLaunchKernelGGL(unpack_gauge_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, U64);
+}
+void launch_gauge_to_f32(const Geo& g, float2* U32, const double2* U64, hipStream_t s) {
+  long long n = 4LL * 2 * 9 * g.Vh;
+  hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, U32, U64);
+}
+void launch_pack_momenta(const Geo& g, double* out, const double* in, hipStream_t s) {
+  hipLaunchKernelGGL(pack_momenta_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, in, 1);
+}
+void launch_unpack_momenta(const Geo& g, double* out, const double* in, hipStream_t s) {
+  hipLaunchKernelGGL(pack_momenta_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, in, 0);
+}
+
+}  // namespace sap

@@ -1,0 +1,113 @@
+"""GPU parity of apply_M and apply_W1_block (FP64 and FP32) against the FP64 oracle on
+the same seeded inputs, element by element, on lattices that span several workgroups and
+have ragged tails, on the 16^3x32 workload, and on the 24^3x48 workload."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, lattice
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # (L, l0, l0_sub, kappa)
+    ((4, 4, 4, 4), 2, 0, 0.155),
+    ((6, 2, 4, 6), 3, 0, 0.16),            # V/2 = 144: one partial workgroup
+    ((8, 6, 2, 10), 2, 0, 0.13),           # V/2 = 480: ragged tail
+    ((16, 4, 6, 4), 4, 2, 0.1575),         # level-2 blocks
+]
+F64_TOL = 1e-13
+F32_TOL = 2e-6
+
+
+@pytest.fixture(scope="module")
+def gu():
+    import gpu_util
+    return gpu_util
+
+
+@pytest.mark.parametrize("L,l0,l0_sub,k", SHAPES)
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_apply_M_matches_oracle(gu, L, l0, l0_sub, k, nrhs):
+    import paper_0710_0066_amd as sap
+    print(f"apply_M L={L} nrhs={nrhs}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1001)
+    psi = synth.gaussian_spinor(L, 2001, nrhs=nrhs)
+    ref = dirac.apply_M(U, psi, k)
+    ctx = gu.make_ctx(L, l0, k, U, l0_sub, max_rhs=nrhs)
+    for prec, tol in [(sap.SAP_F64, F64_TOL), (sap.SAP_F32, F32_TOL)]:
+        fin = gu.to_sap(ctx, psi, nrhs, prec)
+        fout = ctx.new_field(nrhs, prec)
+        sap.apply_M(ctx, fout, fin, nrhs, prec)
+        got = gu.from_sap(ctx, fout, nrhs, psi.shape, prec)
+        assert gu.rel_err(got, ref) <= tol, (prec, gu.rel_err(got, ref))
+
+
+@pytest.mark.parametrize("L,l0,l0_sub,k", SHAPES)
+def test_apply_W_matches_oracle(gu, L, l0, l0_sub, k):
+    import paper_0710_0066_amd as sap
+    print(f"apply_W1_block L={L}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1003)
+    psi = synth.gaussian_spinor(L, 2003, nrhs=2)
+    ctx = gu.make_ctx(L, l0, k, U, l0_sub, max_rhs=2)
+    levels = [(1, l0)] + ([(2, l0_sub)] if l0_sub else [])
+    for level, lb in levels:
+        ref_all = dirac.apply_W(U, psi, k, lb)
+        nb = L[0] // lb
+        cases = [(-1, sap.SAP_ALL, "all"), (-1, sap.SAP_BLACK, "black"), (-1, sap.SAP_WHITE, "white"),
+                 (nb - 1, sap.SAP_ALL, None), (0, sap.SAP_BLACK, None)]
+        for block, color, cname in cases:
+            if block >= 0:
+                m = lattice.single_block_mask(L, lb, block)
+            else:
+                m = lattice.colour_x0_mask(L, lb, cname)
+            ref = ref_all * lattice.site_mask(L, m)
+            for prec, tol in [(sap.SAP_F64, F64_TOL), (sap.SAP_F32, F32_TOL)]:
+                fin = gu.to_sap(ctx, psi, 2, prec)
+                fout = ctx.new_field(2, prec)
+                fout.fill_(7.0)        # every site must be written
+                sap.apply_W1_block(ctx, fout, fin, 2, level, block, color, prec)
+                got = gu.from_sap(ctx, fout, 2, psi.shape, prec)
+                err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref_all)))
+                assert err <= tol, (level, block, color, prec, err)
+
+
+@pytest.mark.parametrize("name", ["plain_16x16x16x32", "batched_24x24x24x48"])
+def test_apply_M_and_W_full_size(gu, name):
+    """Full-size workloads in the launch configuration the benchmark times: every
+    element compared with the oracle (FP64 <= 1e-13, FP32 error bounded)."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS[name]
+    L, k, l0 = cfg["L"], cfg["kappa"], cfg["l0"]
+    print(f"full size {name}", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    psi = synth.gaussian_spinor(L, cfg["seed_src"])
+    ctx = gu.make_ctx(L, l0, k, U, cfg["l0_sub"], max_rhs=1)
+    refM = dirac.apply_M(U, psi, k)
+    refW = dirac.apply_W(U, psi, k, l0)
+    for prec, tol in [(sap.SAP_F64, F64_TOL), (sap.SAP_F32, F32_TOL)]:
+        fin = gu.to_sap(ctx, psi, 1, prec)
+        fout = ctx.new_field(1, prec)
+        sap.apply_M(ctx, fout, fin, 1, prec)
+        assert gu.rel_err(gu.from_sap(ctx, fout, 1, psi.shape, prec), refM) <= tol
+        sap.apply_W1_block(ctx, fout, fin, 1, 1, -1, sap.SAP_ALL, prec)
+        assert gu.rel_err(gu.from_sap(ctx, fout, 1, psi.shape, prec), refW) <= tol
+
+
+def test_pack_unpack_roundtrip(gu):
+    import paper_0710_0066_amd as sap
+    L = (6, 2, 4, 6)
+    U = synth.gauge_field(L, 0.5, 5)
+    psi = synth.gaussian_spinor(L, 6, nrhs=2)
+    ctx = gu.make_ctx(L, 3, 0.1, U, max_rhs=2)
+    f = gu.to_sap(ctx, psi, 2)
+    assert np.array_equal(gu.from_sap(ctx, f, 2, psi.shape), psi)
+    import torch
+    Uo = torch.zeros(U.size, dtype=torch.complex128, device="cuda")
+    ctx.get_gauge(Uo)
+    assert np.array_equal(Uo.cpu().numpy().reshape(U.shape), U)
+    p = synth.gaussian_momenta(L, 7)
+    fp = ctx.new_momenta()
+    ctx.pack_momenta(fp, gu.dev(p))
+    back = ctx.new_momenta()
+    ctx.unpack_momenta(back, fp)
+    assert np.array_equal(back.cpu().numpy().reshape(p.shape), p)
