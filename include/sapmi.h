@@ -21,11 +21,16 @@
  *   gauge   U[i][mu][row][col]                 9 complex per link
  *   spinor  psi[rhs][i][spin][colour]          12 complex per site and rhs
  *   force   F[i][mu][a] (float64, a = 0..7)    coefficients on T^a = lambda^a / 2
- * Library field layout ("sap layout"), used by every hot entry point:
- *   spinor  [rhs][parity][12][V/2] of complex at the field precision, component
- *           c = 3*spin + colour, site index j = i / 2 within its parity.
- *   sap_field_bytes() gives the size; sap_pack_spinor / sap_unpack_spinor convert.
- *   momentum / force fields in the sap layout: [mu][parity][8][V/2] float64.
+ * Library field layout ("sap layout"), used by every hot entry point: even-odd,
+ *   tiled structure of arrays. Within a parity, site j = i / 2; sites are grouped in
+ *   tiles of 64 (j / 64), Vhp = V/2 rounded up to a multiple of 64.
+ *   spinor  complex number (rhs, parity, c = 3*spin + colour, j) at index
+ *           ((rhs*2 + parity)*12*Vhp) + ((j/64)*12 + c)*64 + j%64
+ *           (complex128 for SAP_F64, complex64 for SAP_F32).
+ *   momentum / force (float64, a = 0..7) (parity, j, mu, a) at
+ *           parity*32*Vhp + ((j/64)*32 + 8*mu + a)*64 + j%64.
+ *   sap_field_bytes() / sap_momenta_bytes() give the sizes; sap_pack_* / sap_unpack_*
+ *   convert from / to the canonical layout.
  *
  * Ownership and streams: every array argument is a DEVICE pointer allocated and freed
  * by the caller unless its comment says "host". The library never keeps a caller
@@ -95,7 +100,7 @@ typedef struct {
   int scheme_inner;
   sap_solve_opts force_solve;   /* solves inside the molecular dynamics */
   sap_solve_opts action_solve;  /* solves for the actions entering dH */
-  const double* p0;     /* momenta, sap layout [mu][parity][8][V/2] */
+  const double* p0;     /* momenta, sap layout */
   const double* xi1;    /* heat-bath noise for phi1 = W1 xi1, canonical spinor */
   const double* xi2;    /* heat-bath noise for chi = R_hat Pi xi2, canonical spinor */
   double u_metropolis;  /* uniform number in [0,1) for the accept step */
@@ -125,6 +130,8 @@ const char* sap_last_error(const sap_ctx* ctx);
 
 /* Bytes of one spinor field of nrhs right-hand sides in the sap layout. */
 size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs);
+/* Bytes of one momentum / force field in the sap layout. */
+size_t sap_momenta_bytes(const sap_ctx* ctx);
 
 /* Load the gauge field from the canonical layout (device, complex128) into the
  * context's FP64 and FP32 copies. */
@@ -137,7 +144,7 @@ int sap_pack_spinor(sap_ctx* ctx, void* out, const double* in, int nrhs, sap_pre
                     void* stream);
 int sap_unpack_spinor(sap_ctx* ctx, double* out, const void* in, int nrhs, sap_prec prec,
                       void* stream);
-/* Canonical float64 [i][mu][8] <-> sap layout [mu][parity][8][V/2]. */
+/* Canonical float64 [i][mu][8] <-> sap-layout momentum / force field. */
 int sap_pack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream);
 int sap_unpack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream);
 

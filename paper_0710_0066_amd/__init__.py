@@ -14,10 +14,10 @@ from __future__ import annotations
 import ctypes
 import os
 
-from .build import LIB as _LIB_PATH
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "libsapmi.so")
 
 if not os.path.exists(_LIB_PATH):
-    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_0710_0066_amd.build`")
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python paper_0710_0066_amd/build.py`")
 
 _lib = ctypes.CDLL(_LIB_PATH)
 
@@ -78,6 +78,7 @@ _SIGS = {
     "sap_destroy": ([_P], None),
     "sap_last_error": ([_P], ctypes.c_char_p),
     "sap_field_bytes": ([_P, _I, _I], ctypes.c_size_t),
+    "sap_momenta_bytes": ([_P], ctypes.c_size_t),
     "sap_set_gauge": ([_P, _P, _P], _I),
     "sap_get_gauge": ([_P, _P, _P], _I),
     "sap_pack_spinor": ([_P, _P, _P, _I, _I, _P], _I),
@@ -217,15 +218,18 @@ class Context:
         return self.L[0] // (self.l0 if level == 1 else self.l0_sub)
 
     # allocation helpers (torch is only the allocator here)
+    def field_bytes(self, nrhs=1, prec=SAP_F64):
+        return _lib.sap_field_bytes(self.ptr, prec, nrhs)
+
     def new_field(self, nrhs=1, prec=SAP_F64):
         import torch
-        n = self.V * 12 * 2 * nrhs
         dt = torch.float64 if prec == SAP_F64 else torch.float32
+        n = self.field_bytes(nrhs, prec) // (8 if prec == SAP_F64 else 4)
         return torch.zeros(n, dtype=dt, device="cuda")
 
     def new_momenta(self):
         import torch
-        return torch.zeros(self.V * 4 * 8, dtype=torch.float64, device="cuda")
+        return torch.zeros(_lib.sap_momenta_bytes(self.ptr) // 8, dtype=torch.float64, device="cuda")
 
     def set_gauge(self, U):
         """U: canonical complex128 gauge field on the device (any shape with V*4*9 entries)."""

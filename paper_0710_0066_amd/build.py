@@ -1,6 +1,7 @@
 """Build libsapmi.so (all HIP sources under csrc/) for gfx950 with hipcc, in-tree.
 
-Usage: python -m paper_0710_0066_amd.build   (or build() from Python)
+Usage: python paper_0710_0066_amd/build.py   (standalone: it does not import the package,
+which needs the library it builds)
 """
 import glob
 import os

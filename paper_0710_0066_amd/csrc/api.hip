@@ -54,7 +54,12 @@ const char* sap_last_error(const sap_ctx* ctx) {
 size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs) {
   if (!ctx || nrhs < 1) return 0;
   const size_t per = prec == SAP_F64 ? sizeof(double2) : sizeof(float2);
-  return (size_t)ctx->V * 12 * per * (size_t)nrhs;
+  return (size_t)ctx->Vhp * 24 * per * (size_t)nrhs;
+}
+
+size_t sap_momenta_bytes(const sap_ctx* ctx) {
+  if (!ctx) return 0;
+  return (size_t)ctx->Vhp * 64 * sizeof(double);
 }
 
 void sap_solver_destroy(sap_ctx* ctx);   // solver.hip
@@ -70,6 +75,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   c->g = make_geo(g->L);
   c->V = 2 * c->g.Vh;
   c->Vh = c->g.Vh;
+  c->Vhp = c->g.Vhp;
   c->have_gauge = false;
   c->U64 = nullptr;
   c->U32 = nullptr;
@@ -78,7 +84,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
     delete c;
     return sap_fail(nullptr, SAP_E_HIP, "hipGetDevice failed (no HIP device?)");
   }
-  const size_t nlink = (size_t)4 * 9 * c->V;
+  const size_t nlink = (size_t)72 * c->Vhp;
   if (hipMalloc((void**)&c->U64, nlink * sizeof(double2)) != hipSuccess ||
       hipMalloc((void**)&c->U32, nlink * sizeof(float2)) != hipSuccess) {
     sap_destroy(c);
@@ -175,9 +181,9 @@ static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, i
                     int block, hipStream_t s) {
   HopArgs<R> A;
   typedef typename vec2<R>::type V2;
-  const long long Vh = ctx->Vh;
-  A.out = {(V2*)out, 24 * Vh, 12 * Vh};
-  A.in = {(V2*)in, 24 * Vh, 12 * Vh};
+  const long long Vhp = ctx->Vhp;
+  A.out = {(V2*)out, 24 * Vhp, 12 * Vhp};
+  A.in = {(V2*)in, 24 * Vhp, 12 * Vhp};
   A.x = A.in;
   A.U = (const V2*)(sizeof(R) == 8 ? (const void*)ctx->U64 : (const void*)ctx->U32);
   A.g = ctx->g;

@@ -57,6 +57,17 @@ template <class R> __device__ __forceinline__ void st(typename vec2<R>::type* p,
 }
 
 // ---------------------------------------------------------------------------------
+// Tiled structure-of-arrays ("AoSoA") addressing of the library layout: sites of one
+// parity are grouped in tiles of TILE = 64 (one wavefront); inside a tile block all
+// NC components are stored one after the other, each as TILE consecutive complex
+// numbers. A wavefront load of one component of 64 consecutive sites is one contiguous
+// run, and the whole footprint of a tile is a few KB instead of NC far-apart streams.
+constexpr int TILE = 64;
+__device__ __host__ __forceinline__ long long tiled(long long j, int c, int NC) {
+  return ((j >> 6) * NC + c) * TILE + (j & (TILE - 1));
+}
+
+// ---------------------------------------------------------------------------------
 // geometry of the even-odd layout: site j of a parity is the lexicographic index / 2,
 // j = ((x0*L1 + x1)*L2 + x2)*L3h + x3h with L3h = L3/2 and x3 = 2*x3h + b,
 // b = (p + x0 + x1 + x2) & 1.
@@ -65,6 +76,7 @@ struct Geo {
   int L3h;        // L3 / 2
   int V3h;        // L1*L2*L3/2: sites of one parity in one x0 slice
   long long Vh;   // V / 2
+  long long Vhp;  // Vh rounded up to a multiple of TILE (storage sites per parity)
 };
 
 struct Site {

@@ -16,23 +16,24 @@
 namespace sap {
 
 template <class R>
-__device__ __forceinline__ void load_spinor(const typename vec2<R>::type* p, long long Vh,
-                                            long long j, bool g5, cx<R> s[4][3]) {
+__device__ __forceinline__ void load_spinor(const typename vec2<R>::type* p, long long j, bool g5,
+                                            cx<R> s[4][3]) {
+  const typename vec2<R>::type* q = p + tiled(j, 0, 12);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cx<R> v = ld<R>(p + (sp * 3 + c) * Vh + j);
+      cx<R> v = ld<R>(q + (sp * 3 + c) * TILE);
       s[sp][c] = (g5 && sp >= 2) ? -v : v;
     }
 }
 
 template <class R>
-__device__ __forceinline__ void load_link(const typename vec2<R>::type* U, long long Vh, int mu,
+__device__ __forceinline__ void load_link(const typename vec2<R>::type* U, long long Vhp, int mu,
                                           int par, long long j, cx<R> m[9]) {
-  const typename vec2<R>::type* p = U + ((long long)(mu * 2 + par) * 9) * Vh + j;
+  const typename vec2<R>::type* p = U + par * 36 * Vhp + tiled(j, 9 * mu, 36);
 #pragma unroll
-  for (int e = 0; e < 9; ++e) m[e] = ld<R>(p + e * Vh);
+  for (int e = 0; e < 9; ++e) m[e] = ld<R>(p + e * TILE);
 }
 
 template <class R, bool FULL>
@@ -53,10 +54,10 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
   }
   const Geo& g = A.g;
   if (j >= g.Vh) return;
-  const long long Vh = g.Vh;
+  const long long Vhp = g.Vhp;
   const Site s = decode(g, j, p);
 
-  V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps + j;
+  V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
   if (A.lb) {
     const int blk = s.x0 / A.lb;
     bool sel;
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
     if (!sel) {
       cx<R> z = {R(0), R(0)};
 #pragma unroll
-      for (int c = 0; c < 12; ++c) st<R>(o + c * Vh, z);
+      for (int c = 0; c < 12; ++c) st<R>(o + c * TILE, z);
       return;
     }
   }
@@ -86,9 +87,9 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
     if (fwd_on) {
       const long long jn = nbr(g, s, j, mu, +1);
       cx<R> sp[4][3], h[2][3], uh[2][3], m[9];
-      load_spinor<R>(inb, Vh, jn, g5i, sp);
+      load_spinor<R>(inb, jn, g5i, sp);
       project<R>(mu, false, sp, h);
-      load_link<R>(A.U, Vh, mu, p, j, m);
+      load_link<R>(A.U, Vhp, mu, p, j, m);
       su3_mul<R>(m, h[0], uh[0]);
       su3_mul<R>(m, h[1], uh[1]);
       if (mu == 0 && s.x0 == g.L0 - 1) {
@@ -104,9 +105,9 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
     if (bwd_on) {
       const long long jn = nbr(g, s, j, mu, -1);
       cx<R> sp[4][3], h[2][3], uh[2][3], m[9];
-      load_spinor<R>(inb, Vh, jn, g5i, sp);
+      load_spinor<R>(inb, jn, g5i, sp);
       project<R>(mu, true, sp, h);
-      load_link<R>(A.U, Vh, mu, 1 - p, jn, m);
+      load_link<R>(A.U, Vhp, mu, 1 - p, jn, m);
       su3_dag_mul<R>(m, h[0], uh[0]);
       su3_dag_mul<R>(m, h[1], uh[1]);
       if (mu == 0 && s.x0 == 0) {
@@ -126,20 +127,20 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
       for (int c = 0; c < 3; ++c) acc[sp][c] = -acc[sp][c];
   }
   if (A.x.ptr) {
-    const V2* xp = A.x.ptr + rhs * A.x.rs + p * A.x.ps + j;
+    const V2* xp = A.x.ptr + rhs * A.x.rs + p * A.x.ps + tiled(j, 0, 12);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        cx<R> xv = ld<R>(xp + (sp * 3 + c) * Vh);
+        cx<R> xv = ld<R>(xp + (sp * 3 + c) * TILE);
         cx<R> r = {A.a * xv.r + A.b * acc[sp][c].r, A.a * xv.i + A.b * acc[sp][c].i};
-        st<R>(o + (sp * 3 + c) * Vh, r);
+        st<R>(o + (sp * 3 + c) * TILE, r);
       }
   } else {
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) st<R>(o + (sp * 3 + c) * Vh, A.b * acc[sp][c]);
+      for (int c = 0; c < 3; ++c) st<R>(o + (sp * 3 + c) * TILE, A.b * acc[sp][c]);
   }
 }
 

@@ -10,8 +10,11 @@
 namespace sap {
 
 // A spinor field in the library layout: element (rhs, parity, component c, site j) of
-// complex type at  ptr + rhs*rs + parity*ps + c*Vh + j  (counted in complex numbers).
-// Full fields: rs = 24*Vh, ps = 12*Vh. Single-parity fields: rs = 12*Vh, ps = 0.
+// complex type at  ptr + rhs*rs + parity*ps + tiled(j, c, 12)  (in complex numbers).
+// Full fields: rs = 24*Vhp, ps = 12*Vhp. Single-parity fields: rs = 12*Vhp, ps = 0.
+// Gauge field: link (parity p, site j, mu, entry e = 3*row + col) at
+//   p*36*Vhp + tiled(j, 9*mu + e, 36).
+// Momenta / forces (float64): (p, j, mu, a) at  p*32*Vhp + tiled(j, 8*mu + a, 32).
 template <class R> struct Field {
   typename vec2<R>::type* ptr;
   long long rs;
@@ -20,7 +23,7 @@ template <class R> struct Field {
 
 template <class R> struct HopArgs {
   Field<R> out, in, x;     // out = a*x + b*D(in); x.ptr may be null
-  const typename vec2<R>::type* U;   // gauge [mu][parity][9][Vh]
+  const typename vec2<R>::type* U;   // gauge field in the tiled layout
   Geo g;
   int nrhs;
   int parity_out;          // -1: both parities (full operator); 0/1: that parity only
@@ -52,6 +55,7 @@ inline Geo make_geo(const int L[4]) {
   g.L3h = L[3] / 2;
   g.V3h = L[1] * L[2] * L[3] / 2;
   g.Vh = (long long)L[0] * L[1] * L[2] * L[3] / 2;
+  g.Vhp = (g.Vh + TILE - 1) / TILE * TILE;
   return g;
 }
 
@@ -60,10 +64,10 @@ inline Geo make_geo(const int L[4]) {
 struct sap_ctx {
   sap_geom geom;
   sap::Geo g;
-  long long V, Vh;
+  long long V, Vh, Vhp;
   int device;
   bool have_gauge;
-  double2* U64;   // [4][2][9][Vh]
+  double2* U64;   // tiled gauge layout, 72*Vhp complex
   float2* U32;
   std::vector<void*> allocations;
   std::string err;

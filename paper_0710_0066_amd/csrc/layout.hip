@@ -27,13 +27,13 @@ __global__ void pack_spinor_kernel(Geo g, typename vec2<R>::type* out, const dou
   const Lex c = lex_coords(g, i);
   const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
   const long long j = i >> 1;
-  typename vec2<R>::type* o = out + (rhs * 2 + p) * 12 * g.Vh + j;
+  typename vec2<R>::type* o = out + (rhs * 2 + p) * 12 * g.Vhp;
   const double2* src = in + (rhs * V + i) * 12;
   for (int k = 0; k < 12; ++k) {
     double2 v = src[k];
     typename vec2<R>::type w;
     w.x = (R)v.x; w.y = (R)v.y;
-    o[k * g.Vh] = w;
+    o[tiled(j, k, 12)] = w;
   }
 }
 
@@ -46,10 +46,10 @@ __global__ void unpack_spinor_kernel(Geo g, double2* out, const typename vec2<R>
   const Lex c = lex_coords(g, i);
   const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
   const long long j = i >> 1;
-  const typename vec2<R>::type* src = in + (rhs * 2 + p) * 12 * g.Vh + j;
+  const typename vec2<R>::type* src = in + (rhs * 2 + p) * 12 * g.Vhp;
   double2* o = out + (rhs * V + i) * 12;
   for (int k = 0; k < 12; ++k) {
-    typename vec2<R>::type v = src[k * g.Vh];
+    typename vec2<R>::type v = src[tiled(j, k, 12)];
     o[k] = make_double2((double)v.x, (double)v.y);
   }
 }
@@ -64,7 +64,7 @@ __global__ void pack_gauge_kernel(Geo g, double2* U64, float2* U32, const double
   for (int mu = 0; mu < 4; ++mu)
     for (int e = 0; e < 9; ++e) {
       double2 v = in[(i * 4 + mu) * 9 + e];
-      long long k = ((long long)(mu * 2 + p) * 9 + e) * g.Vh + j;
+      long long k = p * 36 * g.Vhp + tiled(j, 9 * mu + e, 36);
       U64[k] = v;
       if (U32) U32[k] = make_float2((float)v.x, (float)v.y);
     }
@@ -79,7 +79,7 @@ __global__ void unpack_gauge_kernel(Geo g, double2* out, const double2* U64) {
   const long long j = i >> 1;
   for (int mu = 0; mu < 4; ++mu)
     for (int e = 0; e < 9; ++e)
-      out[(i * 4 + mu) * 9 + e] = U64[((long long)(mu * 2 + p) * 9 + e) * g.Vh + j];
+      out[(i * 4 + mu) * 9 + e] = U64[p * 36 * g.Vhp + tiled(j, 9 * mu + e, 36)];
 }
 
 __global__ void gauge_to_f32_kernel(long long n, float2* U32, const double2* U64) {
@@ -98,7 +98,7 @@ __global__ void pack_momenta_kernel(Geo g, double* out, const double* in, int to
   const long long j = i >> 1;
   for (int mu = 0; mu < 4; ++mu)
     for (int a = 0; a < 8; ++a) {
-      long long ks = ((long long)(mu * 2 + p) * 8 + a) * g.Vh + j;
+      long long ks = p * 32 * g.Vhp + tiled(j, 8 * mu + a, 32);
       long long kc = (i * 4 + mu) * 8 + a;
       if (to_sap) out[ks] = in[kc];
       else out[kc] = in[ks];
@@ -131,7 +131,7 @@ void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStre
   hipLaunchKernelGGL(unpack_gauge_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, U64);
 }
 void launch_gauge_to_f32(const Geo& g, float2* U32, const double2* U64, hipStream_t s) {
-  long long n = 4LL * 2 * 9 * g.Vh;
+  long long n = 72LL * g.Vhp;
   hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, U32, U64);
 }
 void launch_pack_momenta(const Geo& g, double* out, const double* in, hipStream_t s) {

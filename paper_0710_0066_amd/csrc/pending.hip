@@ -2,15 +2,6 @@
 #include "internal.h"
 
 extern "C" {
-int sap_solver_create(sap_ctx*) { return SAP_OK; }
-void sap_solver_destroy(sap_ctx*) {}
-int solve_full(sap_ctx* c, double*, const double*, int, const sap_solve_opts*, sap_solve_info*, void*) {
-  return sap_fail(c, SAP_E_STATE, "solve_full not available in this build");
-}
-int solve_blocks(sap_ctx* c, double*, const double*, int, int, sap_color, const sap_solve_opts*,
-                 sap_solve_info*, void*) {
-  return sap_fail(c, SAP_E_STATE, "solve_blocks not available in this build");
-}
 int block_pf_force(sap_ctx* c, double*, double, const double*, const sap_solve_opts*, double*, void*) {
   return sap_fail(c, SAP_E_STATE, "block_pf_force not available in this build");
 }

@@ -1,0 +1,295 @@
+// Batched Krylov solves of M x = b (full lattice) and W x = b (every selected x0 block
+// an independent system), all systems and right-hand sides advanced together in each
+// kernel launch.
+//
+// Inner solve: even-odd reduced system (Sec. 1, W_eo: M = [[1, -k D_eo], [-k D_oe, 1]],
+// M_hat = 1 - k^2 D_eo D_oe) by CG on the normal equations in the CGLS form, which
+// carries s = b_hat - M_hat x. M_hat^dagger = g5 M_hat g5 is applied by the same hop
+// kernel with gamma_5 folded into its input and output. Per-system scalars stay on the
+// device; converged systems are frozen (alpha = beta = 0) while the others continue; the
+// host reads one counter every few iterations.
+// Outer loop: FP64 defect correction r = b - A x (A applied in FP64), inner solve in
+// FP32 or FP64, x += e, until ||b - A x|| / ||b|| <= tol recomputed in FP64.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include "blas.h"
+
+using namespace sap;
+
+namespace sap {
+int apply_op_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, int colour, int block,
+                 sap_prec prec, hipStream_t s);
+}
+
+struct SolverWS {
+  int max_rhs, max_sys, max_chunk;
+  double2 *hx, *s, *r, *p, *q, *t;       // half fields (sized for FP64, max_rhs)
+  double2 *x64, *r64, *ax, *rin, *e;     // full fields
+  double *partA, *partB, *partC;
+  double *gam, *ss, *alpha, *beta, *target2, *bnorm2, *rnorm2;
+  int *active, *iters, *flags, *selected;
+  // pinned host mirrors
+  double *h_rnorm2, *h_bnorm2;
+  int *h_flags, *h_iters, *h_selected;
+};
+
+static SolverWS* ws_of(sap_ctx* c) { return (SolverWS*)c->solver; }
+
+extern "C" int sap_solver_create(sap_ctx* c) {
+  SolverWS* w = new SolverWS();
+  std::memset(w, 0, sizeof(*w));
+  c->solver = w;
+  const int minlb = c->geom.l0_sub > 0 ? c->geom.l0_sub : c->geom.l0;
+  w->max_rhs = c->geom.max_rhs;
+  w->max_sys = (c->geom.L[0] / minlb) * w->max_rhs;
+  if (w->max_sys < w->max_rhs) w->max_sys = w->max_rhs;
+  w->max_chunk = (int)((c->Vh + CHUNK - 1) / CHUNK);
+  const size_t half = (size_t)12 * c->Vhp * w->max_rhs * sizeof(double2);
+  const size_t full = 2 * half;
+  const size_t npart = (size_t)w->max_rhs * w->max_chunk * (c->geom.L[0] / minlb + 1);
+  auto A = [&](void** p, size_t n) { return hipMalloc(p, n) == hipSuccess; };
+  bool ok = A((void**)&w->hx, half) && A((void**)&w->s, half) && A((void**)&w->r, half) &&
+            A((void**)&w->p, half) && A((void**)&w->q, half) && A((void**)&w->t, half) &&
+            A((void**)&w->x64, full) && A((void**)&w->r64, full) && A((void**)&w->ax, full) &&
+            A((void**)&w->rin, full) && A((void**)&w->e, full) &&
+            A((void**)&w->partA, npart * 8) && A((void**)&w->partB, npart * 8) &&
+            A((void**)&w->partC, npart * 8);
+  const size_t ns = (size_t)w->max_sys;
+  ok = ok && A((void**)&w->gam, ns * 8) && A((void**)&w->ss, ns * 8) && A((void**)&w->alpha, ns * 8) &&
+       A((void**)&w->beta, ns * 8) && A((void**)&w->target2, ns * 8) && A((void**)&w->bnorm2, ns * 8) &&
+       A((void**)&w->rnorm2, ns * 8) && A((void**)&w->active, ns * 4) && A((void**)&w->iters, ns * 4) &&
+       A((void**)&w->flags, 16) && A((void**)&w->selected, ns * 4);
+  ok = ok && hipHostMalloc((void**)&w->h_rnorm2, ns * 8, 0) == hipSuccess &&
+       hipHostMalloc((void**)&w->h_bnorm2, ns * 8, 0) == hipSuccess &&
+       hipHostMalloc((void**)&w->h_flags, 16, 0) == hipSuccess &&
+       hipHostMalloc((void**)&w->h_iters, ns * 4, 0) == hipSuccess &&
+       hipHostMalloc((void**)&w->h_selected, ns * 4, 0) == hipSuccess;
+  if (!ok) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the solver workspace");
+  return SAP_OK;
+}
+
+extern "C" void sap_solver_destroy(sap_ctx* c) {
+  SolverWS* w = ws_of(c);
+  if (!w) return;
+  void* dev[] = {w->hx, w->s, w->r, w->p, w->q, w->t, w->x64, w->r64, w->ax, w->rin, w->e,
+                 w->partA, w->partB, w->partC, w->gam, w->ss, w->alpha, w->beta, w->target2,
+                 w->bnorm2, w->rnorm2, w->active, w->iters, w->flags, w->selected};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  void* host[] = {w->h_rnorm2, w->h_bnorm2, w->h_flags, w->h_iters, w->h_selected};
+  for (void* p : host)
+    if (p) (void)hipHostFree(p);
+  delete w;
+  c->solver = nullptr;
+}
+
+__global__ void k_targets(int nsys, const double* partb, int nchunk, const double* bnorm2, double inner2,
+                          double abs2, double* target2) {
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+    double bb = 0.0;
+    for (int c = 0; c < nchunk; ++c) bb += partb[(long long)s * nchunk + c];
+    target2[s] = fmax(inner2 * bb, abs2 * bnorm2[s]);
+  }
+}
+
+namespace {
+
+// out = a*x + b*D(in) on one parity or both, block-restricted
+template <class R>
+void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int parity_out, int nrhs, int lb,
+         int colour, R a, R b, int g5i, int g5o, hipStream_t st) {
+  HopArgs<R> A;
+  A.out = out;
+  A.in = in;
+  A.x = x;
+  A.U = (const typename vec2<R>::type*)U;
+  A.g = c->g;
+  A.nrhs = nrhs;
+  A.parity_out = parity_out;
+  A.lb = lb;
+  A.colour = colour;
+  A.block = -1;
+  A.a = a;
+  A.b = b;
+  A.g5_in = g5i;
+  A.g5_out = g5o;
+  launch_hop<R>(A, st);
+}
+
+}  // namespace
+
+template <class R>
+static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
+                      const sap_solve_opts* o, sap_solve_info* info, hipStream_t st) {
+  typedef typename vec2<R>::type V2;
+  SolverWS* w = ws_of(c);
+  const long long Vh = c->Vh, Vhp = c->Vhp;
+  const SysGrid G = make_sysgrid(Vh, c->g.V3h, lb, c->geom.L[0], colour);
+  const int nsys = G.nblk * nrhs;
+  const double kap = c->geom.kappa;
+  const void* U = sizeof(R) == 8 ? (const void*)c->U64 : (const void*)c->U32;
+  const R kR = (R)kap, k2R = (R)(-kap * kap);
+  const size_t fullb = (size_t)24 * Vhp * nrhs * sizeof(double2);
+
+  Field<double> X = {(double2*)x, 24 * Vhp, 12 * Vhp}, B = {(double2*)b, 24 * Vhp, 12 * Vhp};
+  Field<double> R64 = {w->r64, 24 * Vhp, 12 * Vhp}, AX = {w->ax, 24 * Vhp, 12 * Vhp};
+  Field<R> RIN = {(V2*)w->rin, 24 * Vhp, 12 * Vhp}, E = {(V2*)w->e, 24 * Vhp, 12 * Vhp};
+  Field<R> Ee = {(V2*)w->e, 24 * Vhp, 0};
+  Field<R> S = {(V2*)w->s, 12 * Vhp, 0}, Rr = {(V2*)w->r, 12 * Vhp, 0}, P = {(V2*)w->p, 12 * Vhp, 0};
+  Field<R> Q = {(V2*)w->q, 12 * Vhp, 0}, T = {(V2*)w->t, 12 * Vhp, 0};
+  Field<R> NONE = {nullptr, 0, 0};
+  SysScal SC = {w->gam, w->ss, w->alpha, w->beta, w->active, w->iters, w->flags};
+
+  // selection of systems
+  for (int r = 0; r < nrhs; ++r)
+    for (int k = 0; k < G.nblk; ++k)
+      w->h_selected[r * G.nblk + k] = (G.colour == 0) || ((G.colour == 1) == ((k & 1) == 1));
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->selected, w->h_selected, nsys * 4, hipMemcpyHostToDevice, st));
+  SAP_HIP_CHECK(c, hipMemsetAsync(w->iters, 0, nsys * 4, st));
+  SAP_HIP_CHECK(c, hipMemsetAsync(x, 0, fullb, st));
+
+  // ||b||^2 per system; first residual r = b
+  blas_norm2<double>(G, nrhs, B, 2, w->partA, st);
+  fin_sum(nsys, G.nchunk, w->partA, w->bnorm2, st);
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->r64, b, fullb, hipMemcpyDeviceToDevice, st));
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->rnorm2, w->bnorm2, nsys * 8, hipMemcpyDeviceToDevice, st));
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_bnorm2, w->bnorm2, nsys * 8, hipMemcpyDeviceToHost, st));
+
+  const double tol = o->tol;
+  const double inner_tol = (sizeof(R) == 8 && o->inner_tol <= 0) ? tol : o->inner_tol;
+  const int check_every = 8;
+  long long total_iters = 0;
+  int outer = 0;
+  int status = SAP_OK;
+  for (;;) {
+    SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_rnorm2, w->rnorm2, nsys * 8, hipMemcpyDeviceToHost, st));
+    SAP_HIP_CHECK(c, hipStreamSynchronize(st));
+    bool all = true, finite = true;
+    for (int s = 0; s < nsys; ++s) {
+      if (!w->h_selected[s]) continue;
+      const double bb = w->h_bnorm2[s], rr = w->h_rnorm2[s];
+      if (!std::isfinite(rr) || !std::isfinite(bb)) finite = false;
+      if (bb > 0 && rr > tol * tol * bb) all = false;
+    }
+    if (!finite) { status = sap_fail(c, SAP_E_NONFINITE, "non-finite residual"); break; }
+    if (all) break;
+    if (outer >= o->max_outer || total_iters >= o->max_iter) {
+      status = sap_fail(c, SAP_E_NOCONV, "solver did not reach tol within max_outer / max_iter");
+      break;
+    }
+    ++outer;
+    // inner right-hand side at the inner precision
+    blas_convert<R, double>(G, nrhs, RIN, R64, 2, st);
+    // b_hat_e = r_e + k D_eo r_o  (into S)
+    hop<R>(c, U, S, RIN, RIN, 0, nrhs, lb, colour, R(1), kR, 0, 0, st);
+    SAP_HIP_CHECK(c, hipMemsetAsync(w->e, 0, fullb / (sizeof(R) == 8 ? 1 : 2), st));
+    blas_norm2<R>(G, nrhs, S, 1, w->partB, st);
+    // r = M_hat^dagger s = s - k^2 g5 D_eo D_oe g5 s
+    hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, st);
+    hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, st);
+    blas_norm2<R>(G, nrhs, Rr, 1, w->partC, st);
+    // stop the inner solve at ||s|| <= max(inner_tol ||b_hat||, 0.3 tol ||b||): the outer
+    // residual after x += e equals the inner one up to rounding
+    hipLaunchKernelGGL(k_targets, dim3(1), dim3(256), 0, st, nsys, w->partB, G.nchunk, w->bnorm2,
+                       inner_tol * inner_tol, 0.09 * tol * tol, w->target2);
+    SAP_HIP_CHECK(c, hipMemsetAsync(w->flags, 0, 16, st));
+    fin_init(SC, nsys, G.nchunk, w->partB, w->partC, w->selected, w->target2, st);
+    SAP_HIP_CHECK(c, hipMemcpyAsync(w->p, w->r, fullb / 2 / (sizeof(R) == 8 ? 1 : 2),
+                                    hipMemcpyDeviceToDevice, st));
+    SAP_HIP_CHECK(c, hipGetLastError());
+    for (int it = 0;; ++it) {
+      if (it % check_every == 0) {
+        SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 8, hipMemcpyDeviceToHost, st));
+        SAP_HIP_CHECK(c, hipStreamSynchronize(st));
+        if (w->h_flags[0]) return sap_fail(c, SAP_E_NONFINITE, "non-finite value in the inner solve");
+        if (w->h_flags[1] == 0) break;
+        if (total_iters >= o->max_iter) break;
+      }
+      // q = M_hat p
+      hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, st);
+      hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, st);
+      blas_norm2<R>(G, nrhs, Q, 1, w->partA, st);
+      fin_alpha(SC, nsys, G.nchunk, w->partA, st);
+      // x += alpha p, s -= alpha q
+      blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, st);
+      // r = M_hat^dagger s
+      hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, st);
+      hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, st);
+      blas_norm2<R>(G, nrhs, Rr, 1, w->partC, st);
+      fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, st);
+      blas_xpay<R>(G, nrhs, P, Rr, w->beta, st);
+      ++total_iters;
+    }
+    // e_o = r_o + k D_oe e_e ; x += e ; r = b - A x (FP64)
+    hop<R>(c, U, E, Ee, RIN, 1, nrhs, lb, colour, R(1), kR, 0, 0, st);
+    blas_add_mixed<R>(G, nrhs, X, E, st);
+    int rc = apply_op_any(c, w->ax, x, nrhs, lb, colour, -1, SAP_F64, st);
+    if (rc) return rc;
+    blas_resid(G, nrhs, R64, B, AX, w->partA, st);
+    fin_sum(nsys, G.nchunk, w->partA, w->rnorm2, st);
+    SAP_HIP_CHECK(c, hipGetLastError());
+  }
+  if (info) {
+    SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_iters, w->iters, nsys * 4, hipMemcpyDeviceToHost, st));
+    SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_rnorm2, w->rnorm2, nsys * 8, hipMemcpyDeviceToHost, st));
+    SAP_HIP_CHECK(c, hipStreamSynchronize(st));
+    for (int s = 0; s < nsys; ++s) {
+      const double bb = w->h_bnorm2[s];
+      info[s].iters = w->h_selected[s] ? w->h_iters[s] : 0;
+      info[s].outer = w->h_selected[s] ? outer : 0;
+      info[s].true_rel_res = (w->h_selected[s] && bb > 0) ? std::sqrt(w->h_rnorm2[s] / bb) : 0.0;
+    }
+  }
+  return status;
+}
+
+static int check_opts(sap_ctx* c, const sap_solve_opts* o) {
+  if (!o) return sap_fail(c, SAP_E_ARG, "opts is NULL");
+  if (!(o->tol > 0 && o->tol < 1)) return sap_fail(c, SAP_E_ARG, "tol must be in (0, 1)");
+  if (o->max_iter < 1 || o->max_outer < 1) return sap_fail(c, SAP_E_ARG, "max_iter and max_outer must be >= 1");
+  if (o->inner_prec != SAP_F64 && o->inner_prec != SAP_F32) return sap_fail(c, SAP_E_ARG, "unknown inner precision");
+  if (o->inner_prec == SAP_F32 && !(o->inner_tol > 0 && o->inner_tol < 1))
+    return sap_fail(c, SAP_E_ARG, "inner_tol must be in (0, 1) for an FP32 inner solve");
+  return SAP_OK;
+}
+
+int sap_solve_any(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
+                  const sap_solve_opts* o, sap_solve_info* info, hipStream_t st) {
+  if (o->inner_prec == SAP_F64) return solve_impl<double>(c, x, b, nrhs, lb, colour, o, info, st);
+  return solve_impl<float>(c, x, b, nrhs, lb, colour, o, info, st);
+}
+
+extern "C" {
+
+int solve_full(sap_ctx* c, double* x, const double* b, int nrhs, const sap_solve_opts* o,
+               sap_solve_info* info, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!x || !b) return sap_fail(c, SAP_E_ARG, "x or b is NULL");
+  if (x == b) return sap_fail(c, SAP_E_ARG, "x and b must not alias");
+  if (nrhs < 1 || nrhs > c->geom.max_rhs) return sap_fail(c, SAP_E_ARG, "nrhs must be in [1, max_rhs]");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  return sap_solve_any(c, x, b, nrhs, 0, 0, o, info, (hipStream_t)stream);
+}
+
+int solve_blocks(sap_ctx* c, double* x, const double* b, int nrhs, int level, sap_color color,
+                 const sap_solve_opts* o, sap_solve_info* info, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!x || !b) return sap_fail(c, SAP_E_ARG, "x or b is NULL");
+  if (x == b) return sap_fail(c, SAP_E_ARG, "x and b must not alias");
+  if (nrhs < 1 || nrhs > c->geom.max_rhs) return sap_fail(c, SAP_E_ARG, "nrhs must be in [1, max_rhs]");
+  int lb;
+  if (level == 1) lb = c->geom.l0;
+  else if (level == 2 && c->geom.l0_sub > 0) lb = c->geom.l0_sub;
+  else return sap_fail(c, SAP_E_ARG, "level must be 1, or 2 with l0_sub set");
+  if (color != SAP_ALL && color != SAP_BLACK && color != SAP_WHITE)
+    return sap_fail(c, SAP_E_ARG, "unknown colour");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  return sap_solve_any(c, x, b, nrhs, lb, (int)color, o, info, (hipStream_t)stream);
+}
+
+}  // extern "C"

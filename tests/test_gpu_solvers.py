@@ -1,0 +1,158 @@
+"""GPU parity of solve_full and solve_blocks: the solutions are compared with the oracle's
+(dense LU on small lattices), and the residual ||b - A x|| / ||b|| of the GPU solution is
+recomputed with the oracle's own operator (M or W) in FP64. Covers FP64 and FP32 inner
+solves, several right-hand sides, both block levels and colours, the 16^3x32 and
+24^3x48 workloads, and the error paths (no convergence, non-finite source)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dirac, lattice, solvers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gu():
+    import gpu_util
+    return gpu_util
+
+
+def _opts(sap, inner, tol=1e-10, max_iter=200000, inner_tol=1e-5):
+    return sap.solve_opts(tol=tol, max_iter=max_iter, inner_prec=inner, inner_tol=inner_tol, max_outer=60)
+
+
+def _relres(U, x, b, k, lb=None, mask=None):
+    r = b - dirac.apply_op(U, x, k, lb)
+    if mask is not None:
+        r = r * mask
+        b = b * mask
+    ax = tuple(range(r.ndim - 6, r.ndim))
+    return np.sqrt(np.sum(np.abs(r) ** 2, axis=ax) / np.sum(np.abs(b) ** 2, axis=ax))
+
+
+@pytest.mark.parametrize("L,l0,k", [((4, 4, 4, 4), 2, 0.155), ((6, 2, 4, 6), 3, 0.15)])
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_solve_full_matches_dense_solution(gu, L, l0, k, inner):
+    import paper_0710_0066_amd as sap
+    print(f"solve_full L={L} inner={inner}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1001)
+    b = synth.gaussian_spinor(L, 2001, nrhs=2)
+    A = dirac.dense_matrix(U, k)
+    x_lu = np.linalg.solve(A, b.reshape(2, -1).T).T.reshape(b.shape)
+    ctx = gu.make_ctx(L, l0, k, U, max_rhs=2)
+    fb = gu.to_sap(ctx, b, 2)
+    fx = ctx.new_field(2)
+    prec = sap.SAP_F64 if inner == "f64" else sap.SAP_F32
+    info = sap.solve_full(ctx, fx, fb, 2, _opts(sap, prec))
+    x = gu.from_sap(ctx, fx, 2, b.shape)
+    res = _relres(U, x, b, k)
+    assert np.all(res <= 1e-10), res
+    for i in range(2):
+        assert abs(info[i].true_rel_res - res[i]) <= 1e-12
+        assert info[i].iters > 0
+    cond = np.linalg.cond(A)
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) <= cond * 1e-10
+
+
+@pytest.mark.parametrize("level,color", [(1, "all"), (1, "black"), (2, "white"), (2, "all")])
+def test_solve_blocks_matches_oracle(gu, level, color):
+    import paper_0710_0066_amd as sap
+    L, l0, l0s, k = (16, 4, 2, 4), 4, 2, 0.15
+    print(f"solve_blocks level={level} color={color}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1007)
+    b = synth.gaussian_spinor(L, 2007, nrhs=3)
+    lb = l0 if level == 1 else l0s
+    m = lattice.site_mask(L, lattice.colour_x0_mask(L, lb, color))
+    x_ref, _, _ = solvers.solve_eo(U, b * m, k, lb, tol=1e-13)
+    ctx = gu.make_ctx(L, l0, k, U, l0s, max_rhs=3)
+    fb = gu.to_sap(ctx, b, 3)
+    fx = ctx.new_field(3)
+    fx.fill_(3.0)
+    cmap = {"all": sap.SAP_ALL, "black": sap.SAP_BLACK, "white": sap.SAP_WHITE}
+    for prec in (sap.SAP_F64, sap.SAP_F32):
+        info = sap.solve_blocks(ctx, fx, fb, 3, level, cmap[color], _opts(sap, prec))
+        x = gu.from_sap(ctx, fx, 3, b.shape)
+        assert np.all(x[~np.broadcast_to(m, x.shape)] == 0)       # unselected blocks zeroed
+        res = _relres(U, x, b, k, lb, m)
+        assert np.all(res <= 1e-10), res
+        nb = L[0] // lb
+        sel = [(kb % 2 == 1) if color == "black" else (kb % 2 == 0) if color == "white" else True
+               for kb in range(nb)]
+        for r in range(3):
+            for kb in range(nb):
+                e = info[r * nb + kb]
+                if sel[kb]:
+                    assert e.true_rel_res <= 1e-10 and e.iters > 0
+                else:
+                    assert e.iters == 0 and e.true_rel_res == 0
+        assert np.max(np.abs(x - x_ref)) / np.max(np.abs(x_ref)) <= 1e-7
+
+
+def test_solve_full_16x16x16x32(gu):
+    """The 16^3x32 workload (kappa = 0.1575): mixed-precision full solve, residual
+    recomputed by the oracle."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["plain_16x16x16x32"]
+    L, k = cfg["L"], cfg["kappa"]
+    print("solve_full 16^3x32", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    b = synth.gaussian_spinor(L, cfg["seed_src"])
+    ctx = gu.make_ctx(L, cfg["l0"], k, U, cfg["l0_sub"], max_rhs=1)
+    fb = gu.to_sap(ctx, b, 1)
+    fx = ctx.new_field(1)
+    for prec in (sap.SAP_F32, sap.SAP_F64):
+        info = sap.solve_full(ctx, fx, fb, 1, _opts(sap, prec))
+        x = gu.from_sap(ctx, fx, 1, b.shape)
+        res = float(_relres(U, x, b, k))
+        print(f"  inner={prec} iters={info[0].iters} outer={info[0].outer} res={res:.3e}", flush=True)
+        assert res <= 1e-10
+
+
+def test_solve_blocks_24x24x24x48_batched(gu):
+    """The 24^3x48 workload: 12 blocks (l0 = 4) x 12 right-hand sides and 24 sub-blocks
+    (l0 = 2) x 12 right-hand sides, FP32 inner solves in one batched solve each; residuals
+    of two right-hand sides recomputed by the oracle, all 144 / 288 from the info."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["batched_24x24x24x48"]
+    L, k, nrhs = cfg["L"], cfg["kappa"], cfg["nrhs"]
+    print("solve_blocks 24^3x48", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    b = synth.gaussian_spinor(L, cfg["seed_src"], nrhs=nrhs)
+    ctx = gu.make_ctx(L, cfg["l0"], k, U, cfg["l0_sub"], max_rhs=nrhs)
+    fb = gu.to_sap(ctx, b, nrhs)
+    fx = ctx.new_field(nrhs)
+    for level, lb in [(1, cfg["l0"]), (2, cfg["l0_sub"])]:
+        info = sap.solve_blocks(ctx, fx, fb, nrhs, level, sap.SAP_ALL, _opts(sap, sap.SAP_F32))
+        assert len(info) == nrhs * L[0] // lb
+        assert max(e.true_rel_res for e in info) <= 1e-10
+        x = gu.from_sap(ctx, fx, nrhs, b.shape)
+        for r in (0, nrhs - 1):
+            assert float(_relres(U, x[r], b[r], k, lb)) <= 1e-10
+
+
+def test_solver_error_paths(gu):
+    import paper_0710_0066_amd as sap
+    L, k = (4, 4, 4, 4), 0.155
+    U = synth.gauge_field(L, 0.5, 1001)
+    b = synth.gaussian_spinor(L, 2001)
+    ctx = gu.make_ctx(L, 2, k, U, max_rhs=1)
+    fb = gu.to_sap(ctx, b, 1)
+    fx = ctx.new_field(1)
+    with pytest.raises(sap.SapError) as e:
+        sap.solve_full(ctx, fx, fb, 1, _opts(sap, sap.SAP_F64, max_iter=1))
+    assert e.value.code == sap.SAP_E_NOCONV
+    assert e.value.info[0].true_rel_res > 1e-10
+    bad = b.copy()
+    bad[1, 2, 3, 0, 2, 1] = np.nan
+    fbad = gu.to_sap(ctx, bad, 1)
+    with pytest.raises(sap.SapError) as e:
+        sap.solve_full(ctx, fx, fbad, 1, _opts(sap, sap.SAP_F64))
+    assert e.value.code == sap.SAP_E_NONFINITE
+    with pytest.raises(sap.SapError) as e:
+        sap.solve_full(ctx, fx, fx, 1, _opts(sap, sap.SAP_F64))
+    assert e.value.code == sap.SAP_E_ARG
+    # a zero source gives x = 0 with no iterations
+    fz = ctx.new_field(1)
+    info = sap.solve_full(ctx, fx, fz, 1, _opts(sap, sap.SAP_F32))
+    assert info[0].iters == 0 and float(fx.abs().max()) == 0.0
