@@ -198,10 +198,33 @@ int block_pf_force(sap_ctx* ctx, double* F, double coef, const double* phi,
 int schwarz_boundary_force(sap_ctx* ctx, double* F, double coef, const double* chi,
                            const sap_solve_opts* opts, double* S_R_out, void* stream);
 
+/* Heat bath of the Schwarz boundary field (Sec. 1): chi = R_hat Pi g with
+ *   R_hat = Pi - Pi D_Om^{-1} D_dOm D_Om*^{-1} D_dOm* Pi   (block solves only),
+ * Omega = black level-1 blocks, D_Om / D_Om* = W1 on Omega / Omega*,
+ * D_dOm* = P_Om* M P_Om, D_dOm = P_Om M P_Om*, Pi = (1 - gamma_0)/2 on the first and
+ * (1 + gamma_0)/2 on the last slice of each black block. g: one FP64 field (sap layout),
+ * normally Gaussian noise with density exp(-|g|^2); chi: output field (sap layout). */
+int schwarz_heat_bath(sap_ctx* ctx, double* chi, const double* g, const sap_solve_opts* opts,
+                      void* stream);
+
+/* S_R = ||R_hat^{-1} chi||^2 with R_hat^{-1} chi = chi - Pi M^{-1} D_dOm* chi (one full
+ * solve). chi as for schwarz_boundary_force. *S_R_out (host) receives S_R. */
+int schwarz_action(sap_ctx* ctx, const double* chi, const sap_solve_opts* opts, double* S_R_out,
+                   void* stream);
+
 /* Gauge force of the Wilson plaquette action S_G (Sec. 1): F += coef * dS_G/dw.
  * *S_G_out (host, may be NULL) receives S_G. */
 int gauge_force(sap_ctx* ctx, double* F, double coef, double beta, double* S_G_out,
                 void* stream);
+
+/* The link step T_U(dt) of Sec. 2, eq. 3 on the context's gauge field:
+ * U_mu(x) <- exp(i dt P_mu(x)) U_mu(x), P = sum_a p^a T^a from the sap-layout momenta p
+ * (FP64 exponential, reunitarised). */
+int sap_update_links(sap_ctx* ctx, const double* p, double dt, void* stream);
+
+/* Mean plaquette (1/6V) sum_{x, mu>nu} (1/3) Re Tr U_P of the context's gauge field (host
+ * output). Synchronises. */
+int sap_plaquette(sap_ctx* ctx, double* plaq_out, void* stream);
 
 /* ---- HMC ------------------------------------------------------------------------ */
 

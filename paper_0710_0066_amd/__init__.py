@@ -92,6 +92,10 @@ _SIGS = {
     "block_pf_force": ([_P, _P, _D, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
     "schwarz_boundary_force": ([_P, _P, _D, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
     "gauge_force": ([_P, _P, _D, _D, _P, _P], _I),
+    "schwarz_heat_bath": ([_P, _P, _P, ctypes.POINTER(sap_solve_opts), _P], _I),
+    "schwarz_action": ([_P, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
+    "sap_update_links": ([_P, _P, _D, _P], _I),
+    "sap_plaquette": ([_P, _P, _P], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
 }
 for _name, (_args, _ret) in _SIGS.items():
@@ -177,6 +181,34 @@ def gauge_force(ctx, F, coef, beta):
     S = ctypes.c_double(0.0)
     _check(ctx.ptr, _lib.gauge_force(ctx.ptr, _ptr(F), coef, beta, ctypes.byref(S), _stream()))
     return S.value
+
+
+def schwarz_heat_bath(ctx, chi, g, opts):
+    _check(ctx.ptr, _lib.schwarz_heat_bath(ctx.ptr, _ptr(chi), _ptr(g), ctypes.byref(opts), _stream()))
+
+
+def schwarz_action(ctx, chi, opts):
+    S = ctypes.c_double(0.0)
+    _check(ctx.ptr, _lib.schwarz_action(ctx.ptr, _ptr(chi), ctypes.byref(opts), ctypes.byref(S),
+                                        _stream()))
+    return S.value
+
+
+def sap_update_links(ctx, p, dt):
+    _check(ctx.ptr, _lib.sap_update_links(ctx.ptr, _ptr(p), dt, _stream()))
+
+
+def sap_plaquette(ctx):
+    v = ctypes.c_double(0.0)
+    _check(ctx.ptr, _lib.sap_plaquette(ctx.ptr, ctypes.byref(v), _stream()))
+    return v.value
+
+
+def hmc_params(beta, tau, n_outer, n_inner, p0, xi1, xi2, u_metropolis, force_solve, action_solve,
+               lam=1.0 / 6.0, scheme_outer=1, scheme_inner=1):
+    """sap_hmc_params from torch tensors (p0 in the sap momentum layout, xi canonical)."""
+    return sap_hmc_params(beta, tau, lam, n_outer, n_inner, scheme_outer, scheme_inner, force_solve,
+                          action_solve, p0.data_ptr(), xi1.data_ptr(), xi2.data_ptr(), u_metropolis)
 
 
 def hmc_trajectory(ctx, U, params):

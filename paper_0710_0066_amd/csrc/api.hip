@@ -64,6 +64,10 @@ size_t sap_momenta_bytes(const sap_ctx* ctx) {
 
 void sap_solver_destroy(sap_ctx* ctx);   // solver.hip
 int sap_solver_create(sap_ctx* ctx);     // solver.hip
+}  // extern "C"
+int sap_force_create(sap_ctx* ctx);      // hmc.hip
+void sap_force_destroy(sap_ctx* ctx);    // hmc.hip
+extern "C" {
 
 int sap_create(const sap_geom* g, sap_ctx** out) {
   if (!out) return sap_fail(nullptr, SAP_E_ARG, "out pointer is NULL");
@@ -80,6 +84,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   c->U64 = nullptr;
   c->U32 = nullptr;
   c->solver = nullptr;
+  c->forces = nullptr;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return sap_fail(nullptr, SAP_E_HIP, "hipGetDevice failed (no HIP device?)");
@@ -91,6 +96,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
     return sap_fail(nullptr, SAP_E_NOMEM, "cannot allocate the gauge copies");
   }
   int rc = sap_solver_create(c);
+  if (rc == SAP_OK) rc = sap_force_create(c);
   if (rc != SAP_OK) {
     std::string m = c->err;
     sap_destroy(c);
@@ -103,6 +109,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
 void sap_destroy(sap_ctx* ctx) {
   if (!ctx) return;
   sap_solver_destroy(ctx);
+  sap_force_destroy(ctx);
   if (ctx->U64) (void)hipFree(ctx->U64);
   if (ctx->U32) (void)hipFree(ctx->U32);
   delete ctx;
@@ -190,6 +197,7 @@ static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, i
   A.nrhs = nrhs;
   A.parity_out = -1;
   A.lb = lb;
+  A.slb = lb;
   A.colour = colour;
   A.block = block;
   A.a = R(1);

@@ -58,8 +58,8 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
   const Site s = decode(g, j, p);
 
   V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
-  if (A.lb) {
-    const int blk = s.x0 / A.lb;
+  if (A.slb) {
+    const int blk = s.x0 / A.slb;
     bool sel;
     if (A.block >= 0) sel = (blk == A.block);
     else sel = (A.colour == 0) || ((A.colour == 1) == ((blk & 1) == 1));

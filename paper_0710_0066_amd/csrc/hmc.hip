@@ -1,0 +1,417 @@
+// Host drivers of the pseudo-fermion forces, the Schwarz boundary term and the HMC
+// trajectory (Sec. 1: factorised pseudo-fermion action with W1 and the black-block
+// boundary operator; Sec. 2: T_U / T_P steps, leap-frog and Sexton-Weingarten levels
+// nested on two time scales; Metropolis).
+//
+// Schwarz term (Omega = black x0 blocks, Omega* = white; Pi = (1 - g0)/2 on the first and
+// (1 + g0)/2 on the last slice of every black block):
+//   D_dOm* = P_Om* M P_Om,  D_dOm = P_Om M P_Om*,
+//   heat bath   chi = R_hat Pi g = Pi g - Pi W1^{-1}|_Om D_dOm W1^{-1}|_Om* D_dOm* Pi g,
+//   action      S_R = ||eta||^2,  eta = chi - Pi psi,  psi = M^{-1} D_dOm* chi,
+//   force       F = 2 Re <xi, dM psi> - 2 Re <P_Om* xi, dM chi>,  xi = M^{-dagger} Pi eta,
+// with M^{-dagger} = g5 M^{-1} g5 and W1^{-dagger} = g5 W1^{-1} g5.
+#include <cmath>
+#include <cstring>
+#include "force.h"
+
+using namespace sap;
+
+int sap_solve_any(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
+                  const sap_solve_opts* o, sap_solve_info* info, hipStream_t st);
+
+// Scratch fields: pf_force f[0..2]; schwarz_terms, heat_bath and check_chi f[3..6];
+// the trajectory keeps phi1 in f[7] and chi in f[8].
+struct ForceWS {
+  double2* f[9];       // full FP64 spinor fields of one rhs
+  double* mom;         // momenta (sap layout)
+  double* part;        // reduction partials (one per 128-site tile pair)
+  double* scal;        // device scalars
+  double* h_scal;      // pinned host mirror
+  long long iters;     // inner iterations accumulated by the drivers below
+};
+
+static ForceWS* fws(sap_ctx* c) { return (ForceWS*)c->forces; }
+
+int sap_force_create(sap_ctx* c) {
+  ForceWS* w = new ForceWS();
+  std::memset(w, 0, sizeof(*w));
+  c->forces = w;
+  const size_t fb = (size_t)24 * c->Vhp * sizeof(double2);
+  bool ok = true;
+  for (int i = 0; i < 9; ++i) ok = ok && hipMalloc((void**)&w->f[i], fb) == hipSuccess;
+  ok = ok && hipMalloc((void**)&w->mom, (size_t)64 * c->Vhp * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&w->part, (size_t)((c->Vh + 127) / 128 + 8) * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&w->scal, 64 * 8) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&w->h_scal, 64 * 8, 0) == hipSuccess;
+  if (!ok) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the force workspace");
+  for (int i = 0; i < 9; ++i) (void)hipMemset(w->f[i], 0, fb);
+  return SAP_OK;
+}
+
+void sap_force_destroy(sap_ctx* c) {
+  ForceWS* w = fws(c);
+  if (!w) return;
+  for (int i = 0; i < 9; ++i)
+    if (w->f[i]) (void)hipFree(w->f[i]);
+  if (w->mom) (void)hipFree(w->mom);
+  if (w->part) (void)hipFree(w->part);
+  if (w->scal) (void)hipFree(w->scal);
+  if (w->h_scal) (void)hipHostFree(w->h_scal);
+  delete w;
+  c->forces = nullptr;
+}
+
+namespace {
+
+// |f|^2 of one full FP64 field, read back to the host (synchronises)
+int norm2_host(sap_ctx* c, const double2* f, double* out, hipStream_t s) {
+  ForceWS* w = fws(c);
+  launch_norm2_full(c->g, f, w->part, w->scal, s);
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_scal, w->scal, 8, hipMemcpyDeviceToHost, s));
+  SAP_HIP_CHECK(c, hipStreamSynchronize(s));
+  *out = w->h_scal[0];
+  return SAP_OK;
+}
+
+// out = M in on the sites of the selected colour of level-1 blocks, 0 elsewhere
+void hop_M_sel(sap_ctx* c, double2* out, const double2* in, int colour, hipStream_t s) {
+  HopArgs<double> A;
+  const long long Vhp = c->Vhp;
+  A.out = {out, 24 * Vhp, 12 * Vhp};
+  A.in = {(double2*)in, 24 * Vhp, 12 * Vhp};
+  A.x = A.in;
+  A.U = c->U64;
+  A.g = c->g;
+  A.nrhs = 1;
+  A.parity_out = -1;
+  A.lb = 0;
+  A.slb = c->geom.l0;
+  A.colour = colour;
+  A.block = -1;
+  A.a = 1.0;
+  A.b = -c->geom.kappa;
+  A.g5_in = A.g5_out = 0;
+  launch_hop<double>(A, s);
+}
+
+int solve1(sap_ctx* c, double2* x, const double2* b, int lb, int colour, const sap_solve_opts* o,
+           hipStream_t s) {
+  sap_solve_info inf[64];
+  const int nsys = lb ? c->geom.L[0] / lb : 1;
+  sap_solve_info* ip = nsys <= 64 ? inf : nullptr;
+  int rc = sap_solve_any(c, (double*)x, (const double*)b, 1, lb, colour, o, ip, s);
+  if (ip)
+    for (int i = 0; i < nsys; ++i) fws(c)->iters += inf[i].iters;
+  return rc;
+}
+
+int check_opts(sap_ctx* c, const sap_solve_opts* o) {
+  if (!o) return sap_fail(c, SAP_E_ARG, "opts is NULL");
+  if (!(o->tol > 0 && o->tol < 1) || o->max_iter < 1 || o->max_outer < 1)
+    return sap_fail(c, SAP_E_ARG, "invalid solve options");
+  if (o->inner_prec != SAP_F64 && o->inner_prec != SAP_F32) return sap_fail(c, SAP_E_ARG, "unknown inner precision");
+  if (o->inner_prec == SAP_F32 && !(o->inner_tol > 0 && o->inner_tol < 1))
+    return sap_fail(c, SAP_E_ARG, "inner_tol must be in (0, 1) for an FP32 inner solve");
+  return SAP_OK;
+}
+
+int pf_force(sap_ctx* c, double* F, double coef, const double2* phi, const sap_solve_opts* o, double* S,
+             hipStream_t s) {
+  ForceWS* w = fws(c);
+  const int l0 = c->geom.l0;
+  double2 *X = w->f[0], *T = w->f[1], *Y = w->f[2];
+  int rc = solve1(c, X, phi, l0, SAP_ALL, o, s);                 // X = W1^{-1} phi
+  if (rc) return rc;
+  if (S && (rc = norm2_host(c, X, S, s))) return rc;
+  launch_spin_op(c->g, 0, l0, T, X, nullptr, s);                 // Y = g5 W1^{-1} g5 X
+  if ((rc = solve1(c, Y, T, l0, SAP_ALL, o, s))) return rc;
+  launch_spin_op(c->g, 0, l0, Y, Y, nullptr, s);
+  // F += coef * (-2 Re <Y, dW1 X>)
+  launch_pair_force(c->g, F, c->geom.kappa * coef, Y, X, c->U64, l0, s);
+  SAP_HIP_CHECK(c, hipGetLastError());
+  return SAP_OK;
+}
+
+int schwarz_terms(sap_ctx* c, double* F, double coef, const double2* chi, const sap_solve_opts* o,
+                  double* S_R, hipStream_t s) {
+  ForceWS* w = fws(c);
+  const int l0 = c->geom.l0;
+  double2 *v = w->f[3], *psi = w->f[4], *eta = w->f[5], *t = w->f[6];
+  hop_M_sel(c, v, chi, SAP_WHITE, s);                            // v = D_dOm* chi
+  int rc = solve1(c, psi, v, 0, SAP_ALL, o, s);                  // psi = M^{-1} v
+  if (rc) return rc;
+  launch_spin_op(c->g, 3, l0, eta, chi, psi, s);                 // eta = chi - Pi psi
+  if (S_R && (rc = norm2_host(c, eta, S_R, s))) return rc;
+  if (!F) return SAP_OK;
+  launch_spin_op(c->g, 1, l0, t, eta, nullptr, s);               // t = g5 Pi eta
+  launch_spin_op(c->g, 0, l0, t, t, nullptr, s);
+  if ((rc = solve1(c, v, t, 0, SAP_ALL, o, s))) return rc;       // xi = g5 M^{-1} g5 Pi eta
+  launch_spin_op(c->g, 0, l0, v, v, nullptr, s);
+  launch_pair_force(c->g, F, -c->geom.kappa * coef, v, psi, c->U64, 0, s);
+  launch_spin_op(c->g, 2, l0, t, v, nullptr, s);                 // P_Om* xi
+  launch_pair_force(c->g, F, c->geom.kappa * coef, t, chi, c->U64, 0, s);
+  SAP_HIP_CHECK(c, hipGetLastError());
+  return SAP_OK;
+}
+
+int heat_bath(sap_ctx* c, double2* chi, const double2* g, const sap_solve_opts* o, hipStream_t s) {
+  ForceWS* w = fws(c);
+  const int l0 = c->geom.l0;
+  double2 *pg = w->f[3], *v = w->f[4], *x = w->f[5], *u = w->f[6];
+  launch_spin_op(c->g, 1, l0, pg, g, nullptr, s);                // Pi g
+  hop_M_sel(c, v, pg, SAP_WHITE, s);                             // D_dOm* Pi g
+  int rc = solve1(c, x, v, l0, SAP_WHITE, o, s);                 // white-block solves
+  if (rc) return rc;
+  hop_M_sel(c, u, x, SAP_BLACK, s);                              // D_dOm (x vanishes on black)
+  if ((rc = solve1(c, v, u, l0, SAP_BLACK, o, s))) return rc;    // black-block solves
+  launch_spin_op(c->g, 3, l0, chi, pg, v, s);                    // chi = Pi g - Pi z
+  SAP_HIP_CHECK(c, hipGetLastError());
+  return SAP_OK;
+}
+
+int check_chi(sap_ctx* c, const double2* chi, hipStream_t s) {
+  ForceWS* w = fws(c);
+  double n_chi = 0, n_off = 0;
+  int rc = norm2_host(c, chi, &n_chi, s);
+  if (rc) return rc;
+  launch_spin_op(c->g, 3, c->geom.l0, w->f[6], chi, chi, s);     // chi - Pi chi
+  if ((rc = norm2_host(c, w->f[6], &n_off, s))) return rc;
+  if (!(n_off <= 1e-24 * n_chi))
+    return sap_fail(c, SAP_E_ARG, "chi is not supported on the black-block boundaries in the range of Pi");
+  return SAP_OK;
+}
+
+int gauge_action_host(sap_ctx* c, double beta, double* S, hipStream_t s) {
+  ForceWS* w = fws(c);
+  launch_plaq_sum(c->g, c->U64, w->part, w->scal, s);
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_scal, w->scal, 8, hipMemcpyDeviceToHost, s));
+  SAP_HIP_CHECK(c, hipStreamSynchronize(s));
+  *S = -beta / 3.0 * w->h_scal[0];
+  return SAP_OK;
+}
+
+int kinetic_host(sap_ctx* c, const double* P, double* K, hipStream_t s) {
+  ForceWS* w = fws(c);
+  launch_kinetic(c->g, P, w->part, w->scal, s);
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_scal, w->scal, 8, hipMemcpyDeviceToHost, s));
+  SAP_HIP_CHECK(c, hipStreamSynchronize(s));
+  *K = w->h_scal[0];
+  return SAP_OK;
+}
+
+void links_changed(sap_ctx* c, hipStream_t s) { launch_gauge_to_f32(c->g, c->U32, c->U64, s); }
+
+// ---- the two-level integrator --------------------------------------------------------
+struct Traj {
+  sap_ctx* c;
+  const sap_hmc_params* P;
+  const double2 *phi1, *chi;
+  hipStream_t s;
+};
+
+int kick_pf(Traj& T, double dt) {
+  int rc = pf_force(T.c, fws(T.c)->mom, -dt, T.phi1, &T.P->force_solve, nullptr, T.s);
+  if (rc) return rc;
+  return schwarz_terms(T.c, fws(T.c)->mom, -dt, T.chi, &T.P->force_solve, nullptr, T.s);
+}
+int kick_g(Traj& T, double dt) {
+  launch_gauge_force(T.c->g, fws(T.c)->mom, -dt * T.P->beta / 6.0, T.c->U64, T.s);
+  SAP_HIP_CHECK(T.c, hipGetLastError());
+  return SAP_OK;
+}
+int move_links(Traj& T, double dt) {
+  launch_update_links(T.c->g, T.c->U64, fws(T.c)->mom, dt, T.s);
+  links_changed(T.c, T.s);
+  SAP_HIP_CHECK(T.c, hipGetLastError());
+  return SAP_OK;
+}
+// level 0: gauge action
+int step0(Traj& T, double dt) {
+  int rc;
+  const double l = T.P->lambda;
+  if (T.P->scheme_inner == 0) {
+    if ((rc = kick_g(T, 0.5 * dt)) || (rc = move_links(T, dt)) || (rc = kick_g(T, 0.5 * dt))) return rc;
+  } else {
+    if ((rc = kick_g(T, l * dt)) || (rc = move_links(T, 0.5 * dt)) || (rc = kick_g(T, (1 - 2 * l) * dt)) ||
+        (rc = move_links(T, 0.5 * dt)) || (rc = kick_g(T, l * dt)))
+      return rc;
+  }
+  return SAP_OK;
+}
+// level 1: pseudo-fermion action, n_inner steps of level 0 per step
+int step1(Traj& T, double dt) {
+  int rc;
+  const int n = T.P->n_inner;
+  const double d0 = dt / n, l = T.P->lambda;
+  if (T.P->scheme_outer == 0) {
+    if ((rc = kick_pf(T, 0.5 * dt))) return rc;
+    for (int i = 0; i < n; ++i)
+      if ((rc = step0(T, d0))) return rc;
+    return kick_pf(T, 0.5 * dt);
+  }
+  if ((rc = kick_pf(T, l * dt))) return rc;
+  for (int i = 0; i < n / 2; ++i)
+    if ((rc = step0(T, d0))) return rc;
+  if ((rc = kick_pf(T, (1 - 2 * l) * dt))) return rc;
+  for (int i = 0; i < n / 2; ++i)
+    if ((rc = step0(T, d0))) return rc;
+  return kick_pf(T, l * dt);
+}
+
+int hamiltonian(Traj& T, double* K, double* SG, double* SW, double* SR) {
+  int rc;
+  if ((rc = kinetic_host(T.c, fws(T.c)->mom, K, T.s))) return rc;
+  if ((rc = gauge_action_host(T.c, T.P->beta, SG, T.s))) return rc;
+  ForceWS* w = fws(T.c);
+  if ((rc = solve1(T.c, w->f[0], T.phi1, T.c->geom.l0, SAP_ALL, &T.P->action_solve, T.s))) return rc;
+  if ((rc = norm2_host(T.c, w->f[0], SW, T.s))) return rc;
+  return schwarz_terms(T.c, nullptr, 0.0, T.chi, &T.P->action_solve, SR, T.s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int block_pf_force(sap_ctx* c, double* F, double coef, const double* phi, const sap_solve_opts* o,
+                   double* S_out, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!F || !phi) return sap_fail(c, SAP_E_ARG, "F or phi is NULL");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  return pf_force(c, F, coef, (const double2*)phi, o, S_out, (hipStream_t)stream);
+}
+
+int schwarz_boundary_force(sap_ctx* c, double* F, double coef, const double* chi, const sap_solve_opts* o,
+                           double* S_R_out, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!F || !chi) return sap_fail(c, SAP_E_ARG, "F or chi is NULL");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = check_chi(c, (const double2*)chi, s))) return rc;
+  return schwarz_terms(c, F, coef, (const double2*)chi, o, S_R_out, s);
+}
+
+int schwarz_heat_bath(sap_ctx* c, double* chi, const double* g, const sap_solve_opts* o, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!chi || !g || chi == g) return sap_fail(c, SAP_E_ARG, "chi and g must be distinct non-NULL fields");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  return heat_bath(c, (double2*)chi, (const double2*)g, o, (hipStream_t)stream);
+}
+
+int schwarz_action(sap_ctx* c, const double* chi, const sap_solve_opts* o, double* S_R_out, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!chi || !S_R_out) return sap_fail(c, SAP_E_ARG, "chi or S_R_out is NULL");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = check_chi(c, (const double2*)chi, s))) return rc;
+  return schwarz_terms(c, nullptr, 0.0, (const double2*)chi, o, S_R_out, s);
+}
+
+int gauge_force(sap_ctx* c, double* F, double coef, double beta, double* S_G_out, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!F) return sap_fail(c, SAP_E_ARG, "F is NULL");
+  if (!std::isfinite(beta)) return sap_fail(c, SAP_E_ARG, "beta must be finite");
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  hipStream_t s = (hipStream_t)stream;
+  launch_gauge_force(c->g, F, coef * beta / 6.0, c->U64, s);
+  SAP_HIP_CHECK(c, hipGetLastError());
+  if (S_G_out) return gauge_action_host(c, beta, S_G_out, s);
+  return SAP_OK;
+}
+
+int sap_update_links(sap_ctx* c, const double* p, double dt, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!p) return sap_fail(c, SAP_E_ARG, "p is NULL");
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  hipStream_t s = (hipStream_t)stream;
+  launch_update_links(c->g, c->U64, p, dt, s);
+  links_changed(c, s);
+  SAP_HIP_CHECK(c, hipGetLastError());
+  return SAP_OK;
+}
+
+int sap_plaquette(sap_ctx* c, double* plaq_out, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!plaq_out) return sap_fail(c, SAP_E_ARG, "plaq_out is NULL");
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  double S;
+  int rc = gauge_action_host(c, -3.0, &S, (hipStream_t)stream);    // S = sum Re tr U_P
+  if (rc) return rc;
+  *plaq_out = S / (18.0 * (double)c->V);
+  return SAP_OK;
+}
+
+int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream);
+int sap_get_gauge(sap_ctx* ctx, double* U, void* stream);
+int sap_pack_spinor(sap_ctx* ctx, void* out, const double* in, int nrhs, sap_prec prec, void* stream);
+
+int hmc_trajectory(sap_ctx* c, double* U, const sap_hmc_params* P, sap_hmc_info* info, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!U || !P || !info) return sap_fail(c, SAP_E_ARG, "U, params and info must be non-NULL");
+  if (!P->p0 || !P->xi1 || !P->xi2) return sap_fail(c, SAP_E_ARG, "p0, xi1 and xi2 must be given");
+  if (P->n_outer < 1 || P->n_inner < 1) return sap_fail(c, SAP_E_ARG, "n_outer and n_inner must be >= 1");
+  if ((P->scheme_outer != 0 && P->scheme_outer != 1) || (P->scheme_inner != 0 && P->scheme_inner != 1))
+    return sap_fail(c, SAP_E_ARG, "scheme must be 0 (leap-frog) or 1 (Sexton-Weingarten)");
+  if (P->scheme_outer == 1 && (P->n_inner % 2))
+    return sap_fail(c, SAP_E_ARG, "a Sexton-Weingarten outer level needs an even n_inner");
+  if (!(P->tau > 0) || !std::isfinite(P->beta) || !std::isfinite(P->lambda))
+    return sap_fail(c, SAP_E_ARG, "tau must be > 0, beta and lambda finite");
+  int rc;
+  if ((rc = check_opts(c, &P->force_solve)) || (rc = check_opts(c, &P->action_solve))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  ForceWS* w = fws(c);
+  w->iters = 0;
+  std::memset(info, 0, sizeof(*info));
+  if ((rc = sap_set_gauge(c, U, stream))) return rc;
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->mom, P->p0, (size_t)64 * c->Vhp * 8, hipMemcpyDeviceToDevice, s));
+  // heat bath: phi1 = W1 xi1, chi = R_hat Pi xi2 (xi staged in f[0])
+  double2 *phi1 = w->f[7], *chi = w->f[8];
+  if ((rc = sap_pack_spinor(c, w->f[0], P->xi1, 1, SAP_F64, stream))) return rc;
+  HopArgs<double> A;
+  const long long Vhp = c->Vhp;
+  A.out = {phi1, 24 * Vhp, 12 * Vhp};
+  A.in = {w->f[0], 24 * Vhp, 12 * Vhp};
+  A.x = A.in;
+  A.U = c->U64; A.g = c->g; A.nrhs = 1; A.parity_out = -1;
+  A.lb = c->geom.l0; A.slb = c->geom.l0; A.colour = 0; A.block = -1;
+  A.a = 1.0; A.b = -c->geom.kappa; A.g5_in = A.g5_out = 0;
+  launch_hop<double>(A, s);
+  if ((rc = sap_pack_spinor(c, w->f[0], P->xi2, 1, SAP_F64, stream))) return rc;
+  if ((rc = heat_bath(c, chi, w->f[0], &P->action_solve, s))) goto fail;
+  {
+    Traj T = {c, P, phi1, chi, s};
+    double K0, K1;
+    if ((rc = hamiltonian(T, &K0, &info->S_G0, &info->S_W0, &info->S_R0))) goto fail;
+    info->H0 = K0 + info->S_G0 + info->S_W0 + info->S_R0;
+    const double dt = P->tau / P->n_outer;
+    for (int k = 0; k < P->n_outer; ++k)
+      if ((rc = step1(T, dt))) goto fail;
+    if ((rc = hamiltonian(T, &K1, &info->S_G1, &info->S_W1, &info->S_R1))) goto fail;
+    info->H1 = K1 + info->S_G1 + info->S_W1 + info->S_R1;
+    info->dH = info->H1 - info->H0;
+    info->accepted = P->u_metropolis < std::exp(-info->dH);
+    if (info->accepted) {
+      if ((rc = sap_get_gauge(c, U, stream))) goto fail;
+    } else if ((rc = sap_set_gauge(c, U, stream))) {
+      goto fail;
+    }
+    info->solver_iters = w->iters;
+    if ((rc = sap_plaquette(c, &info->plaq, stream))) return rc;
+    return SAP_OK;
+  }
+fail : {
+  const std::string m = c->err;
+  (void)sap_set_gauge(c, U, stream);     // leave the context on the caller's field
+  c->err = m;
+  return rc;
+}
+}
+
+}  // extern "C"

@@ -27,8 +27,9 @@ template <class R> struct HopArgs {
   Geo g;
   int nrhs;
   int parity_out;          // -1: both parities (full operator); 0/1: that parity only
-  int lb;                  // x0 block length, 0 = no blocks
-  int colour;              // 0 all, 1 black (odd b), 2 white (even b)
+  int lb;                  // hops between x0 blocks of this length are dropped (0: none)
+  int slb;                 // output restricted to x0 blocks of this length (0: all sites)
+  int colour;              // selection for slb: 0 all, 1 black (odd b), 2 white (even b)
   int block;               // >= 0: only this block (colour ignored)
   R a, b;
   int g5_in, g5_out;       // multiply the hop input / the hop result by gamma_5
@@ -69,9 +70,9 @@ struct sap_ctx {
   bool have_gauge;
   double2* U64;   // tiled gauge layout, 72*Vhp complex
   float2* U32;
-  std::vector<void*> allocations;
   std::string err;
   void* solver;   // solver workspace (solver.hip)
+  void* forces;   // force / trajectory workspace (hmc.hip)
 };
 
 // error helpers (api.hip)

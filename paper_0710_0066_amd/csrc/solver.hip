@@ -108,6 +108,7 @@ void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int p
   A.nrhs = nrhs;
   A.parity_out = parity_out;
   A.lb = lb;
+  A.slb = lb;
   A.colour = colour;
   A.block = -1;
   A.a = a;

@@ -1,0 +1,251 @@
+"""GPU parity of the forces, the Schwarz boundary term, the link update and the HMC
+trajectory against the FP64 oracle (small lattices, tight solves on both sides), and the
+force/action consistency on the 16^3x32 workload by a central finite difference
+(eps = 1e-5) along a random su(3) direction."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import dirac, forces, hmc, lattice, schwarz, solvers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gu():
+    import gpu_util
+    return gpu_util
+
+
+def _opts(sap, tol=1e-13, inner=None):
+    inner = sap.SAP_F64 if inner is None else inner
+    return sap.solve_opts(tol=tol, max_iter=500000, inner_prec=inner, inner_tol=1e-6, max_outer=80)
+
+
+def _mom_to_sap(ctx, gu, p):
+    f = ctx.new_momenta()
+    ctx.pack_momenta(f, gu.dev(p))
+    return f
+
+
+def _mom_from_sap(ctx, f, L):
+    out = torch.zeros(int(np.prod(L)) * 32, dtype=torch.float64, device="cuda")
+    ctx.unpack_momenta(out, f)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().reshape(tuple(L) + (4, 8))
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def test_gauge_force_plaquette_and_link_update(gu):
+    import paper_0710_0066_amd as sap
+    L, beta = (8, 4, 2, 6), 5.6
+    print("gauge force / plaquette / T_U", flush=True)
+    U = synth.gauge_field(L, 0.5, 71)
+    ctx = gu.make_ctx(L, 2, 0.15, U)
+    F = ctx.new_momenta()
+    SG = sap.gauge_force(ctx, F, 1.0, beta)
+    assert _rel(_mom_from_sap(ctx, F, L), forces.gauge_force(U, beta)) <= 1e-12
+    assert abs(SG - forces.gauge_action(U, beta)) <= 1e-12 * abs(SG)
+    assert abs(sap.sap_plaquette(ctx) - forces.mean_plaquette(U)) <= 1e-14
+    # coef scales and accumulates
+    sap.gauge_force(ctx, F, -3.0, beta)
+    assert _rel(_mom_from_sap(ctx, F, L), -2.0 * forces.gauge_force(U, beta)) <= 1e-12
+    # T_U(dt): U <- exp(i dt P) U
+    p = synth.gaussian_momenta(L, 72)
+    sap.sap_update_links(ctx, _mom_to_sap(ctx, gu, p), 0.37)
+    Uo = torch.zeros(U.size, dtype=torch.complex128, device="cuda")
+    ctx.get_gauge(Uo)
+    ref = hmc.T_U(U, p, 0.37)
+    assert np.max(np.abs(Uo.cpu().numpy().reshape(U.shape) - ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("L,l0,k", [((8, 4, 4, 4), 2, 0.155), ((12, 2, 4, 6), 3, 0.15)])
+def test_block_pf_force_matches_oracle(gu, L, l0, k):
+    import paper_0710_0066_amd as sap
+    print(f"block_pf_force L={L}", flush=True)
+    U = synth.gauge_field(L, 0.5, 73)
+    phi = synth.gaussian_spinor(L, 74)
+    ctx = gu.make_ctx(L, l0, k, U)
+    F = ctx.new_momenta()
+    S = sap.block_pf_force(ctx, F, 1.0, gu.to_sap(ctx, phi, 1), _opts(sap))
+    ref = forces.pf_force(U, phi, k, l0, tol=1e-13)
+    assert _rel(_mom_from_sap(ctx, F, L), ref) <= 1e-9
+    assert abs(S - forces.pf_action(U, phi, k, l0, tol=1e-13)) <= 1e-10 * S
+    # the force on links between blocks vanishes
+    Fg = _mom_from_sap(ctx, F, L)
+    x0 = np.arange(L[0])
+    assert np.all(Fg[(x0 % l0) == l0 - 1, :, :, :, 0] == 0)
+
+
+def test_schwarz_heat_bath_action_force_match_oracle(gu):
+    import paper_0710_0066_amd as sap
+    L, l0, k = (8, 4, 4, 4), 2, 0.155
+    print("schwarz heat bath / action / force", flush=True)
+    U = synth.gauge_field(L, 0.5, 75)
+    g = synth.noise_spinor(L, 76)
+    ctx = gu.make_ctx(L, l0, k, U)
+    S_or = schwarz.Solvers(U, k, l0, tol=1e-13)
+    chi_ref = schwarz.heat_bath(U, g, k, l0, S_or)
+    fchi = ctx.new_field(1)
+    sap.schwarz_heat_bath(ctx, fchi, gu.to_sap(ctx, g, 1), _opts(sap))
+    chi = gu.from_sap(ctx, fchi, 1, g.shape)
+    assert _rel(chi, chi_ref) <= 1e-10
+    SR = sap.schwarz_action(ctx, fchi, _opts(sap))
+    SR_ref = schwarz.action(U, chi_ref, k, l0, S_or)
+    assert abs(SR - SR_ref) <= 1e-10 * SR_ref
+    # at the heat bath, S_R = ||Pi g||^2 (R_hat^{-1} R_hat = 1)
+    assert abs(SR - float(np.sum(np.abs(schwarz.Pi(g, L, l0)) ** 2))) <= 1e-9 * SR
+    F = ctx.new_momenta()
+    SR2 = sap.schwarz_boundary_force(ctx, F, 1.0, fchi, _opts(sap))
+    assert abs(SR2 - SR) <= 1e-12 * SR
+    ref = forces.schwarz_force(U, chi_ref, k, l0, S_or)
+    assert _rel(_mom_from_sap(ctx, F, L), ref) <= 1e-9
+    # a field outside the range of Pi is rejected
+    with pytest.raises(sap.SapError) as e:
+        sap.schwarz_boundary_force(ctx, F, 1.0, gu.to_sap(ctx, g, 1), _opts(sap))
+    assert e.value.code == sap.SAP_E_ARG
+
+
+def _g5(f):
+    out = f.copy()
+    out[..., 2:, :] *= -1
+    return out
+
+
+def test_forces_match_finite_differences_16x16x16x32(gu):
+    """d/dt S(exp(i t Omega) U) at t = 0 by a central difference with eps = 1e-5 against
+    sum F^a omega^a, S = S_G + ||W1^{-1} phi||^2 + S_R, beta = 5.6, kappa = 0.1575.
+    The pseudo-fermion actions are evaluated with estimators whose error is quadratic in
+    the solver error: S_W = 2 Re<phi, y> - ||W1^dag y||^2 with y = (W1 W1^dag)^{-1} phi, and
+    S_R = ||eta||^2 + 2 Re<xi, M psi - v>."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["hmc_16x16x16x32"]
+    L, k, l0, beta = cfg["L"], cfg["kappa"], cfg["l0"], cfg["beta"]
+    print("FD 16^3x32", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    phi = synth.gaussian_spinor(L, cfg["seed_src"])
+    omega = synth.gaussian_momenta(L, 3050)
+    ctx = gu.make_ctx(L, l0, k, U, cfg["l0_sub"])
+    o = _opts(sap, tol=1e-12, inner=sap.SAP_F32)
+    fphi = gu.to_sap(ctx, phi, 1)
+    fchi = ctx.new_field(1)
+    sap.schwarz_heat_bath(ctx, fchi, gu.to_sap(ctx, synth.noise_spinor(L, cfg["seed_noise2"]), 1), o)
+    chi = gu.from_sap(ctx, fchi, 1, phi.shape)
+    F = ctx.new_momenta()
+    sap.gauge_force(ctx, F, 1.0, beta)
+    sap.block_pf_force(ctx, F, 1.0, fphi, o)
+    sap.schwarz_boundary_force(ctx, F, 1.0, fchi, o)
+    an = float(np.sum(_mom_from_sap(ctx, F, L) * omega))
+    fom = _mom_to_sap(ctx, gu, omega)
+    dummy = ctx.new_momenta()
+    white = lattice.site_mask(L, lattice.colour_x0_mask(L, l0, "white"))
+
+    def apply(field, op):
+        fin = gu.to_sap(ctx, field, 1)
+        fout = ctx.new_field(1)
+        if op == "M":
+            sap.apply_M(ctx, fout, fin, 1, sap.SAP_F64)
+        else:
+            sap.apply_W1_block(ctx, fout, fin, 1, 1, -1, sap.SAP_ALL, sap.SAP_F64)
+        return gu.from_sap(ctx, fout, 1, field.shape)
+
+    def solve(field, op):
+        fb = gu.to_sap(ctx, field, 1)
+        fx = ctx.new_field(1)
+        if op == "M":
+            sap.solve_full(ctx, fx, fb, 1, o)
+        else:
+            sap.solve_blocks(ctx, fx, fb, 1, 1, sap.SAP_ALL, o)
+        return gu.from_sap(ctx, fx, 1, field.shape)
+
+    def action(t):
+        ctx.set_gauge(gu.dev(U))
+        sap.sap_update_links(ctx, fom, t)
+        SG = sap.gauge_force(ctx, dummy, 0.0, beta)
+        X = solve(phi, "W")
+        y = _g5(solve(_g5(X), "W"))
+        W_dag_y = _g5(apply(_g5(y), "W"))
+        SW = 2 * np.vdot(phi, y).real - np.vdot(W_dag_y, W_dag_y).real
+        v = apply(chi, "M") * white
+        psi = solve(v, "M")
+        eta = chi - schwarz.Pi(psi, L, l0)
+        xi = _g5(solve(_g5(schwarz.Pi(eta, L, l0)), "M"))
+        SR = np.vdot(eta, eta).real + 2 * np.vdot(xi, apply(psi, "M") - v).real
+        return SG + SW + SR
+
+    eps = 1e-5
+    fd = (action(eps) - action(-eps)) / (2 * eps)
+    print(f"  FD {fd:.10e}  analytic {an:.10e}  rel {abs(fd - an) / abs(an):.2e}", flush=True)
+    assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def _hmc_inputs(L, seed):
+    return (synth.gaussian_momenta(L, seed), synth.noise_spinor(L, seed + 1),
+            synth.noise_spinor(L, seed + 2))
+
+
+def test_hmc_trajectory_matches_oracle(gu):
+    """One tau = 0.5 trajectory, two Sexton-Weingarten levels (pseudo-fermion n_outer = 3,
+    gauge n_inner = 2), same momenta, noise and Metropolis number on both sides."""
+    import paper_0710_0066_amd as sap
+    L, l0, k, beta, tau = (8, 4, 2, 4), 2, 0.15, 5.6, 0.5
+    print("hmc vs oracle", flush=True)
+    U = synth.gauge_field(L, 0.3, 77)
+    p0, xi1, xi2 = _hmc_inputs(L, 78)
+    # oracle
+    mk = lambda V: schwarz.Solvers(V, k, l0, tol=1e-13)
+    phi1 = dirac.apply_W(U, xi1, k, l0)
+    chi = schwarz.heat_bath(U, xi2, k, l0, mk(U))
+    lev = hmc.schwarz_two_level(phi1, chi, k, beta, l0, 3, 2, mk)
+    U_ref, acc_ref, dH_ref, H0_ref, H1_ref = hmc.trajectory(lev, U, p0, tau, u_metropolis=0.0)
+    # GPU
+    ctx = gu.make_ctx(L, l0, k, U)
+    fU = gu.dev(U).clone()
+    o = _opts(sap, tol=1e-13)
+    prm = sap.hmc_params(beta, tau, 3, 2, _mom_to_sap(ctx, gu, p0), gu.dev(xi1), gu.dev(xi2), 0.0, o, o)
+    info = sap.hmc_trajectory(ctx, fU, prm)
+    print(f"  dH gpu {info.dH:.12e} oracle {dH_ref:.12e}", flush=True)
+    assert info.accepted == 1 and acc_ref
+    assert abs(info.H0 - H0_ref) <= 1e-9 * abs(H0_ref)
+    assert abs(info.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref))
+    Ug = fU.cpu().numpy().reshape(U.shape)
+    assert np.max(np.abs(Ug - U_ref)) <= 1e-9
+    assert abs(info.plaq - forces.mean_plaquette(U_ref)) <= 1e-12
+    # rejection leaves the field unchanged
+    fU2 = gu.dev(U).clone()
+    prm2 = sap.hmc_params(beta, tau, 3, 2, _mom_to_sap(ctx, gu, p0), gu.dev(xi1), gu.dev(xi2),
+                          float(np.nextafter(np.exp(-info.dH), 2.0)), o, o)
+    info2 = sap.hmc_trajectory(ctx, fU2, prm2)
+    assert info2.accepted == 0 and torch.equal(fU2, gu.dev(U))
+
+
+def test_hmc_trajectory_16x16x16x32(gu):
+    """One tau = 1 trajectory on the 16^3x32 workload (beta = 5.6, kappa = 0.1575), two
+    Sexton-Weingarten levels (8 pseudo-fermion steps, 4 gauge steps each), mixed-precision
+    solves to 1e-10. Checks the heat-bath identities S_W0 = ||xi1||^2, S_R0 = ||Pi xi2||^2
+    and reports dH."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["hmc_16x16x16x32"]
+    L, k, l0, beta = cfg["L"], cfg["kappa"], cfg["l0"], cfg["beta"]
+    print("hmc 16^3x32", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    p0 = synth.gaussian_momenta(L, cfg["seed_mom"])
+    xi1 = synth.noise_spinor(L, cfg["seed_noise1"])
+    xi2 = synth.noise_spinor(L, cfg["seed_noise2"])
+    u = synth.uniform(cfg["seed_metropolis"])
+    ctx = gu.make_ctx(L, l0, k, U, cfg["l0_sub"])
+    fU = gu.dev(U).clone()
+    fo = _opts(sap, tol=1e-10, inner=sap.SAP_F32)
+    ao = _opts(sap, tol=1e-12, inner=sap.SAP_F32)
+    prm = sap.hmc_params(beta, 1.0, 8, 4, _mom_to_sap(ctx, gu, p0), gu.dev(xi1), gu.dev(xi2), u, fo, ao)
+    info = sap.hmc_trajectory(ctx, fU, prm)
+    print(f"  dH {info.dH:.6e} accepted {info.accepted} plaq {info.plaq:.6f} iters {info.solver_iters}",
+          flush=True)
+    assert np.isfinite(info.dH)
+    assert abs(info.S_W0 - float(np.sum(np.abs(xi1) ** 2))) <= 1e-8 * info.S_W0
+    assert abs(info.S_R0 - float(np.sum(np.abs(schwarz.Pi(xi2, L, l0)) ** 2))) <= 1e-8 * info.S_R0
+    assert info.accepted == (u < np.exp(-info.dH))
