@@ -163,6 +163,25 @@ int apply_M(sap_ctx* ctx, void* out, const void* in, int nrhs, sap_prec prec, vo
 int apply_W1_block(sap_ctx* ctx, void* out, const void* in, int nrhs, int level, int block,
                    sap_color color, sap_prec prec, void* stream);
 
+/* Even-odd hop (Sec. 1, W_eo: M = [[1, -kappa D_eo], [-kappa D_oe, 1]] in the (even, odd)
+ * partition): on the sites of parity `parity` (0 even, 1 odd), out = D in, where D is
+ * the hop sum of eq. 2 without the factor -kappa and without the unit term, reading `in`
+ * on the other parity only. Sites of the other parity of out are not written. Fields:
+ * nrhs fields in the sap layout at precision prec; out and in must not overlap. This is
+ * the operator that the even-odd solvers apply four times per iteration. */
+int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, sap_prec prec,
+                    void* stream);
+
+/* Autotuner of the hop kernel for nrhs right-hand sides (2 <= nrhs <= max_rhs): times each
+ * work-item mapping (one rhs per work-item; 4 rhs sharing link loads within a wavefront;
+ * 4 rhs on the 4 wavefronts of a workgroup) on this context's lattice for the full
+ * operator and the even-odd hop in FP64 and FP32, and keeps the fastest for every later
+ * call with that nrhs (apply_M, apply_W1_block, apply_Dslash_eo and the solvers).
+ * us_out (host, may be NULL): 12 floats, microseconds per launch, ordered
+ * [full f64 x3, full f32 x3, even-odd f64 x3, even-odd f32 x3]. Uses the solver workspace;
+ * synchronises. Untuned calls use the 4-rhs-per-wavefront mapping. */
+int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
+
 /* ---- solvers ------------------------------------------------------------------ */
 
 /* Solve M x = b for nrhs FP64 fields (sap layout): even-odd reduced CG on the normal
@@ -174,12 +193,13 @@ int apply_W1_block(sap_ctx* ctx, void* out, const void* in, int nrhs, int level,
 int solve_full(sap_ctx* ctx, double* x, const double* b, int nrhs, const sap_solve_opts* opts,
                sap_solve_info* info, void* stream);
 
-/* Solve W_level x = b on every selected block as an independent system (all blocks
- * and all nrhs fields batched in each kernel launch). Sites outside the selected
- * colour are set to zero in x. info: host array of nblocks(level)*nrhs entries
- * ordered [rhs][block] (entries of unselected blocks are zeroed). Synchronises. */
+/* Solve W_level x = b on every selected block as an independent system (all selected
+ * blocks and all nrhs fields batched in each kernel launch). block >= 0 selects that
+ * single block (color is then ignored), block = -1 all blocks of the colour. Sites
+ * outside the selection are set to zero in x. info: host array of nblocks(level)*nrhs
+ * entries ordered [rhs][block] (entries of unselected blocks are zeroed). Synchronises. */
 int solve_blocks(sap_ctx* ctx, double* x, const double* b, int nrhs, int level,
-                 sap_color color, const sap_solve_opts* opts, sap_solve_info* info,
+                 sap_color color, int block, const sap_solve_opts* opts, sap_solve_info* info,
                  void* stream);
 
 /* ---- forces -------------------------------------------------------------------- */

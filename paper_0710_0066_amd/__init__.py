@@ -87,8 +87,9 @@ _SIGS = {
     "sap_unpack_momenta": ([_P, _P, _P, _P], _I),
     "apply_M": ([_P, _P, _P, _I, _I, _P], _I),
     "apply_W1_block": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
+    "apply_Dslash_eo": ([_P, _P, _P, _I, _I, _I, _P], _I),
     "solve_full": ([_P, _P, _P, _I, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
-    "solve_blocks": ([_P, _P, _P, _I, _I, _I, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
+    "solve_blocks": ([_P, _P, _P, _I, _I, _I, _I, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
     "block_pf_force": ([_P, _P, _D, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
     "schwarz_boundary_force": ([_P, _P, _D, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
     "gauge_force": ([_P, _P, _D, _D, _P, _P], _I),
@@ -96,6 +97,7 @@ _SIGS = {
     "schwarz_action": ([_P, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
     "sap_update_links": ([_P, _P, _D, _P], _I),
     "sap_plaquette": ([_P, _P, _P], _I),
+    "sap_tune": ([_P, _I, _P, _P], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
 }
 for _name, (_args, _ret) in _SIGS.items():
@@ -147,6 +149,10 @@ def apply_W1_block(ctx, out, inp, nrhs, level=1, block=-1, color=SAP_ALL, prec=S
                                         prec, _stream()))
 
 
+def apply_Dslash_eo(ctx, out, inp, nrhs, parity, prec):
+    _check(ctx.ptr, _lib.apply_Dslash_eo(ctx.ptr, _ptr(out), _ptr(inp), nrhs, parity, prec, _stream()))
+
+
 def solve_full(ctx, x, b, nrhs, opts):
     info = (sap_solve_info * nrhs)()
     rc = _lib.solve_full(ctx.ptr, _ptr(x), _ptr(b), nrhs, ctypes.byref(opts), info, _stream())
@@ -154,11 +160,11 @@ def solve_full(ctx, x, b, nrhs, opts):
     return list(info)
 
 
-def solve_blocks(ctx, x, b, nrhs, level, color, opts):
+def solve_blocks(ctx, x, b, nrhs, level, color, opts, block=-1):
     nb = ctx.nblocks(level)
     info = (sap_solve_info * (nb * nrhs))()
-    rc = _lib.solve_blocks(ctx.ptr, _ptr(x), _ptr(b), nrhs, level, color, ctypes.byref(opts), info,
-                           _stream())
+    rc = _lib.solve_blocks(ctx.ptr, _ptr(x), _ptr(b), nrhs, level, color, block, ctypes.byref(opts),
+                           info, _stream())
     _check(ctx.ptr, rc, info)
     return list(info)
 
@@ -202,6 +208,15 @@ def sap_plaquette(ctx):
     v = ctypes.c_double(0.0)
     _check(ctx.ptr, _lib.sap_plaquette(ctx.ptr, ctypes.byref(v), _stream()))
     return v.value
+
+
+def sap_tune(ctx, nrhs):
+    """Tune the hop mapping for nrhs; returns microseconds per launch per variant."""
+    us = (ctypes.c_float * 12)()
+    _check(ctx.ptr, _lib.sap_tune(ctx.ptr, nrhs, us, _stream()))
+    names = ["full_f64", "full_f32", "eo_f64", "eo_f32"]
+    maps = ["site", "lane4", "wave4"]
+    return {n: {m: us[3 * i + k] for k, m in enumerate(maps)} for i, n in enumerate(names)}
 
 
 def hmc_params(beta, tau, n_outer, n_inner, p0, xi1, xi2, u_metropolis, force_solve, action_solve,

@@ -85,6 +85,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   c->U32 = nullptr;
   c->solver = nullptr;
   c->forces = nullptr;
+  std::memset(c->hop_map, -1, sizeof(c->hop_map));
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return sap_fail(nullptr, SAP_E_HIP, "hipGetDevice failed (no HIP device?)");
@@ -204,7 +205,39 @@ static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, i
   A.b = R(-ctx->geom.kappa);
   A.g5_in = 0;
   A.g5_out = 0;
+  A.map = hop_map_for(ctx, true, sizeof(R) == 4, nrhs);
   launch_hop<R>(A, s);
+}
+
+template <class R>
+static void eo_hop(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, hipStream_t s) {
+  HopArgs<R> A;
+  typedef typename vec2<R>::type V2;
+  const long long Vhp = ctx->Vhp;
+  A.out = {(V2*)out, 24 * Vhp, 12 * Vhp};
+  A.in = {(V2*)in, 24 * Vhp, 12 * Vhp};
+  A.x = {nullptr, 0, 0};
+  A.U = (const V2*)(sizeof(R) == 8 ? (const void*)ctx->U64 : (const void*)ctx->U32);
+  A.g = ctx->g;
+  A.nrhs = nrhs;
+  A.parity_out = parity;
+  A.lb = 0;
+  A.slb = 0;
+  A.colour = 0;
+  A.block = -1;
+  A.a = R(0);
+  A.b = R(1);
+  A.g5_in = 0;
+  A.g5_out = 0;
+  A.map = hop_map_for(ctx, false, sizeof(R) == 4, nrhs);
+  launch_hop<R>(A, s);
+}
+
+int eo_hop_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, sap_prec prec, hipStream_t s) {
+  if (prec == SAP_F64) eo_hop<double>(ctx, out, in, nrhs, parity, s);
+  else eo_hop<float>(ctx, out, in, nrhs, parity, s);
+  SAP_HIP_CHECK(ctx, hipGetLastError());
+  return SAP_OK;
 }
 
 int apply_op_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, int colour, int block,
@@ -225,6 +258,16 @@ int apply_M(sap_ctx* ctx, void* out, const void* in, int nrhs, sap_prec prec, vo
   if (out == in) return sap_fail(ctx, SAP_E_ARG, "out and in must not alias");
   if (!ctx->have_gauge) return sap_fail(ctx, SAP_E_STATE, "no gauge field set");
   return apply_op_any(ctx, out, in, nrhs, 0, 0, -1, prec, (hipStream_t)stream);
+}
+
+int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, sap_prec prec,
+                    void* stream) {
+  int rc = check_fields(ctx, out, in, nrhs, prec);
+  if (rc) return rc;
+  if (out == in) return sap_fail(ctx, SAP_E_ARG, "out and in must not alias");
+  if (parity != 0 && parity != 1) return sap_fail(ctx, SAP_E_ARG, "parity must be 0 or 1");
+  if (!ctx->have_gauge) return sap_fail(ctx, SAP_E_STATE, "no gauge field set");
+  return eo_hop_any(ctx, out, in, nrhs, parity, prec, (hipStream_t)stream);
 }
 
 int apply_W1_block(sap_ctx* ctx, void* out, const void* in, int nrhs, int level, int block,

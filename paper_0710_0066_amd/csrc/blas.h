@@ -7,7 +7,8 @@ namespace sap {
 constexpr int CHUNK = 1024;   // sites of one parity per workgroup in the BLAS kernels
 
 // Systems of a batched solve: nblk x0 blocks of Vb sites per parity (nblk = 1, Vb = Vh
-// for the full lattice), colour selection of the blocks (0 all, 1 black, 2 white).
+// for the full lattice), selection of the blocks (block_selected code: 0 all, 1 black,
+// 2 white, 3 + b block b).
 struct SysGrid {
   int nblk;
   long long Vb;

@@ -41,7 +41,7 @@ __device__ __forceinline__ Tile tile_of(const SysGrid& G) {
   t.rhs = blockIdx.z;
   t.blk = blockIdx.y;
   t.sys = (long long)t.rhs * G.nblk + t.blk;
-  t.selected = (G.colour == 0) || ((G.colour == 1) == ((t.blk & 1) == 1));
+  t.selected = block_selected(G.colour, t.blk);
   t.j0 = (long long)t.blk * G.Vb + (long long)blockIdx.x * CHUNK;
   t.j1 = (long long)t.blk * G.Vb + G.Vb;
   if (t.j0 + CHUNK < t.j1) t.j1 = t.j0 + CHUNK;

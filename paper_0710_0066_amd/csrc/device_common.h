@@ -222,6 +222,13 @@ __device__ __forceinline__ void accum_recon(int mu, bool plus, const cx<R> g[2][
   }
 }
 
+// Block selection code used by the block-restricted kernels: 0 all blocks, 1 black (odd
+// block index), 2 white (even), 3 + b the single block b.
+__device__ __host__ __forceinline__ bool block_selected(int sel, int blk) {
+  if (sel >= 3) return blk == sel - 3;
+  return sel == 0 || ((sel == 1) == ((blk & 1) == 1));
+}
+
 // XCD-aware workgroup order: the hardware deals consecutive workgroup ids round-robin
 // to the 8 XCDs; when the grid is a multiple of 8, renumber so that each XCD walks a
 // contiguous range of logical workgroups (neighbouring tiles share that XCD's L2).

@@ -5,12 +5,11 @@
 //   out = a * x + b * D(in)
 // on both parities (M = 1 - kappa D) or on one parity (the even-odd half hops).
 //
-// Bandwidth-bound 8-point gather: one work-item per (output site, rhs), structure-of-
-// arrays complex loads that coalesce across the 64-lane wavefront, half-spinor
-// projection before the SU(3) product (2 colour vectors per link instead of 4), FP64 or
-// FP32 arithmetic matching the storage. Workgroups are numbered rhs-fastest and
-// renumbered per XCD, so the right-hand sides of one site tile run back to back on one
-// XCD and re-read the tile's links from that XCD's L2.
+// Bandwidth-bound 8-point gather: one work-item per (output site, rhs), tiled
+// structure-of-arrays complex loads that coalesce across the 64-lane wavefront,
+// half-spinor projection before the SU(3) product (2 colour vectors per link instead of
+// 4), FP64 or FP32 arithmetic matching the storage. Workgroups are numbered rhs-fastest
+// and renumbered per XCD; with several rhs four of them share each link load.
 #include "internal.h"
 
 namespace sap {
@@ -36,21 +35,58 @@ __device__ __forceinline__ void load_link(const typename vec2<R>::type* U, long 
   for (int e = 0; e < 9; ++e) m[e] = ld<R>(p + e * TILE);
 }
 
-template <class R, bool FULL>
+// Work-item mappings (MAP):
+//  SITE  one work-item per (site, rhs); a workgroup holds 256 sites of one parity (half
+//        hop) or 128 sites of each parity (full operator), workgroups rhs-fastest.
+//  LANE4 a wavefront holds 16 sites x 4 rhs: the four lanes of a site read the same link
+//        address in the same load instruction, so the link is fetched once for 4 rhs; a
+//        workgroup holds 64 sites (half hop) or 32 sites of each parity (full).
+//  WAVE4 a workgroup holds 64 sites (half hop; full: 32 sites of each parity) x 4 rhs with
+//        one rhs per wavefront: the wavefronts of a workgroup load the same links back to
+//        back through the CU's L1, and each keeps 64 consecutive sites for neighbour reuse.
+template <class R, bool FULL, int MAP>
 __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
   typedef typename vec2<R>::type V2;
   const long long nwg = gridDim.x;
   const long long w = xcd_logical_block(blockIdx.x, nwg);
-  const int rhs = (int)(w % A.nrhs);
-  const long long chunk = w / A.nrhs;
-  int p;
+  int p, rhs;
   long long j;
-  if (FULL) {
-    p = threadIdx.x >> 7;
-    j = chunk * 128 + (threadIdx.x & 127);
+  if (MAP == HOP_MAP_SITE) {
+    rhs = (int)(w % A.nrhs);
+    const long long chunk = w / A.nrhs;
+    if (FULL) {
+      p = threadIdx.x >> 7;
+      j = chunk * 128 + (threadIdx.x & 127);
+    } else {
+      p = A.parity_out;
+      j = chunk * 256 + threadIdx.x;
+    }
+  } else if (MAP == HOP_MAP_LANE4) {
+    const int ngroups = (A.nrhs + 3) >> 2;
+    const long long chunk = w / ngroups;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    rhs = (int)(w % ngroups) * 4 + (lane >> 4);
+    if (rhs >= A.nrhs) return;
+    if (FULL) {
+      p = wave >> 1;
+      j = chunk * 32 + (wave & 1) * 16 + (lane & 15);
+    } else {
+      p = A.parity_out;
+      j = chunk * 64 + wave * 16 + (lane & 15);
+    }
   } else {
-    p = A.parity_out;
-    j = chunk * 256 + threadIdx.x;
+    const int ngroups = (A.nrhs + 3) >> 2;
+    const long long chunk = w / ngroups;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    rhs = (int)(w % ngroups) * 4 + wave;
+    if (rhs >= A.nrhs) return;
+    if (FULL) {
+      p = lane >> 5;
+      j = chunk * 32 + (lane & 31);
+    } else {
+      p = A.parity_out;
+      j = chunk * 64 + lane;
+    }
   }
   const Geo& g = A.g;
   if (j >= g.Vh) return;
@@ -148,13 +184,21 @@ static inline long long round8(long long n) { return (n + 7) / 8 * 8; }
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t st) {
   const bool full = A.parity_out < 0;
-  const long long per = full ? 128 : 256;
+  const int map = A.nrhs > 1 ? A.map : HOP_MAP_SITE;
+  const bool grouped = map != HOP_MAP_SITE;
+  const long long per = grouped ? (full ? 32 : 64) : (full ? 128 : 256);
+  const long long groups = grouped ? (A.nrhs + 3) / 4 : A.nrhs;
   const long long chunks = (A.g.Vh + per - 1) / per;
-  const long long nwg = round8(chunks * A.nrhs);
-  if (full)
-    hipLaunchKernelGGL((hop_kernel<R, true>), dim3((unsigned)nwg), dim3(256), 0, st, A);
-  else
-    hipLaunchKernelGGL((hop_kernel<R, false>), dim3((unsigned)nwg), dim3(256), 0, st, A);
+  const dim3 grid((unsigned)round8(chunks * groups)), blk(256);
+  if (full) {
+    if (map == HOP_MAP_LANE4) hipLaunchKernelGGL((hop_kernel<R, true, HOP_MAP_LANE4>), grid, blk, 0, st, A);
+    else if (map == HOP_MAP_WAVE4) hipLaunchKernelGGL((hop_kernel<R, true, HOP_MAP_WAVE4>), grid, blk, 0, st, A);
+    else hipLaunchKernelGGL((hop_kernel<R, true, HOP_MAP_SITE>), grid, blk, 0, st, A);
+  } else {
+    if (map == HOP_MAP_LANE4) hipLaunchKernelGGL((hop_kernel<R, false, HOP_MAP_LANE4>), grid, blk, 0, st, A);
+    else if (map == HOP_MAP_WAVE4) hipLaunchKernelGGL((hop_kernel<R, false, HOP_MAP_WAVE4>), grid, blk, 0, st, A);
+    else hipLaunchKernelGGL((hop_kernel<R, false, HOP_MAP_SITE>), grid, blk, 0, st, A);
+  }
 }
 
 template void launch_hop<double>(const HopArgs<double>&, hipStream_t);

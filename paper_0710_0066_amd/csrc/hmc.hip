@@ -91,6 +91,7 @@ void hop_M_sel(sap_ctx* c, double2* out, const double2* in, int colour, hipStrea
   A.a = 1.0;
   A.b = -c->geom.kappa;
   A.g5_in = A.g5_out = 0;
+  A.map = HOP_MAP_SITE;
   launch_hop<double>(A, s);
 }
 
@@ -381,7 +382,7 @@ int hmc_trajectory(sap_ctx* c, double* U, const sap_hmc_params* P, sap_hmc_info*
   A.x = A.in;
   A.U = c->U64; A.g = c->g; A.nrhs = 1; A.parity_out = -1;
   A.lb = c->geom.l0; A.slb = c->geom.l0; A.colour = 0; A.block = -1;
-  A.a = 1.0; A.b = -c->geom.kappa; A.g5_in = A.g5_out = 0;
+  A.a = 1.0; A.b = -c->geom.kappa; A.g5_in = A.g5_out = 0; A.map = HOP_MAP_SITE;
   launch_hop<double>(A, s);
   if ((rc = sap_pack_spinor(c, w->f[0], P->xi2, 1, SAP_F64, stream))) return rc;
   if ((rc = heat_bath(c, chi, w->f[0], &P->action_solve, s))) goto fail;

@@ -33,7 +33,14 @@ template <class R> struct HopArgs {
   int block;               // >= 0: only this block (colour ignored)
   R a, b;
   int g5_in, g5_out;       // multiply the hop input / the hop result by gamma_5
+  int map;                 // work-item mapping (HOP_MAP_*), nrhs > 1 only
 };
+
+// Work-item mappings of the hop kernel for several right-hand sides.
+enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fastest
+       HOP_MAP_LANE4 = 1,   // wavefront = 16 sites x 4 rhs: four lanes share each link load
+       HOP_MAP_WAVE4 = 2,   // workgroup = 64 sites x 4 rhs, one rhs per wavefront
+       HOP_NMAP = 3 };
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
 
@@ -73,7 +80,16 @@ struct sap_ctx {
   std::string err;
   void* solver;   // solver workspace (solver.hip)
   void* forces;   // force / trajectory workspace (hmc.hip)
+  // tuned hop mapping per [full operator?][precision][nrhs] (-1: not tuned)
+  signed char hop_map[2][2][65];
 };
+
+// mapping used for a hop launch: the tuned one, else LANE4 for nrhs > 1
+inline int hop_map_for(const sap_ctx* c, bool full, int prec_is_f32, int nrhs) {
+  if (nrhs <= 1) return sap::HOP_MAP_SITE;
+  const int m = c->hop_map[full ? 1 : 0][prec_is_f32][nrhs > 64 ? 64 : nrhs];
+  return m >= 0 ? m : sap::HOP_MAP_LANE4;
+}
 
 // error helpers (api.hip)
 int sap_fail(sap_ctx* ctx, int code, const std::string& msg);

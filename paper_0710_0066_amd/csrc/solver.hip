@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 #include "blas.h"
 
 using namespace sap;
@@ -32,13 +33,19 @@ struct SolverWS {
   // pinned host mirrors
   double *h_rnorm2, *h_bnorm2;
   int *h_flags, *h_iters, *h_selected;
+  // captured inner-loop graphs (ITERS_PER_GRAPH CG iterations each), replayed on the
+  // caller's stream; captured on a private non-blocking stream of default priority
+  hipStream_t cap;
+  struct G { int nrhs, lb, sel, f32; hipGraphExec_t exec; };
+  std::vector<G> graphs;
 };
+
+constexpr int ITERS_PER_GRAPH = 8;
 
 static SolverWS* ws_of(sap_ctx* c) { return (SolverWS*)c->solver; }
 
 extern "C" int sap_solver_create(sap_ctx* c) {
-  SolverWS* w = new SolverWS();
-  std::memset(w, 0, sizeof(*w));
+  SolverWS* w = new SolverWS();   // value-initialised: every pointer starts null
   c->solver = w;
   const int minlb = c->geom.l0_sub > 0 ? c->geom.l0_sub : c->geom.l0;
   w->max_rhs = c->geom.max_rhs;
@@ -66,7 +73,14 @@ extern "C" int sap_solver_create(sap_ctx* c) {
        hipHostMalloc((void**)&w->h_iters, ns * 4, 0) == hipSuccess &&
        hipHostMalloc((void**)&w->h_selected, ns * 4, 0) == hipSuccess;
   if (!ok) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the solver workspace");
+  if (hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess)
+    return sap_fail(c, SAP_E_HIP, "cannot create the capture stream");
   return SAP_OK;
+}
+
+static void drop_graphs(SolverWS* w) {
+  for (auto& g : w->graphs) (void)hipGraphExecDestroy(g.exec);
+  w->graphs.clear();
 }
 
 extern "C" void sap_solver_destroy(sap_ctx* c) {
@@ -80,6 +94,8 @@ extern "C" void sap_solver_destroy(sap_ctx* c) {
   void* host[] = {w->h_rnorm2, w->h_bnorm2, w->h_flags, w->h_iters, w->h_selected};
   for (void* p : host)
     if (p) (void)hipHostFree(p);
+  drop_graphs(w);
+  if (w->cap) (void)hipStreamDestroy(w->cap);
   delete w;
   c->solver = nullptr;
 }
@@ -109,12 +125,13 @@ void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int p
   A.parity_out = parity_out;
   A.lb = lb;
   A.slb = lb;
-  A.colour = colour;
-  A.block = -1;
+  A.colour = colour < 3 ? colour : 0;
+  A.block = colour < 3 ? -1 : colour - 3;
   A.a = a;
   A.b = b;
   A.g5_in = g5i;
   A.g5_out = g5o;
+  A.map = hop_map_for(c, parity_out < 0, sizeof(R) == 4, nrhs);
   launch_hop<R>(A, st);
 }
 
@@ -145,7 +162,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
   // selection of systems
   for (int r = 0; r < nrhs; ++r)
     for (int k = 0; k < G.nblk; ++k)
-      w->h_selected[r * G.nblk + k] = (G.colour == 0) || ((G.colour == 1) == ((k & 1) == 1));
+      w->h_selected[r * G.nblk + k] = block_selected(G.colour, k);
   SAP_HIP_CHECK(c, hipMemcpyAsync(w->selected, w->h_selected, nsys * 4, hipMemcpyHostToDevice, st));
   SAP_HIP_CHECK(c, hipMemsetAsync(w->iters, 0, nsys * 4, st));
   SAP_HIP_CHECK(c, hipMemsetAsync(x, 0, fullb, st));
@@ -159,7 +176,6 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
 
   const double tol = o->tol;
   const double inner_tol = (sizeof(R) == 8 && o->inner_tol <= 0) ? tol : o->inner_tol;
-  const int check_every = 8;
   long long total_iters = 0;
   int outer = 0;
   int status = SAP_OK;
@@ -199,33 +215,55 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     SAP_HIP_CHECK(c, hipMemcpyAsync(w->p, w->r, fullb / 2 / (sizeof(R) == 8 ? 1 : 2),
                                     hipMemcpyDeviceToDevice, st));
     SAP_HIP_CHECK(c, hipGetLastError());
-    for (int it = 0;; ++it) {
-      if (it % check_every == 0) {
-        SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 8, hipMemcpyDeviceToHost, st));
-        SAP_HIP_CHECK(c, hipStreamSynchronize(st));
-        if (w->h_flags[0]) return sap_fail(c, SAP_E_NONFINITE, "non-finite value in the inner solve");
-        if (w->h_flags[1] == 0) break;
-        if (total_iters >= o->max_iter) break;
-      }
+    // one CG iteration on all systems (no host interaction; scalars stay on the device)
+    auto iterate = [&](hipStream_t q) {
       // q = M_hat p
-      hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, st);
-      hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, st);
-      blas_norm2<R>(G, nrhs, Q, 1, w->partA, st);
-      fin_alpha(SC, nsys, G.nchunk, w->partA, st);
+      hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+      hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
+      blas_norm2<R>(G, nrhs, Q, 1, w->partA, q);
+      fin_alpha(SC, nsys, G.nchunk, w->partA, q);
       // x += alpha p, s -= alpha q
-      blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, st);
+      blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, q);
       // r = M_hat^dagger s
-      hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, st);
-      hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, st);
-      blas_norm2<R>(G, nrhs, Rr, 1, w->partC, st);
-      fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, st);
-      blas_xpay<R>(G, nrhs, P, Rr, w->beta, st);
-      ++total_iters;
+      hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, q);
+      hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, q);
+      blas_norm2<R>(G, nrhs, Rr, 1, w->partC, q);
+      fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, q);
+      blas_xpay<R>(G, nrhs, P, Rr, w->beta, q);
+    };
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : w->graphs)
+      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.f32 == (int)(sizeof(R) == 4)) exec = g.exec;
+    if (!exec) {
+      hipGraph_t graph;
+      if (hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        for (int k = 0; k < ITERS_PER_GRAPH; ++k) iterate(w->cap);
+        if (hipStreamEndCapture(w->cap, &graph) == hipSuccess) {
+          if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
+          (void)hipGraphDestroy(graph);
+        }
+      }
+      (void)hipGetLastError();
+      if (exec) w->graphs.push_back({nrhs, lb, colour, (int)(sizeof(R) == 4), exec});
+    }
+    for (;;) {
+      SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 8, hipMemcpyDeviceToHost, st));
+      SAP_HIP_CHECK(c, hipStreamSynchronize(st));
+      if (w->h_flags[0]) return sap_fail(c, SAP_E_NONFINITE, "non-finite value in the inner solve");
+      if (w->h_flags[1] == 0) break;
+      if (total_iters >= o->max_iter) break;
+      if (exec) {
+        SAP_HIP_CHECK(c, hipGraphLaunch(exec, st));
+      } else {
+        for (int k = 0; k < ITERS_PER_GRAPH; ++k) iterate(st);
+      }
+      total_iters += ITERS_PER_GRAPH;
     }
     // e_o = r_o + k D_oe e_e ; x += e ; r = b - A x (FP64)
     hop<R>(c, U, E, Ee, RIN, 1, nrhs, lb, colour, R(1), kR, 0, 0, st);
     blas_add_mixed<R>(G, nrhs, X, E, st);
-    int rc = apply_op_any(c, w->ax, x, nrhs, lb, colour, -1, SAP_F64, st);
+    int rc = apply_op_any(c, w->ax, x, nrhs, lb, colour < 3 ? colour : 0, colour < 3 ? -1 : colour - 3,
+                          SAP_F64, st);
     if (rc) return rc;
     blas_resid(G, nrhs, R64, B, AX, w->partA, st);
     fin_sum(nsys, G.nchunk, w->partA, w->rnorm2, st);
@@ -243,6 +281,69 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     }
   }
   return status;
+}
+
+// ---- hop-mapping autotuner -------------------------------------------------------------
+template <class R>
+static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_out) {
+  SolverWS* w = ws_of(c);
+  typedef typename vec2<R>::type V2;
+  const long long Vhp = c->Vhp;
+  HopArgs<R> A;
+  A.out = {(V2*)w->ax, 24 * Vhp, 12 * Vhp};
+  A.in = {(V2*)w->r64, 24 * Vhp, 12 * Vhp};
+  A.x = full ? A.in : Field<R>{nullptr, 0, 0};
+  A.U = (const V2*)(sizeof(R) == 8 ? (const void*)c->U64 : (const void*)c->U32);
+  A.g = c->g;
+  A.nrhs = nrhs;
+  A.parity_out = full ? -1 : 0;
+  A.lb = A.slb = 0;
+  A.colour = 0;
+  A.block = -1;
+  A.a = R(1);
+  A.b = R(-c->geom.kappa);
+  A.g5_in = A.g5_out = 0;
+  hipEvent_t e0, e1;
+  SAP_HIP_CHECK(c, hipEventCreate(&e0));
+  SAP_HIP_CHECK(c, hipEventCreate(&e1));
+  int best = HOP_MAP_SITE;
+  float best_ms = 1e30f;
+  for (int m = 0; m < HOP_NMAP; ++m) {
+    A.map = m;
+    for (int k = 0; k < 2; ++k) launch_hop<R>(A, st);
+    SAP_HIP_CHECK(c, hipEventRecord(e0, st));
+    const int reps = 6;
+    for (int k = 0; k < reps; ++k) launch_hop<R>(A, st);
+    SAP_HIP_CHECK(c, hipEventRecord(e1, st));
+    SAP_HIP_CHECK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    SAP_HIP_CHECK(c, hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    if (us_out) us_out[m] = ms * 1e3f;
+    if (ms < best_ms) { best_ms = ms; best = m; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->hop_map[full ? 1 : 0][sizeof(R) == 4 ? 1 : 0][nrhs] = (signed char)best;
+  return SAP_OK;
+}
+
+extern "C" int sap_tune(sap_ctx* c, int nrhs, float* us_out, void* stream) {
+  if (c && c->solver) drop_graphs(ws_of(c));   // captured graphs hold the old mappings
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (nrhs < 2 || nrhs > c->geom.max_rhs) return sap_fail(c, SAP_E_ARG, "nrhs must be in [2, max_rhs]");
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  hipStream_t st = (hipStream_t)stream;
+  SolverWS* w = ws_of(c);
+  const size_t fb = (size_t)24 * c->Vhp * nrhs * sizeof(double2);
+  SAP_HIP_CHECK(c, hipMemsetAsync(w->r64, 0, fb, st));
+  SAP_HIP_CHECK(c, hipMemsetAsync(w->ax, 0, fb, st));
+  int rc;
+  if ((rc = tune_one<double>(c, true, nrhs, st, us_out ? us_out + 0 : nullptr))) return rc;
+  if ((rc = tune_one<float>(c, true, nrhs, st, us_out ? us_out + 3 : nullptr))) return rc;
+  if ((rc = tune_one<double>(c, false, nrhs, st, us_out ? us_out + 6 : nullptr))) return rc;
+  if ((rc = tune_one<float>(c, false, nrhs, st, us_out ? us_out + 9 : nullptr))) return rc;
+  return SAP_OK;
 }
 
 static int check_opts(sap_ctx* c, const sap_solve_opts* o) {
@@ -275,7 +376,7 @@ int solve_full(sap_ctx* c, double* x, const double* b, int nrhs, const sap_solve
   return sap_solve_any(c, x, b, nrhs, 0, 0, o, info, (hipStream_t)stream);
 }
 
-int solve_blocks(sap_ctx* c, double* x, const double* b, int nrhs, int level, sap_color color,
+int solve_blocks(sap_ctx* c, double* x, const double* b, int nrhs, int level, sap_color color, int block,
                  const sap_solve_opts* o, sap_solve_info* info, void* stream) {
   if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
   if (!x || !b) return sap_fail(c, SAP_E_ARG, "x or b is NULL");
@@ -287,10 +388,12 @@ int solve_blocks(sap_ctx* c, double* x, const double* b, int nrhs, int level, sa
   else return sap_fail(c, SAP_E_ARG, "level must be 1, or 2 with l0_sub set");
   if (color != SAP_ALL && color != SAP_BLACK && color != SAP_WHITE)
     return sap_fail(c, SAP_E_ARG, "unknown colour");
+  if (block < -1 || block >= c->geom.L[0] / lb) return sap_fail(c, SAP_E_ARG, "block out of range");
   int rc = check_opts(c, o);
   if (rc) return rc;
   if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
-  return sap_solve_any(c, x, b, nrhs, lb, (int)color, o, info, (hipStream_t)stream);
+  const int sel = block >= 0 ? 3 + block : (int)color;
+  return sap_solve_any(c, x, b, nrhs, lb, sel, o, info, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -71,6 +71,29 @@ def test_apply_W_matches_oracle(gu, L, l0, l0_sub, k):
                 assert err <= tol, (level, block, color, prec, err)
 
 
+@pytest.mark.parametrize("L,l0,l0_sub,k", SHAPES[:3])
+@pytest.mark.parametrize("nrhs", [1, 5])
+def test_apply_Dslash_eo_matches_oracle(gu, L, l0, l0_sub, k, nrhs):
+    """D_eo / D_oe: the hop of eq. 2 restricted to one output parity, reading the other."""
+    import paper_0710_0066_amd as sap
+    print(f"apply_Dslash_eo L={L} nrhs={nrhs}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1011)
+    psi = synth.gaussian_spinor(L, 2011, nrhs=nrhs)
+    par = lattice.parity(L)
+    ctx = gu.make_ctx(L, l0, k, U, l0_sub, max_rhs=nrhs)
+    for parity in (0, 1):
+        m_out = lattice.site_mask(L, par == parity)
+        ref = dirac.hop(U, psi * lattice.site_mask(L, par != parity)) * m_out
+        for prec, tol in [(sap.SAP_F64, F64_TOL), (sap.SAP_F32, F32_TOL)]:
+            fin = gu.to_sap(ctx, psi, nrhs, prec)
+            fout = gu.to_sap(ctx, psi, nrhs, prec)      # the other parity must stay as it was
+            sap.apply_Dslash_eo(ctx, fout, fin, nrhs, parity, prec)
+            got = gu.from_sap(ctx, fout, nrhs, psi.shape, prec)
+            keep = np.broadcast_to(~m_out, got.shape)
+            assert np.array_equal(got[keep], gu.from_sap(ctx, fin, nrhs, psi.shape, prec)[keep])
+            assert gu.rel_err(got * m_out, ref) <= tol, (parity, prec)
+
+
 @pytest.mark.parametrize("name", ["plain_16x16x16x32", "batched_24x24x24x48"])
 def test_apply_M_and_W_full_size(gu, name):
     """Full-size workloads in the launch configuration the benchmark times: every

@@ -89,6 +89,29 @@ def test_solve_blocks_matches_oracle(gu, level, color):
         assert np.max(np.abs(x - x_ref)) / np.max(np.abs(x_ref)) <= 1e-7
 
 
+def test_solve_blocks_single_block(gu):
+    """block >= 0 solves that block alone; every other site of x is zero."""
+    import paper_0710_0066_amd as sap
+    L, l0, k = (16, 4, 2, 4), 4, 0.15
+    U = synth.gauge_field(L, 0.5, 1008)
+    b = synth.gaussian_spinor(L, 2008, nrhs=2)
+    ctx = gu.make_ctx(L, l0, k, U, 2, max_rhs=2)
+    fb = gu.to_sap(ctx, b, 2)
+    fx = ctx.new_field(2)
+    for level, lb, blk in [(1, 4, 2), (2, 2, 7)]:
+        m = lattice.site_mask(L, lattice.single_block_mask(L, lb, blk))
+        info = sap.solve_blocks(ctx, fx, fb, 2, level, sap.SAP_ALL, _opts(sap, sap.SAP_F32), block=blk)
+        x = gu.from_sap(ctx, fx, 2, b.shape)
+        assert np.all(x[~np.broadcast_to(m, x.shape)] == 0)
+        assert np.all(_relres(U, x, b, k, lb, m) <= 1e-10)
+        nb = L[0] // lb
+        for r in range(2):
+            for kb in range(nb):
+                assert (info[r * nb + kb].iters > 0) == (kb == blk)
+    with pytest.raises(sap.SapError):
+        sap.solve_blocks(ctx, fx, fb, 2, 1, sap.SAP_ALL, _opts(sap, sap.SAP_F32), block=4)
+
+
 def test_solve_full_16x16x16x32(gu):
     """The 16^3x32 workload (kappa = 0.1575): mixed-precision full solve, residual
     recomputed by the oracle."""
