@@ -245,8 +245,7 @@ def main():
         return lambda s: sap.apply_M(ctx, fout, fin, 1, PREC[prec])
 
     if args.only_dslash:       # one operator only, for profiler runs
-        if args.nrhs > 1:
-            sap.sap_tune(ctx, args.nrhs)
+        sap.sap_tune(ctx, args.nrhs if args.op == "eo" else 1)
         fn = eo(args.prec, args.nrhs) if args.op == "eo" else full(args.prec)
         ms = time_op(sap, torch, fn, args.steps, args.warmup)
         print(f"[bench] {args.op} {args.prec} nrhs={args.nrhs if args.op == 'eo' else 1}: "
@@ -256,7 +255,7 @@ def main():
         return
 
     print("[bench] tuning the hop mapping", file=sys.stderr, flush=True)
-    tuning = sap.sap_tune(ctx, nrhs)
+    tuning = {"nrhs_%d" % n: sap.sap_tune(ctx, n) for n in (1, nrhs)}
     ms = time_op(sap, torch, eo("f32", nrhs), args.steps, args.warmup)
     gbs = eo_bytes(V, "f32", nrhs) / (ms * 1e-3) / 1e9
     print(f"[bench] D_eo f32 {nrhs} rhs: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s", file=sys.stderr, flush=True)
@@ -283,7 +282,8 @@ def main():
                         "roofline": roofline(g, name)}
         print(f"[bench] {name}: {t * 1e3:.1f} us, {g:.0f} GB/s", file=sys.stderr, flush=True)
     result["other_operators"] = others
-    result["hop_tuning_us"] = {k: {m: round(v, 1) for m, v in d.items()} for k, d in tuning.items()}
+    result["hop_tuning_us"] = {n: {k: {m: round(v, 1) for m, v in d.items()} for k, d in t.items()}
+                               for n, t in tuning.items()}
     fields.clear()
     result["hbm_probe"] = hbm_probe(torch)
     if not args.skip_solve:

@@ -172,15 +172,26 @@ int apply_W1_block(sap_ctx* ctx, void* out, const void* in, int nrhs, int level,
 int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, sap_prec prec,
                     void* stream);
 
-/* Autotuner of the hop kernel for nrhs right-hand sides (2 <= nrhs <= max_rhs): times each
+/* Autotuner of the hop kernel for nrhs right-hand sides (1 <= nrhs <= max_rhs): times each
  * work-item mapping (one rhs per work-item; 4 rhs sharing link loads within a wavefront;
- * 4 rhs on the 4 wavefronts of a workgroup) on this context's lattice for the full
- * operator and the even-odd hop in FP64 and FP32, and keeps the fastest for every later
- * call with that nrhs (apply_M, apply_W1_block, apply_Dslash_eo and the solvers).
- * us_out (host, may be NULL): 12 floats, microseconds per launch, ordered
- * [full f64 x3, full f32 x3, even-odd f64 x3, even-odd f32 x3]. Uses the solver workspace;
- * synchronises. Untuned calls use the 4-rhs-per-wavefront mapping. */
+ * 4 rhs on the 4 wavefronts of a workgroup; for the even-odd hop also an x0-streaming
+ * kernel that keeps time neighbours in registers and stages each input slice in LDS) on
+ * this context's lattice for the full operator and the even-odd hop in FP64 and FP32,
+ * and keeps the fastest for every later call with that nrhs (apply_M, apply_W1_block,
+ * apply_Dslash_eo and the solvers). us_out (host, may be NULL): 16 floats, microseconds
+ * per launch (-1: not applicable), ordered [full f64 x4, full f32 x4, even-odd f64 x4,
+ * even-odd f32 x4] over the mappings [site, lane4, wave4, stream]. Uses the solver
+ * workspace; synchronises. Untuned calls use the 4-rhs-per-wavefront mapping. */
 int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
+/* (us_out holds 36 floats: 4 operator kinds x 9 mappings [site, lane4, wave4, stream,
+ *  site+sweep, lane4+sweep, wave4+sweep, reg2, reg4]; "sweep" orders the workgroups
+ *  rhs-slowest, "regN" applies each loaded link to N rhs held in registers.) */
+
+/* Set the hop mapping used for nrhs right-hand sides by hand (map: 0 site, 1 lane4,
+ * 2 wave4, 3 stream (even-odd hop only, full = 0), 4..6 = 0..2 with rhs-slowest workgroup
+ * order, 7 reg2, 8 reg4; -1 restores the default), for the full
+ * operator (full = 1) or the even-odd hop (full = 0) at precision prec. */
+int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);
 
 /* ---- solvers ------------------------------------------------------------------ */
 

@@ -98,6 +98,7 @@ _SIGS = {
     "sap_update_links": ([_P, _P, _D, _P], _I),
     "sap_plaquette": ([_P, _P, _P], _I),
     "sap_tune": ([_P, _I, _P, _P], _I),
+    "sap_set_hop_map": ([_P, _I, _I, _I, _I], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
 }
 for _name, (_args, _ret) in _SIGS.items():
@@ -212,11 +213,20 @@ def sap_plaquette(ctx):
 
 def sap_tune(ctx, nrhs):
     """Tune the hop mapping for nrhs; returns microseconds per launch per variant."""
-    us = (ctypes.c_float * 12)()
+    us = (ctypes.c_float * 36)()
     _check(ctx.ptr, _lib.sap_tune(ctx.ptr, nrhs, us, _stream()))
     names = ["full_f64", "full_f32", "eo_f64", "eo_f32"]
-    maps = ["site", "lane4", "wave4"]
-    return {n: {m: us[3 * i + k] for k, m in enumerate(maps)} for i, n in enumerate(names)}
+    maps = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4"]
+    return {n: {m: us[9 * i + k] for k, m in enumerate(maps) if us[9 * i + k] >= 0}
+            for i, n in enumerate(names)}
+
+
+HOP_MAP_SITE, HOP_MAP_LANE4, HOP_MAP_WAVE4, HOP_MAP_STREAM, HOP_SWEEP = 0, 1, 2, 3, 4
+HOP_MAP_REG2, HOP_MAP_REG4 = 7, 8
+
+
+def sap_set_hop_map(ctx, full, prec, nrhs, hop_map):
+    _check(ctx.ptr, _lib.sap_set_hop_map(ctx.ptr, int(full), prec, nrhs, hop_map))
 
 
 def hmc_params(beta, tau, n_outer, n_inner, p0, xi1, xi2, u_metropolis, force_solve, action_solve,

@@ -44,16 +44,17 @@ __device__ __forceinline__ void load_link(const typename vec2<R>::type* U, long 
 //  WAVE4 a workgroup holds 64 sites (half hop; full: 32 sites of each parity) x 4 rhs with
 //        one rhs per wavefront: the wavefronts of a workgroup load the same links back to
 //        back through the CU's L1, and each keeps 64 consecutive sites for neighbour reuse.
-template <class R, bool FULL, int MAP>
-__global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
+template <class R, bool FULL, int MAP, bool SWEEP>
+__global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A, long long nchunk) {
   typedef typename vec2<R>::type V2;
   const long long nwg = gridDim.x;
   const long long w = xcd_logical_block(blockIdx.x, nwg);
   int p, rhs;
   long long j;
   if (MAP == HOP_MAP_SITE) {
-    rhs = (int)(w % A.nrhs);
-    const long long chunk = w / A.nrhs;
+    rhs = SWEEP ? (int)(w / nchunk) : (int)(w % A.nrhs);
+    const long long chunk = SWEEP ? w % nchunk : w / A.nrhs;
+    if (rhs >= A.nrhs) return;
     if (FULL) {
       p = threadIdx.x >> 7;
       j = chunk * 128 + (threadIdx.x & 127);
@@ -63,9 +64,10 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
     }
   } else if (MAP == HOP_MAP_LANE4) {
     const int ngroups = (A.nrhs + 3) >> 2;
-    const long long chunk = w / ngroups;
+    const long long chunk = SWEEP ? w % nchunk : w / ngroups;
+    const int group = SWEEP ? (int)(w / nchunk) : (int)(w % ngroups);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    rhs = (int)(w % ngroups) * 4 + (lane >> 4);
+    rhs = group * 4 + (lane >> 4);
     if (rhs >= A.nrhs) return;
     if (FULL) {
       p = wave >> 1;
@@ -76,9 +78,10 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
     }
   } else {
     const int ngroups = (A.nrhs + 3) >> 2;
-    const long long chunk = w / ngroups;
+    const long long chunk = SWEEP ? w % nchunk : w / ngroups;
+    const int group = SWEEP ? (int)(w / nchunk) : (int)(w % ngroups);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    rhs = (int)(w % ngroups) * 4 + wave;
+    rhs = group * 4 + wave;
     if (rhs >= A.nrhs) return;
     if (FULL) {
       p = lane >> 5;
@@ -180,25 +183,367 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A) {
   }
 }
 
+// x0-streaming even-odd hop (output parity p, input parity q = 1 - p). A workgroup owns
+// S consecutive slice-local sites s (site j = x0*V3h + s of its parity) for one rhs and
+// walks a chunk of x0 slices. The time neighbours of output (x0, s) are the inputs
+// (x0 +/- 1, s) with the same s, so each input is loaded once per chunk: its (1 + g0)
+// projection is carried in registers for the backward hop two slices later, and the
+// whole input slice is staged in LDS (double buffered), from where the spatial
+// neighbours inside [s0, s0 + S) are read; only neighbours outside the range are loaded
+// from memory. Links are used once per half hop and are read directly.
+template <class R, int S>
+__global__ __launch_bounds__(S) void hop_stream_kernel(HopArgs<R> A, int T, int nrange, int nchunk) {
+  typedef typename vec2<R>::type V2;
+  extern __shared__ char smem_raw[];
+  V2* plane = (V2*)smem_raw;                       // [2 buffers][12 components][S]
+  const Geo& g = A.g;
+  const long long nwg = gridDim.x;
+  const long long w = xcd_logical_block(blockIdx.x, nwg);
+  const int rhs = (int)(w % A.nrhs);
+  const long long rest = w / A.nrhs;
+  const int range = (int)(rest % nrange);
+  const int chunk = (int)(rest / nrange);
+  if (chunk >= nchunk) return;                     // whole workgroup: padding of the grid
+  const int p = A.parity_out, q = 1 - p;
+  const int t = threadIdx.x;
+  const int s0 = range * S;
+  const int s = s0 + t;
+  const bool active = s < g.V3h;
+  const int x0a = chunk * T;
+  const int x0b = min(x0a + T, g.L0);
+  const long long Vhp = g.Vhp;
+  const V2* inb = A.in.ptr + rhs * A.in.rs + q * A.in.ps;
+  const bool g5i = A.g5_in != 0;
+  const int lb = A.lb;
+
+  auto ldsp = [&](int buf, int tt, cx<R> sp[4][3]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<R> v = ld<R>(plane + ((buf * 12) + a * 3 + c) * S + tt);
+        sp[a][c] = (g5i && a >= 2) ? -v : v;
+      }
+  };
+  auto put = [&](int buf, const cx<R> sp[4][3]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) st<R>(plane + ((buf * 12) + a * 3 + c) * S + t, sp[a][c]);
+  };
+  auto slice_j = [&](int x0) { return (long long)x0 * g.V3h + s; };
+  auto wrap = [&](int x0) { return x0 < 0 ? x0 + g.L0 : (x0 >= g.L0 ? x0 - g.L0 : x0); };
+
+  // carried (1 + g0) projections of the inputs on the two previous slices
+  cx<R> carry[2][2][3];
+  cx<R> sp[4][3];
+  if (active) {
+    const bool need_prev = !(lb && (x0a % lb) == 0);
+    if (need_prev) {
+      load_spinor<R>(inb, slice_j(wrap(x0a - 1)), g5i, sp);
+      project<R>(0, true, sp, carry[(x0a - 1) & 1]);
+    }
+    load_spinor<R>(inb, slice_j(x0a), false, sp);      // raw copy to LDS, g5 applied on read
+    put(x0a & 1, sp);
+    if (g5i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { sp[2][c] = -sp[2][c]; sp[3][c] = -sp[3][c]; }
+    project<R>(0, true, sp, carry[x0a & 1]);
+  }
+  __syncthreads();
+
+  for (int x0 = x0a; x0 < x0b; ++x0) {
+    const int buf = x0 & 1;
+    if (active) {
+      const long long j = slice_j(x0);
+      const Site st_ = decode(g, j, p);
+      V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
+      bool sel = true;
+      if (A.slb) {
+        const int blk = x0 / A.slb;
+        sel = A.block >= 0 ? (blk == A.block) : ((A.colour == 0) || ((A.colour == 1) == ((blk & 1) == 1)));
+      }
+      // next input slice: time-forward neighbour, staged for the next step
+      cx<R> nx[4][3];
+      const bool fwd_on = !(lb && (x0 % lb) == lb - 1);
+      if (fwd_on || x0 + 1 < x0b) {
+        load_spinor<R>(inb, slice_j(wrap(x0 + 1)), false, nx);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) nx[a][c] = {R(0), R(0)};
+      }
+      if (x0 + 1 < x0b) put(buf ^ 1, nx);
+      if (g5i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { nx[2][c] = -nx[2][c]; nx[3][c] = -nx[3][c]; }
+      if (!sel) {
+        cx<R> z = {R(0), R(0)};
+#pragma unroll
+        for (int c = 0; c < 12; ++c) st<R>(o + c * TILE, z);
+      } else {
+        cx<R> acc[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[a][c] = {R(0), R(0)};
+        // spatial directions: neighbours from LDS when inside this workgroup's range
+#pragma unroll
+        for (int mu = 1; mu < 4; ++mu) {
+#pragma unroll
+          for (int dir = 0; dir < 2; ++dir) {
+            const long long jn = nbr(g, st_, j, mu, dir == 0 ? +1 : -1);
+            const int sn = (int)(jn - (long long)x0 * g.V3h);
+            cx<R> nb[4][3], h[2][3], uh[2][3], m[9];
+            if (sn >= s0 && sn < s0 + S) ldsp(buf, sn - s0, nb);
+            else load_spinor<R>(inb, jn, g5i, nb);
+            project<R>(mu, dir == 1, nb, h);
+            if (dir == 0) {
+              load_link<R>(A.U, Vhp, mu, p, j, m);
+              su3_mul<R>(m, h[0], uh[0]);
+              su3_mul<R>(m, h[1], uh[1]);
+            } else {
+              load_link<R>(A.U, Vhp, mu, q, jn, m);
+              su3_dag_mul<R>(m, h[0], uh[0]);
+              su3_dag_mul<R>(m, h[1], uh[1]);
+            }
+            accum_recon<R>(mu, dir == 1, uh, acc);
+          }
+        }
+        // time forward: (1 - g0) U_0(x) in(x + 0)
+        if (fwd_on) {
+          cx<R> h[2][3], uh[2][3], m[9];
+          project<R>(0, false, nx, h);
+          load_link<R>(A.U, Vhp, 0, p, j, m);
+          su3_mul<R>(m, h[0], uh[0]);
+          su3_mul<R>(m, h[1], uh[1]);
+          if (x0 == g.L0 - 1)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+          accum_recon<R>(0, false, uh, acc);
+        }
+        // time backward: (1 + g0) U_0(x - 0)^+ in(x - 0), projection carried
+        if (!(lb && (x0 % lb) == 0)) {
+          cx<R> uh[2][3], m[9];
+          load_link<R>(A.U, Vhp, 0, q, slice_j(wrap(x0 - 1)), m);
+          su3_dag_mul<R>(m, carry[(x0 - 1) & 1][0], uh[0]);
+          su3_dag_mul<R>(m, carry[(x0 - 1) & 1][1], uh[1]);
+          if (x0 == 0)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+          accum_recon<R>(0, true, uh, acc);
+        }
+        if (A.g5_out) {
+#pragma unroll
+          for (int a = 2; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[a][c] = -acc[a][c];
+        }
+        if (A.x.ptr) {
+          const V2* xp = A.x.ptr + rhs * A.x.rs + p * A.x.ps + tiled(j, 0, 12);
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              cx<R> xv = ld<R>(xp + (a * 3 + c) * TILE);
+              cx<R> r = {A.a * xv.r + A.b * acc[a][c].r, A.a * xv.i + A.b * acc[a][c].i};
+              st<R>(o + (a * 3 + c) * TILE, r);
+            }
+        } else {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st<R>(o + (a * 3 + c) * TILE, A.b * acc[a][c]);
+        }
+      }
+      // the input of this step's forward hop is the backward input two steps later
+      project<R>(0, true, nx, carry[(x0 + 1) & 1]);
+    }
+    __syncthreads();
+  }
+}
+
+// Register-blocked hop: one work-item per site and group of NR right-hand sides; each
+// link is loaded once and applied to the NR input spinors, so link traffic falls by NR
+// with no reliance on caches, while each rhs keeps the single-rhs access pattern (64
+// consecutive sites per wavefront). Workgroups are ordered group-fastest.
+template <class R, bool FULL, int NR>
+__global__ __launch_bounds__(256) void hop_reg_kernel(HopArgs<R> A) {
+  typedef typename vec2<R>::type V2;
+  const long long nwg = gridDim.x;
+  const long long w = xcd_logical_block(blockIdx.x, nwg);
+  const int ngroups = (A.nrhs + NR - 1) / NR;
+  const int r0 = (int)(w % ngroups) * NR;
+  const long long chunk = w / ngroups;
+  const int nr = min(NR, A.nrhs - r0);
+  int p;
+  long long j;
+  if (FULL) {
+    p = threadIdx.x >> 7;
+    j = chunk * 128 + (threadIdx.x & 127);
+  } else {
+    p = A.parity_out;
+    j = chunk * 256 + threadIdx.x;
+  }
+  const Geo& g = A.g;
+  if (j >= g.Vh) return;
+  const long long Vhp = g.Vhp;
+  const Site s = decode(g, j, p);
+  if (A.slb) {
+    const int blk = s.x0 / A.slb;
+    bool sel;
+    if (A.block >= 0) sel = (blk == A.block);
+    else sel = (A.colour == 0) || ((A.colour == 1) == ((blk & 1) == 1));
+    if (!sel) {
+      cx<R> z = {R(0), R(0)};
+      for (int r = 0; r < nr; ++r) {
+        V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) st<R>(o + c * TILE, z);
+      }
+      return;
+    }
+  }
+  cx<R> acc[NR][4][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r][a][c] = {R(0), R(0)};
+  const V2* inb = A.in.ptr + (1 - p) * A.in.ps;
+  const bool g5i = A.g5_in != 0;
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool on = dir == 0 ? !(A.lb && mu == 0 && (s.x0 % A.lb) == A.lb - 1)
+                               : !(A.lb && mu == 0 && (s.x0 % A.lb) == 0);
+      if (!on) continue;
+      const long long jn = nbr(g, s, j, mu, dir == 0 ? +1 : -1);
+      cx<R> m[9];
+      if (dir == 0) load_link<R>(A.U, Vhp, mu, p, j, m);
+      else load_link<R>(A.U, Vhp, mu, 1 - p, jn, m);
+      const bool flip = mu == 0 && (dir == 0 ? s.x0 == g.L0 - 1 : s.x0 == 0);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+          cx<R> sp[4][3], h[2][3], uh[2][3];
+          load_spinor<R>(inb + (r0 + r) * A.in.rs, jn, g5i, sp);
+          project<R>(mu, dir == 1, sp, h);
+          if (dir == 0) {
+            su3_mul<R>(m, h[0], uh[0]);
+            su3_mul<R>(m, h[1], uh[1]);
+          } else {
+            su3_dag_mul<R>(m, h[0], uh[0]);
+            su3_dag_mul<R>(m, h[1], uh[1]);
+          }
+          if (flip)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+          accum_recon<R>(mu, dir == 1, uh, acc[r]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) continue;
+    if (A.g5_out) {
+#pragma unroll
+      for (int a = 2; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r][a][c] = -acc[r][a][c];
+    }
+    V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
+    if (A.x.ptr) {
+      const V2* xp = A.x.ptr + (r0 + r) * A.x.rs + p * A.x.ps + tiled(j, 0, 12);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cx<R> xv = ld<R>(xp + (a * 3 + c) * TILE);
+          cx<R> v = {A.a * xv.r + A.b * acc[r][a][c].r, A.a * xv.i + A.b * acc[r][a][c].i};
+          st<R>(o + (a * 3 + c) * TILE, v);
+        }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st<R>(o + (a * 3 + c) * TILE, A.b * acc[r][a][c]);
+    }
+  }
+}
+
 static inline long long round8(long long n) { return (n + 7) / 8 * 8; }
+
+template <class R, int NR> static void launch_reg(const HopArgs<R>& A, hipStream_t st) {
+  const bool full = A.parity_out < 0;
+  const long long per = full ? 128 : 256;
+  const long long chunks = (A.g.Vh + per - 1) / per;
+  const long long groups = (A.nrhs + NR - 1) / NR;
+  const dim3 grid((unsigned)round8(chunks * groups)), blk(256);
+  if (full) hipLaunchKernelGGL((hop_reg_kernel<R, true, NR>), grid, blk, 0, st, A);
+  else hipLaunchKernelGGL((hop_reg_kernel<R, false, NR>), grid, blk, 0, st, A);
+}
+
+template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {
+  typedef typename vec2<R>::type V2;
+  constexpr int S = sizeof(R) == 8 ? 128 : 256;     // 48 KB of LDS either way
+  const int T = A.lb ? A.lb : (A.g.L0 >= 8 ? 8 : A.g.L0);
+  const int nrange = (A.g.V3h + S - 1) / S;
+  const int nchunk = (A.g.L0 + T - 1) / T;
+  const long long nwg = round8((long long)nrange * nchunk * A.nrhs);
+  const size_t lds = 2 * 12 * S * sizeof(V2);
+  hipLaunchKernelGGL((hop_stream_kernel<R, S>), dim3((unsigned)nwg), dim3(S), lds, st, A, T, nrange, nchunk);
+}
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t st) {
   const bool full = A.parity_out < 0;
-  const int map = A.nrhs > 1 ? A.map : HOP_MAP_SITE;
+  if (A.map == HOP_MAP_STREAM && !full) {
+    launch_stream<R>(A, st);
+    return;
+  }
+  if (A.map == HOP_MAP_REG2 && A.nrhs > 1) {
+    launch_reg<R, 2>(A, st);
+    return;
+  }
+  if (A.map == HOP_MAP_REG4 && A.nrhs > 1) {
+    launch_reg<R, 4>(A, st);
+    return;
+  }
+  int map = (A.map == HOP_MAP_STREAM || A.map >= HOP_MAP_REG2) ? HOP_MAP_SITE : A.map;
+  const bool sweep = map >= HOP_SWEEP;
+  if (sweep) map -= HOP_SWEEP;
+  if (A.nrhs == 1) map = HOP_MAP_SITE;                       // LANE4 / WAVE4 need several rhs
   const bool grouped = map != HOP_MAP_SITE;
   const long long per = grouped ? (full ? 32 : 64) : (full ? 128 : 256);
   const long long groups = grouped ? (A.nrhs + 3) / 4 : A.nrhs;
   const long long chunks = (A.g.Vh + per - 1) / per;
   const dim3 grid((unsigned)round8(chunks * groups)), blk(256);
+#define SAP_HOP(F, M, SW) hipLaunchKernelGGL((hop_kernel<R, F, M, SW>), grid, blk, 0, st, A, chunks)
+#define SAP_HOP_MAPS(F, SW)                                                              \
+  do {                                                                                   \
+    if (map == HOP_MAP_LANE4) SAP_HOP(F, HOP_MAP_LANE4, SW);                             \
+    else if (map == HOP_MAP_WAVE4) SAP_HOP(F, HOP_MAP_WAVE4, SW);                        \
+    else SAP_HOP(F, HOP_MAP_SITE, SW);                                                   \
+  } while (0)
   if (full) {
-    if (map == HOP_MAP_LANE4) hipLaunchKernelGGL((hop_kernel<R, true, HOP_MAP_LANE4>), grid, blk, 0, st, A);
-    else if (map == HOP_MAP_WAVE4) hipLaunchKernelGGL((hop_kernel<R, true, HOP_MAP_WAVE4>), grid, blk, 0, st, A);
-    else hipLaunchKernelGGL((hop_kernel<R, true, HOP_MAP_SITE>), grid, blk, 0, st, A);
+    if (sweep) SAP_HOP_MAPS(true, true);
+    else SAP_HOP_MAPS(true, false);
   } else {
-    if (map == HOP_MAP_LANE4) hipLaunchKernelGGL((hop_kernel<R, false, HOP_MAP_LANE4>), grid, blk, 0, st, A);
-    else if (map == HOP_MAP_WAVE4) hipLaunchKernelGGL((hop_kernel<R, false, HOP_MAP_WAVE4>), grid, blk, 0, st, A);
-    else hipLaunchKernelGGL((hop_kernel<R, false, HOP_MAP_SITE>), grid, blk, 0, st, A);
+    if (sweep) SAP_HOP_MAPS(false, true);
+    else SAP_HOP_MAPS(false, false);
   }
+#undef SAP_HOP_MAPS
+#undef SAP_HOP
 }
 
 template void launch_hop<double>(const HopArgs<double>&, hipStream_t);

@@ -40,7 +40,12 @@ template <class R> struct HopArgs {
 enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fastest
        HOP_MAP_LANE4 = 1,   // wavefront = 16 sites x 4 rhs: four lanes share each link load
        HOP_MAP_WAVE4 = 2,   // workgroup = 64 sites x 4 rhs, one rhs per wavefront
-       HOP_NMAP = 3 };
+       HOP_MAP_STREAM = 3,  // half hop only: x0-streaming, input slice staged in LDS
+       HOP_SWEEP = 4,       // added to SITE/LANE4/WAVE4: workgroups rhs(-group)-slowest, so
+                            // each rhs sweeps the lattice like a single-rhs launch
+       HOP_MAP_REG2 = 7,    // one work-item per site for 2 rhs held in registers: each
+       HOP_MAP_REG4 = 8,    //   link is loaded once and applied to 2 (4) rhs
+       HOP_NMAP = 9 };
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
 
@@ -84,11 +89,12 @@ struct sap_ctx {
   signed char hop_map[2][2][65];
 };
 
-// mapping used for a hop launch: the tuned one, else LANE4 for nrhs > 1
+// mapping used for a hop launch: the tuned (or set) one, else SITE for one rhs and LANE4
+// for several
 inline int hop_map_for(const sap_ctx* c, bool full, int prec_is_f32, int nrhs) {
-  if (nrhs <= 1) return sap::HOP_MAP_SITE;
   const int m = c->hop_map[full ? 1 : 0][prec_is_f32][nrhs > 64 ? 64 : nrhs];
-  return m >= 0 ? m : sap::HOP_MAP_LANE4;
+  if (m >= 0) return m;
+  return nrhs <= 1 ? sap::HOP_MAP_SITE : sap::HOP_MAP_LANE4;
 }
 
 // error helpers (api.hip)

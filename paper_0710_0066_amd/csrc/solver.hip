@@ -309,6 +309,13 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
   int best = HOP_MAP_SITE;
   float best_ms = 1e30f;
   for (int m = 0; m < HOP_NMAP; ++m) {
+    if ((full && m == HOP_MAP_STREAM) || (nrhs == 1 && (m == HOP_MAP_LANE4 || m == HOP_MAP_WAVE4 ||
+                                                           m >= HOP_SWEEP))) {
+      // the streaming kernel exists for half hops only; with one rhs the grouped and
+      // sweep orders coincide with SITE
+      if (us_out) us_out[m] = -1.0f;
+      continue;
+    }
     A.map = m;
     for (int k = 0; k < 2; ++k) launch_hop<R>(A, st);
     SAP_HIP_CHECK(c, hipEventRecord(e0, st));
@@ -319,6 +326,7 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
     float ms = 0;
     SAP_HIP_CHECK(c, hipEventElapsedTime(&ms, e0, e1));
     ms /= reps;
+    if (hipGetLastError() != hipSuccess) ms = 1e30f;   // variant not launchable here
     if (us_out) us_out[m] = ms * 1e3f;
     if (ms < best_ms) { best_ms = ms; best = m; }
   }
@@ -331,7 +339,7 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
 extern "C" int sap_tune(sap_ctx* c, int nrhs, float* us_out, void* stream) {
   if (c && c->solver) drop_graphs(ws_of(c));   // captured graphs hold the old mappings
   if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
-  if (nrhs < 2 || nrhs > c->geom.max_rhs) return sap_fail(c, SAP_E_ARG, "nrhs must be in [2, max_rhs]");
+  if (nrhs < 1 || nrhs > c->geom.max_rhs) return sap_fail(c, SAP_E_ARG, "nrhs must be in [1, max_rhs]");
   if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
   hipStream_t st = (hipStream_t)stream;
   SolverWS* w = ws_of(c);
@@ -339,10 +347,21 @@ extern "C" int sap_tune(sap_ctx* c, int nrhs, float* us_out, void* stream) {
   SAP_HIP_CHECK(c, hipMemsetAsync(w->r64, 0, fb, st));
   SAP_HIP_CHECK(c, hipMemsetAsync(w->ax, 0, fb, st));
   int rc;
-  if ((rc = tune_one<double>(c, true, nrhs, st, us_out ? us_out + 0 : nullptr))) return rc;
-  if ((rc = tune_one<float>(c, true, nrhs, st, us_out ? us_out + 3 : nullptr))) return rc;
-  if ((rc = tune_one<double>(c, false, nrhs, st, us_out ? us_out + 6 : nullptr))) return rc;
-  if ((rc = tune_one<float>(c, false, nrhs, st, us_out ? us_out + 9 : nullptr))) return rc;
+  if ((rc = tune_one<double>(c, true, nrhs, st, us_out ? us_out + 0 * HOP_NMAP : nullptr))) return rc;
+  if ((rc = tune_one<float>(c, true, nrhs, st, us_out ? us_out + 1 * HOP_NMAP : nullptr))) return rc;
+  if ((rc = tune_one<double>(c, false, nrhs, st, us_out ? us_out + 2 * HOP_NMAP : nullptr))) return rc;
+  if ((rc = tune_one<float>(c, false, nrhs, st, us_out ? us_out + 3 * HOP_NMAP : nullptr))) return rc;
+  return SAP_OK;
+}
+
+extern "C" int sap_set_hop_map(sap_ctx* c, int full, sap_prec prec, int nrhs, int map) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (nrhs < 1 || nrhs > 64) return sap_fail(c, SAP_E_ARG, "nrhs must be in [1, 64]");
+  if (map < -1 || map >= HOP_NMAP) return sap_fail(c, SAP_E_ARG, "unknown mapping");
+  if (full && map == HOP_MAP_STREAM) return sap_fail(c, SAP_E_ARG, "the streaming mapping is for the even-odd hop only");
+  if (prec != SAP_F64 && prec != SAP_F32) return sap_fail(c, SAP_E_ARG, "unknown precision");
+  if (c->solver) drop_graphs(ws_of(c));
+  c->hop_map[full ? 1 : 0][prec == SAP_F32 ? 1 : 0][nrhs] = (signed char)map;
   return SAP_OK;
 }
 

@@ -94,6 +94,50 @@ def test_apply_Dslash_eo_matches_oracle(gu, L, l0, l0_sub, k, nrhs):
             assert gu.rel_err(got * m_out, ref) <= tol, (parity, prec)
 
 
+@pytest.mark.parametrize("hop_map", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15)])
+def test_every_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
+    """Each work-item mapping of the hop kernel (site, lane4, wave4 and, for the even-odd
+    hop, the x0-streaming kernel with LDS staging) gives the oracle's D_eo, M and W, with
+    1 and 5 right-hand sides, including the gamma_5-folded and block-restricted forms the
+    solvers use (through solve_blocks)."""
+    import paper_0710_0066_amd as sap
+    print(f"hop map {hop_map} L={L}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1021)
+    par = lattice.parity(L)
+    for nrhs in (1, 5):
+        psi = synth.gaussian_spinor(L, 2021 + nrhs, nrhs=nrhs)
+        ctx = gu.make_ctx(L, l0, k, U, l0_sub, max_rhs=nrhs)
+        for prec, tol in [(sap.SAP_F64, F64_TOL), (sap.SAP_F32, F32_TOL)]:
+            sap.sap_set_hop_map(ctx, 0, prec, nrhs, hop_map)
+            if hop_map != 3:
+                sap.sap_set_hop_map(ctx, 1, prec, nrhs, hop_map)   # full operator too
+            fin = gu.to_sap(ctx, psi, nrhs, prec)
+            fout = ctx.new_field(nrhs, prec)
+            for parity in (0, 1):
+                m_out = lattice.site_mask(L, par == parity)
+                ref = dirac.hop(U, psi * lattice.site_mask(L, par != parity)) * m_out
+                sap.apply_Dslash_eo(ctx, fout, fin, nrhs, parity, prec)
+                got = gu.from_sap(ctx, fout, nrhs, psi.shape, prec) * m_out
+                assert gu.rel_err(got, ref) <= tol, (nrhs, prec, parity)
+            sap.apply_M(ctx, fout, fin, nrhs, prec)
+            assert gu.rel_err(gu.from_sap(ctx, fout, nrhs, psi.shape, prec), dirac.apply_M(U, psi, k)) <= tol
+        # the solvers' even-odd block hops (gamma_5 folding, block drop, colour selection)
+        b = psi
+        fb = gu.to_sap(ctx, b, nrhs)
+        fx = ctx.new_field(nrhs)
+        opts = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F32, inner_tol=1e-5)
+        cases = [(1, l0, sap.SAP_BLACK, "black")] + ([(2, l0_sub, sap.SAP_ALL, "all")] if l0_sub else [])
+        for level, lb, colour, cname in cases:
+            sap.solve_blocks(ctx, fx, fb, nrhs, level, colour, opts)
+            x = gu.from_sap(ctx, fx, nrhs, b.shape)
+            msk = lattice.site_mask(L, lattice.colour_x0_mask(L, lb, cname))
+            r = (b - dirac.apply_W(U, x, k, lb)) * msk
+            ax = tuple(range(r.ndim - 6, r.ndim))
+            res = np.sqrt(np.sum(np.abs(r) ** 2, axis=ax) / np.sum(np.abs(b * msk) ** 2, axis=ax))
+            assert np.all(res <= 1e-10), (level, res)
+
+
 @pytest.mark.parametrize("name", ["plain_16x16x16x32", "batched_24x24x24x48"])
 def test_apply_M_and_W_full_size(gu, name):
     """Full-size workloads in the launch configuration the benchmark times: every
