@@ -183,13 +183,14 @@ int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parit
  * even-odd f32 x4] over the mappings [site, lane4, wave4, stream]. Uses the solver
  * workspace; synchronises. Untuned calls use the 4-rhs-per-wavefront mapping. */
 int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
-/* (us_out holds 36 floats: 4 operator kinds x 9 mappings [site, lane4, wave4, stream,
- *  site+sweep, lane4+sweep, wave4+sweep, reg2, reg4]; "sweep" orders the workgroups
- *  rhs-slowest, "regN" applies each loaded link to N rhs held in registers.) */
+/* (us_out holds 44 floats: 4 operator kinds x 11 mappings [site, lane4, wave4, stream,
+ *  site+sweep, lane4+sweep, wave4+sweep, reg2, reg4, reg2+sweep, reg4+sweep]; "sweep"
+ *  orders the workgroups rhs-slowest, "regN" applies each loaded link to N rhs held in
+ *  registers.) */
 
 /* Set the hop mapping used for nrhs right-hand sides by hand (map: 0 site, 1 lane4,
  * 2 wave4, 3 stream (even-odd hop only, full = 0), 4..6 = 0..2 with rhs-slowest workgroup
- * order, 7 reg2, 8 reg4; -1 restores the default), for the full
+ * order, 7 reg2, 8 reg4, 9 / 10 reg2 / reg4 group-slowest; -1 restores the default), for the full
  * operator (full = 1) or the even-odd hop (full = 0) at precision prec. */
 int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);
 

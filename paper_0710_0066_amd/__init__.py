@@ -213,16 +213,17 @@ def sap_plaquette(ctx):
 
 def sap_tune(ctx, nrhs):
     """Tune the hop mapping for nrhs; returns microseconds per launch per variant."""
-    us = (ctypes.c_float * 36)()
+    us = (ctypes.c_float * 44)()
     _check(ctx.ptr, _lib.sap_tune(ctx.ptr, nrhs, us, _stream()))
     names = ["full_f64", "full_f32", "eo_f64", "eo_f32"]
-    maps = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4"]
-    return {n: {m: us[9 * i + k] for k, m in enumerate(maps) if us[9 * i + k] >= 0}
+    maps = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4",
+            "reg2_sweep", "reg4_sweep"]
+    return {n: {m: us[11 * i + k] for k, m in enumerate(maps) if us[11 * i + k] >= 0}
             for i, n in enumerate(names)}
 
 
 HOP_MAP_SITE, HOP_MAP_LANE4, HOP_MAP_WAVE4, HOP_MAP_STREAM, HOP_SWEEP = 0, 1, 2, 3, 4
-HOP_MAP_REG2, HOP_MAP_REG4 = 7, 8
+HOP_MAP_REG2, HOP_MAP_REG4, HOP_MAP_REG2_SWEEP, HOP_MAP_REG4_SWEEP = 7, 8, 9, 10
 
 
 def sap_set_hop_map(ctx, full, prec, nrhs, hop_map):

@@ -372,14 +372,15 @@ __global__ __launch_bounds__(S) void hop_stream_kernel(HopArgs<R> A, int T, int 
 // link is loaded once and applied to the NR input spinors, so link traffic falls by NR
 // with no reliance on caches, while each rhs keeps the single-rhs access pattern (64
 // consecutive sites per wavefront). Workgroups are ordered group-fastest.
-template <class R, bool FULL, int NR>
-__global__ __launch_bounds__(256) void hop_reg_kernel(HopArgs<R> A) {
+template <class R, bool FULL, int NR, bool SWEEP>
+__global__ __launch_bounds__(256) void hop_reg_kernel(HopArgs<R> A, long long nchunk) {
   typedef typename vec2<R>::type V2;
   const long long nwg = gridDim.x;
   const long long w = xcd_logical_block(blockIdx.x, nwg);
   const int ngroups = (A.nrhs + NR - 1) / NR;
-  const int r0 = (int)(w % ngroups) * NR;
-  const long long chunk = w / ngroups;
+  const int r0 = (SWEEP ? (int)(w / nchunk) : (int)(w % ngroups)) * NR;
+  const long long chunk = SWEEP ? w % nchunk : w / ngroups;
+  if (r0 >= A.nrhs) return;
   const int nr = min(NR, A.nrhs - r0);
   int p;
   long long j;
@@ -484,14 +485,14 @@ __global__ __launch_bounds__(256) void hop_reg_kernel(HopArgs<R> A) {
 
 static inline long long round8(long long n) { return (n + 7) / 8 * 8; }
 
-template <class R, int NR> static void launch_reg(const HopArgs<R>& A, hipStream_t st) {
+template <class R, int NR, bool SWEEP> static void launch_reg(const HopArgs<R>& A, hipStream_t st) {
   const bool full = A.parity_out < 0;
   const long long per = full ? 128 : 256;
   const long long chunks = (A.g.Vh + per - 1) / per;
   const long long groups = (A.nrhs + NR - 1) / NR;
   const dim3 grid((unsigned)round8(chunks * groups)), blk(256);
-  if (full) hipLaunchKernelGGL((hop_reg_kernel<R, true, NR>), grid, blk, 0, st, A);
-  else hipLaunchKernelGGL((hop_reg_kernel<R, false, NR>), grid, blk, 0, st, A);
+  if (full) hipLaunchKernelGGL((hop_reg_kernel<R, true, NR, SWEEP>), grid, blk, 0, st, A, chunks);
+  else hipLaunchKernelGGL((hop_reg_kernel<R, false, NR, SWEEP>), grid, blk, 0, st, A, chunks);
 }
 
 template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {
@@ -511,13 +512,14 @@ template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t st) {
     launch_stream<R>(A, st);
     return;
   }
-  if (A.map == HOP_MAP_REG2 && A.nrhs > 1) {
-    launch_reg<R, 2>(A, st);
-    return;
-  }
-  if (A.map == HOP_MAP_REG4 && A.nrhs > 1) {
-    launch_reg<R, 4>(A, st);
-    return;
+  if (A.nrhs > 1) {
+    switch (A.map) {
+      case HOP_MAP_REG2: launch_reg<R, 2, false>(A, st); return;
+      case HOP_MAP_REG4: launch_reg<R, 4, false>(A, st); return;
+      case HOP_MAP_REG2_SWEEP: launch_reg<R, 2, true>(A, st); return;
+      case HOP_MAP_REG4_SWEEP: launch_reg<R, 4, true>(A, st); return;
+      default: break;
+    }
   }
   int map = (A.map == HOP_MAP_STREAM || A.map >= HOP_MAP_REG2) ? HOP_MAP_SITE : A.map;
   const bool sweep = map >= HOP_SWEEP;

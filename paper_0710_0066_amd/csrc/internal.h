@@ -45,7 +45,9 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
                             // each rhs sweeps the lattice like a single-rhs launch
        HOP_MAP_REG2 = 7,    // one work-item per site for 2 rhs held in registers: each
        HOP_MAP_REG4 = 8,    //   link is loaded once and applied to 2 (4) rhs
-       HOP_NMAP = 9 };
+       HOP_MAP_REG2_SWEEP = 9,   // REG2 / REG4 with workgroups group-slowest: each group
+       HOP_MAP_REG4_SWEEP = 10,  //   of rhs sweeps the lattice like a small-rhs launch
+       HOP_NMAP = 11 };
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
 

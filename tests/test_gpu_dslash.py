@@ -94,7 +94,7 @@ def test_apply_Dslash_eo_matches_oracle(gu, L, l0, l0_sub, k, nrhs):
             assert gu.rel_err(got * m_out, ref) <= tol, (parity, prec)
 
 
-@pytest.mark.parametrize("hop_map", [0, 1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("hop_map", list(range(11)))
 @pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15)])
 def test_every_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
     """Each work-item mapping of the hop kernel (site, lane4, wave4 and, for the even-odd
