@@ -104,6 +104,10 @@ typedef struct {
   const double* xi1;    /* heat-bath noise for phi1 = W1 xi1, canonical spinor */
   const double* xi2;    /* heat-bath noise for chi = R_hat Pi xi2, canonical spinor */
   double u_metropolis;  /* uniform number in [0,1) for the accept step */
+  const double* step_scale; /* host [L0][4]: step of link (x0, mu) = dt * s (Sec. 2, x0-dependent
+                            * step size; s = 0 freezes the link); NULL: s = 1 */
+  int time_shift;       /* translate the resulting field by this many slices in x0
+                         * (U'(x0) = U(x0 + n)) after the accept step (Sec. 2); 0: none */
 } sap_hmc_params;
 
 typedef struct {
@@ -254,6 +258,10 @@ int gauge_force(sap_ctx* ctx, double* F, double coef, double beta, double* S_G_o
  * (FP64 exponential, reunitarised). */
 int sap_update_links(sap_ctx* ctx, const double* p, double dt, void* stream);
 
+/* Translate the context's gauge field by n slices in x0: U'(x0, ...) = U(x0 + n, ...)
+ * (Sec. 2: shift after each trajectory for ergodicity of the inactive links). */
+int sap_shift_gauge(sap_ctx* ctx, int n, void* stream);
+
 /* Mean plaquette (1/6V) sum_{x, mu>nu} (1/3) Re Tr U_P of the context's gauge field (host
  * output). Synchronises. */
 int sap_plaquette(sap_ctx* ctx, double* plaq_out, void* stream);
@@ -264,8 +272,9 @@ int sap_plaquette(sap_ctx* ctx, double* plaq_out, void* stream);
  * S_pf = ||W1^{-1} phi1||^2 + ||R_hat^{-1} chi||^2, the inner level the gauge action;
  * steps T_U: U -> exp(i dt P) U (FP64 exponential + reunitarisation) and
  * T_P: p -> p - dt F; leap-frog or Sexton-Weingarten per level; Metropolis with
- * p->u_metropolis. U: canonical gauge field, replaced by the new field if accepted
- * (left unchanged otherwise); the context's gauge copies end equal to U. info: host. */
+ * p->u_metropolis, then the optional x0 translation. U: canonical gauge field, replaced
+ * by the resulting field (the new one if accepted, else the old one, translated when
+ * time_shift != 0); the context's gauge copies end equal to U. info: host. */
 int hmc_trajectory(sap_ctx* ctx, double* U, const sap_hmc_params* p, sap_hmc_info* info,
                    void* stream);
 

@@ -11,6 +11,10 @@ n_{j-1}/2 steps) of level j-1 with dt_{j-1} = dt_j / n_{j-1}; a trajectory of le
 is n_J steps of the top level J.
 Metropolis (Sec. 3, P_acc): accept with probability min(1, exp(-dH)),
 H = 1/2 sum p^2 + sum_j S_j.
+x0-dependent step size (Sec. 2): every link moves with dt * s_mu(x0) in both T_U and T_P
+(s = 0: the link stays fixed); schemes A, B, C are the paper's periodic tables, separate
+for space-like and time-like links. After a trajectory the configuration may be
+translated in x0 (Sec. 2, ergodicity).
 """
 import numpy as np
 
@@ -31,8 +35,47 @@ def exp_iP(p, dt):
     return np.einsum("...ij,...j,...kj->...ik", v, np.exp(1j * dt * w), v.conj())
 
 
-def T_U(U, p, dt):
+def T_U(U, p, dt, scale=None):
+    """U <- exp(i dt s P) U; ``scale`` (shape [L0, 4]) gives s_mu(x0), default 1."""
+    if scale is not None:
+        p = p * scale[:, None, None, None, :, None]
     return exp_iP(p, dt) @ U
+
+
+def kick(p, F, dt, scale=None):
+    """p <- p - dt s F."""
+    if scale is not None:
+        F = F * scale[:, None, None, None, :, None]
+    return p - dt * F
+
+
+# Sec. 2, schemes (A) L0 = 24, (B) and (C) L0 = 32: s(x0) for space-like and time-like
+# links over one period; scheme A's spatial x0 = 5 entry read as 0.2 (printed: 2).
+STEP_SCHEMES = {
+    "A": ([0.2, 0.5, 1, 1, 0.5, 0.2], [0.2, 0.5, 1, 0.5, 0.2, 0]),
+    "B": ([0, 0.5, 1, 1, 1, 1, 0.5, 0], [0, 0.5, 1, 1, 1, 0.5, 0, 0]),
+    "C": ([0, 0.25, 0.5, 1, 1, 1, 1, 0.25, 0.25, 1, 1, 1, 1, 0.5, 0.25, 0],
+          [0, 0, 0.25, 0.5, 1, 1, 0.25, 0, 0.25, 1, 1, 1, 0.5, 0.25, 0, 0]),
+}
+
+
+def step_profile(scheme, L0):
+    """s_mu(x0) as an array [L0, 4] (mu = 0 time-like, 1..3 space-like), the scheme's
+    table repeated with its period."""
+    sp, tm = STEP_SCHEMES[scheme]
+    per = len(sp)
+    if L0 % per:
+        raise ValueError("L0 must be a multiple of the scheme's period")
+    s = np.zeros((L0, 4))
+    for x0 in range(L0):
+        s[x0, 0] = tm[x0 % per]
+        s[x0, 1:] = sp[x0 % per]
+    return s
+
+
+def time_shift(U, n):
+    """The configuration translated by n slices in x0: U'(x0, ...) = U(x0 + n, ...)."""
+    return np.roll(U, -n, axis=0)
 
 
 def kinetic(p):
@@ -48,57 +91,57 @@ class Level:
         self.force, self.action, self.scheme, self.n = force, action, scheme, n
 
 
-def _inner(levels, j, U, p, dt):
+def _inner(levels, j, U, p, dt, sc):
     """What sits between the two half kicks of a leap-frog level j: T_U(dt) for j = 0,
     else n_{j-1} steps of level j-1 of length dt / n_{j-1}."""
     if j == 0:
-        return T_U(U, p, dt), p
+        return T_U(U, p, dt, sc), p
     nlow = levels[j - 1].n
     for _ in range(nlow):
-        U, p = step(levels, j - 1, U, p, dt / nlow)
+        U, p = step(levels, j - 1, U, p, dt / nlow, sc)
     return U, p
 
 
-def step(levels, j, U, p, dt):
+def step(levels, j, U, p, dt, sc=None):
     lev = levels[j]
     if lev.scheme == "LF":
-        p = p - 0.5 * dt * lev.force(U)
-        U, p = _inner(levels, j, U, p, dt)
-        p = p - 0.5 * dt * lev.force(U)
+        p = kick(p, lev.force(U), 0.5 * dt, sc)
+        U, p = _inner(levels, j, U, p, dt, sc)
+        p = kick(p, lev.force(U), 0.5 * dt, sc)
     elif lev.scheme == "SW":
         lam = LAMBDA_SW
-        p = p - lam * dt * lev.force(U)
+        p = kick(p, lev.force(U), lam * dt, sc)
         if j == 0:
-            U = T_U(U, p, 0.5 * dt)
+            U = T_U(U, p, 0.5 * dt, sc)
         else:
-            U, p = _half(levels, j, U, p, dt)
-        p = p - (1 - 2 * lam) * dt * lev.force(U)
+            U, p = _half(levels, j, U, p, dt, sc)
+        p = kick(p, lev.force(U), (1 - 2 * lam) * dt, sc)
         if j == 0:
-            U = T_U(U, p, 0.5 * dt)
+            U = T_U(U, p, 0.5 * dt, sc)
         else:
-            U, p = _half(levels, j, U, p, dt)
-        p = p - lam * dt * lev.force(U)
+            U, p = _half(levels, j, U, p, dt, sc)
+        p = kick(p, lev.force(U), lam * dt, sc)
     else:
         raise ValueError(lev.scheme)
     return U, p
 
 
-def _half(levels, j, U, p, dt):
+def _half(levels, j, U, p, dt, sc):
     """[T_X,j-1(dt_{j-1})]^{n_{j-1}/2} with dt_{j-1} = dt / n_{j-1}."""
     nlow = levels[j - 1].n
     if nlow % 2:
         raise ValueError("an SW level needs an even step count below it")
     for _ in range(nlow // 2):
-        U, p = step(levels, j - 1, U, p, dt / nlow)
+        U, p = step(levels, j - 1, U, p, dt / nlow, sc)
     return U, p
 
 
-def integrate(levels, U, p, tau):
-    """n_J steps of the top level, dt_J = tau / n_J."""
+def integrate(levels, U, p, tau, scale=None):
+    """n_J steps of the top level, dt_J = tau / n_J; ``scale`` = s_mu(x0) [L0, 4]."""
     J = len(levels) - 1
     dt = tau / levels[J].n
     for _ in range(levels[J].n):
-        U, p = step(levels, J, U, p, dt)
+        U, p = step(levels, J, U, p, dt, scale)
     return U, p
 
 
@@ -106,14 +149,16 @@ def hamiltonian(levels, U, p):
     return kinetic(p) + sum(lev.action(U) for lev in levels)
 
 
-def trajectory(levels, U, p0, tau, u_metropolis):
-    """One HMC trajectory from (U, p0): returns (U_out, accepted, dH, H0, H1)."""
+def trajectory(levels, U, p0, tau, u_metropolis, scale=None, shift=0):
+    """One HMC trajectory from (U, p0): returns (U_out, accepted, dH, H0, H1); U_out is
+    translated by ``shift`` slices in x0 after the accept / reject step."""
     H0 = hamiltonian(levels, U, p0)
-    U1, p1 = integrate(levels, U, p0, tau)
+    U1, p1 = integrate(levels, U, p0, tau, scale)
     H1 = hamiltonian(levels, U1, p1)
     dH = H1 - H0
     acc = u_metropolis < np.exp(-dH)
-    return (U1 if acc else U), bool(acc), dH, H0, H1
+    Uo = U1 if acc else U
+    return (time_shift(Uo, shift) if shift else Uo), bool(acc), dH, H0, H1
 
 
 def schwarz_two_level(phi1, chi, kappa, beta, l0, n_outer, n_inner, make_solvers,

@@ -56,7 +56,8 @@ class sap_hmc_params(ctypes.Structure):
                 ("scheme_outer", ctypes.c_int), ("scheme_inner", ctypes.c_int),
                 ("force_solve", sap_solve_opts), ("action_solve", sap_solve_opts),
                 ("p0", ctypes.c_void_p), ("xi1", ctypes.c_void_p), ("xi2", ctypes.c_void_p),
-                ("u_metropolis", ctypes.c_double)]
+                ("u_metropolis", ctypes.c_double), ("step_scale", ctypes.c_void_p),
+                ("time_shift", ctypes.c_int)]
 
 
 class sap_hmc_info(ctypes.Structure):
@@ -97,6 +98,7 @@ _SIGS = {
     "schwarz_action": ([_P, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
     "sap_update_links": ([_P, _P, _D, _P], _I),
     "sap_plaquette": ([_P, _P, _P], _I),
+    "sap_shift_gauge": ([_P, _I, _P], _I),
     "sap_tune": ([_P, _I, _P, _P], _I),
     "sap_set_hop_map": ([_P, _I, _I, _I, _I], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
@@ -230,11 +232,22 @@ def sap_set_hop_map(ctx, full, prec, nrhs, hop_map):
     _check(ctx.ptr, _lib.sap_set_hop_map(ctx.ptr, int(full), prec, nrhs, hop_map))
 
 
+def sap_shift_gauge(ctx, n):
+    _check(ctx.ptr, _lib.sap_shift_gauge(ctx.ptr, n, _stream()))
+
+
 def hmc_params(beta, tau, n_outer, n_inner, p0, xi1, xi2, u_metropolis, force_solve, action_solve,
-               lam=1.0 / 6.0, scheme_outer=1, scheme_inner=1):
-    """sap_hmc_params from torch tensors (p0 in the sap momentum layout, xi canonical)."""
-    return sap_hmc_params(beta, tau, lam, n_outer, n_inner, scheme_outer, scheme_inner, force_solve,
-                          action_solve, p0.data_ptr(), xi1.data_ptr(), xi2.data_ptr(), u_metropolis)
+               lam=1.0 / 6.0, scheme_outer=1, scheme_inner=1, step_scale=None, time_shift=0):
+    """sap_hmc_params from torch tensors (p0 in the sap momentum layout, xi canonical);
+    step_scale: host float64 array [L0, 4] (kept alive on the returned object)."""
+    prm = sap_hmc_params(beta, tau, lam, n_outer, n_inner, scheme_outer, scheme_inner, force_solve,
+                         action_solve, p0.data_ptr(), xi1.data_ptr(), xi2.data_ptr(), u_metropolis,
+                         None, time_shift)
+    if step_scale is not None:
+        import numpy as np
+        prm._scale = np.ascontiguousarray(step_scale, dtype=np.float64)
+        prm.step_scale = prm._scale.ctypes.data
+    return prm
 
 
 def hmc_trajectory(ctx, U, params):

@@ -4,15 +4,20 @@
 
 namespace sap {
 // F += c * Im tr(lambda^a Q) per link (c = -kappa * coef), W = M (lb = 0) or x0 blocks of lb
+// sx (device, [L0][4], or null): per-link step scale s_mu(x0) multiplying c
 void launch_pair_force(const Geo& g, double* F, double c, const double2* a, const double2* b,
-                       const double2* U, int lb, hipStream_t s);
+                       const double2* U, int lb, hipStream_t s, const double* sx = nullptr);
 // F += c * Im tr(lambda^a U A) (c = coef * beta / 6)
-void launch_gauge_force(const Geo& g, double* F, double c, const double2* U, hipStream_t s);
+void launch_gauge_force(const Geo& g, double* F, double c, const double2* U, hipStream_t s,
+                        const double* sx = nullptr);
+// out = in translated by n slices in x0 (out(x0) = in(x0 + n)); out != in
+void launch_shift_links(const Geo& g, double2* out, const double2* in, int n, hipStream_t s);
 // out[0] = sum_x sum_{mu>nu} Re tr U_P (part: ceil(Vh/128) doubles of scratch)
 void launch_plaq_sum(const Geo& g, const double2* U, double* part, double* out, hipStream_t s);
 void launch_kinetic(const Geo& g, const double* P, double* part, double* out, hipStream_t s);
 void launch_norm2_full(const Geo& g, const double2* f, double* part, double* out, hipStream_t s);
-void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s);
+void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s,
+                         const double* sx = nullptr);
 // mode 0: gamma5; 1: Pi (black-boundary projector, blocks of l0); 2: keep white blocks; 3: in - Pi in2
 void launch_spin_op(const Geo& g, int mode, int l0, double2* out, const double2* in, const double2* in2,
                     hipStream_t s);

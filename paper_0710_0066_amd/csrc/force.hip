@@ -125,7 +125,8 @@ __device__ __forceinline__ M3 outer2(const C h1[2][3], const C h2[2][3]) {
 
 // One work-item per site (128 sites of each parity per workgroup), its four forward links.
 __global__ __launch_bounds__(256) void k_pair_force(Geo g, double* F, double c, const double2* a,
-                                                    const double2* b, const double2* U, int lb) {
+                                                    const double2* b, const double2* U, int lb,
+                                                    const double* sx) {
   const int p = threadIdx.x >> 7;
   const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
   if (j >= g.Vh) return;
@@ -156,7 +157,7 @@ __global__ __launch_bounds__(256) void k_pair_force(Geo g, double* F, double c, 
     double v[8];
     im_tr_lambda(Q, v);
     const double sgn = (mu == 0 && s.x0 == g.L0 - 1) ? -1.0 : 1.0;
-    add_force(F, Vhp, p, j, mu, c * sgn, v);
+    add_force(F, Vhp, p, j, mu, c * sgn * (sx ? sx[s.x0 * 4 + mu] : 1.0), v);
   }
 }
 
@@ -186,7 +187,8 @@ __device__ M3 staples(const Geo& g, const double2* U, int p, long long j, const 
   return A;
 }
 
-__global__ __launch_bounds__(256) void k_gauge_force(Geo g, double* F, double c, const double2* U) {
+__global__ __launch_bounds__(256) void k_gauge_force(Geo g, double* F, double c, const double2* U,
+                                                     const double* sx) {
   const int p = threadIdx.x >> 7;
   const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
   if (j >= g.Vh) return;
@@ -195,7 +197,7 @@ __global__ __launch_bounds__(256) void k_gauge_force(Geo g, double* F, double c,
     const M3 W = mmul(load_U(U, g.Vhp, p, j, mu), staples(g, U, p, j, s, mu));
     double v[8];
     im_tr_lambda(W, v);
-    add_force(F, g.Vhp, p, j, mu, c, v);
+    add_force(F, g.Vhp, p, j, mu, c * (sx ? sx[s.x0 * 4 + mu] : 1.0), v);
   }
 }
 
@@ -309,11 +311,15 @@ __device__ M3 reunitarize(const M3& U) {
 }
 
 // U_mu(x) <- exp(i dt P_mu(x)) U_mu(x), P = sum_a p^a lambda^a / 2
-__global__ __launch_bounds__(256) void k_update_links(Geo g, double2* U, const double* Pm, double dt) {
+__global__ __launch_bounds__(256) void k_update_links(Geo g, double2* U, const double* Pm, double dt0,
+                                                      const double* sx) {
   const int p = threadIdx.x >> 7;
   const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
   if (j >= g.Vh) return;
+  const int x0 = (int)(j / g.V3h);
   for (int mu = 0; mu < 4; ++mu) {
+    const double dt = dt0 * (sx ? sx[x0 * 4 + mu] : 1.0);
+    if (dt == 0.0) continue;                   // inactive link: stays as it is
     const double* q = Pm + p * 32 * g.Vhp + tiled(j, 8 * mu, 32);
     double a[8];
 #pragma unroll
@@ -334,6 +340,20 @@ __global__ __launch_bounds__(256) void k_update_links(Geo g, double2* U, const d
     const M3 Un = reunitarize(mmul(E, load_U(U, g.Vhp, p, j, mu)));
     store_U(U, g.Vhp, p, j, mu, Un);
   }
+}
+
+// U'(x0, ...) = U(x0 + n, ...): translation of the gauge field by n slices in x0
+__global__ __launch_bounds__(256) void k_shift_links(Geo g, double2* out, const double2* in, int n) {
+  const int p = threadIdx.x >> 7;
+  const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
+  if (j >= g.Vh) return;
+  const int x0 = (int)(j / g.V3h);
+  const long long sidx = j - (long long)x0 * g.V3h;
+  int y0 = (x0 + n) % g.L0;
+  if (y0 < 0) y0 += g.L0;
+  const int py = (p + n) & 1;
+  const long long jy = (long long)y0 * g.V3h + sidx;
+  for (int mu = 0; mu < 4; ++mu) store_U(out, g.Vhp, p, j, mu, load_U(in, g.Vhp, py, jy, mu));
 }
 
 // elementwise helpers on full FP64 spinor fields (both parities, valid sites only)
@@ -403,11 +423,15 @@ __global__ void k_axpy_mom(long long n, double* p, double c, const double* F) {
 static inline unsigned site_blocks(const Geo& g) { return (unsigned)((g.Vh + 127) / 128); }
 
 void launch_pair_force(const Geo& g, double* F, double coef_times_minus_kappa, const double2* a, const double2* b,
-                       const double2* U, int lb, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_force, dim3(site_blocks(g)), dim3(256), 0, s, g, F, coef_times_minus_kappa, a, b, U, lb);
+                       const double2* U, int lb, hipStream_t s, const double* sx) {
+  hipLaunchKernelGGL(k_pair_force, dim3(site_blocks(g)), dim3(256), 0, s, g, F, coef_times_minus_kappa, a, b, U, lb,
+                     sx);
 }
-void launch_gauge_force(const Geo& g, double* F, double c, const double2* U, hipStream_t s) {
-  hipLaunchKernelGGL(k_gauge_force, dim3(site_blocks(g)), dim3(256), 0, s, g, F, c, U);
+void launch_gauge_force(const Geo& g, double* F, double c, const double2* U, hipStream_t s, const double* sx) {
+  hipLaunchKernelGGL(k_gauge_force, dim3(site_blocks(g)), dim3(256), 0, s, g, F, c, U, sx);
+}
+void launch_shift_links(const Geo& g, double2* out, const double2* in, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_shift_links, dim3(site_blocks(g)), dim3(256), 0, s, g, out, in, n);
 }
 void launch_plaq_sum(const Geo& g, const double2* U, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_plaq, dim3(site_blocks(g)), dim3(256), 0, s, g, U, part);
@@ -421,8 +445,8 @@ void launch_norm2_full(const Geo& g, const double2* f, double* part, double* out
   hipLaunchKernelGGL(k_norm2_full, dim3(site_blocks(g)), dim3(256), 0, s, g, f, part);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, (int)site_blocks(g), part, out);
 }
-void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_links, dim3(site_blocks(g)), dim3(256), 0, s, g, U, P, dt);
+void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s, const double* sx) {
+  hipLaunchKernelGGL(k_update_links, dim3(site_blocks(g)), dim3(256), 0, s, g, U, P, dt, sx);
 }
 void launch_spin_op(const Geo& g, int mode, int l0, double2* out, const double2* in, const double2* in2,
                     hipStream_t s) {

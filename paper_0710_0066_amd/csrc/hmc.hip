@@ -27,6 +27,8 @@ struct ForceWS {
   double* part;        // reduction partials (one per 128-site tile pair)
   double* scal;        // device scalars
   double* h_scal;      // pinned host mirror
+  double* sx;          // per-link step scale s_mu(x0), [L0][4]
+  double2* Utmp;       // gauge field scratch (translations)
   long long iters;     // inner iterations accumulated by the drivers below
 };
 
@@ -43,6 +45,8 @@ int sap_force_create(sap_ctx* c) {
   ok = ok && hipMalloc((void**)&w->part, (size_t)((c->Vh + 127) / 128 + 8) * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&w->scal, 64 * 8) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&w->h_scal, 64 * 8, 0) == hipSuccess;
+  ok = ok && hipMalloc((void**)&w->sx, (size_t)c->geom.L[0] * 4 * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&w->Utmp, (size_t)72 * c->Vhp * sizeof(double2)) == hipSuccess;
   if (!ok) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the force workspace");
   for (int i = 0; i < 9; ++i) (void)hipMemset(w->f[i], 0, fb);
   return SAP_OK;
@@ -57,6 +61,8 @@ void sap_force_destroy(sap_ctx* c) {
   if (w->part) (void)hipFree(w->part);
   if (w->scal) (void)hipFree(w->scal);
   if (w->h_scal) (void)hipHostFree(w->h_scal);
+  if (w->sx) (void)hipFree(w->sx);
+  if (w->Utmp) (void)hipFree(w->Utmp);
   delete w;
   c->forces = nullptr;
 }
@@ -117,7 +123,7 @@ int check_opts(sap_ctx* c, const sap_solve_opts* o) {
 }
 
 int pf_force(sap_ctx* c, double* F, double coef, const double2* phi, const sap_solve_opts* o, double* S,
-             hipStream_t s) {
+             hipStream_t s, const double* sx = nullptr) {
   ForceWS* w = fws(c);
   const int l0 = c->geom.l0;
   double2 *X = w->f[0], *T = w->f[1], *Y = w->f[2];
@@ -128,13 +134,13 @@ int pf_force(sap_ctx* c, double* F, double coef, const double2* phi, const sap_s
   if ((rc = solve1(c, Y, T, l0, SAP_ALL, o, s))) return rc;
   launch_spin_op(c->g, 0, l0, Y, Y, nullptr, s);
   // F += coef * (-2 Re <Y, dW1 X>)
-  launch_pair_force(c->g, F, c->geom.kappa * coef, Y, X, c->U64, l0, s);
+  launch_pair_force(c->g, F, c->geom.kappa * coef, Y, X, c->U64, l0, s, sx);
   SAP_HIP_CHECK(c, hipGetLastError());
   return SAP_OK;
 }
 
 int schwarz_terms(sap_ctx* c, double* F, double coef, const double2* chi, const sap_solve_opts* o,
-                  double* S_R, hipStream_t s) {
+                  double* S_R, hipStream_t s, const double* sx = nullptr) {
   ForceWS* w = fws(c);
   const int l0 = c->geom.l0;
   double2 *v = w->f[3], *psi = w->f[4], *eta = w->f[5], *t = w->f[6];
@@ -148,9 +154,9 @@ int schwarz_terms(sap_ctx* c, double* F, double coef, const double2* chi, const 
   launch_spin_op(c->g, 0, l0, t, t, nullptr, s);
   if ((rc = solve1(c, v, t, 0, SAP_ALL, o, s))) return rc;       // xi = g5 M^{-1} g5 Pi eta
   launch_spin_op(c->g, 0, l0, v, v, nullptr, s);
-  launch_pair_force(c->g, F, -c->geom.kappa * coef, v, psi, c->U64, 0, s);
+  launch_pair_force(c->g, F, -c->geom.kappa * coef, v, psi, c->U64, 0, s, sx);
   launch_spin_op(c->g, 2, l0, t, v, nullptr, s);                 // P_Om* xi
-  launch_pair_force(c->g, F, c->geom.kappa * coef, t, chi, c->U64, 0, s);
+  launch_pair_force(c->g, F, c->geom.kappa * coef, t, chi, c->U64, 0, s, sx);
   SAP_HIP_CHECK(c, hipGetLastError());
   return SAP_OK;
 }
@@ -208,20 +214,21 @@ struct Traj {
   const sap_hmc_params* P;
   const double2 *phi1, *chi;
   hipStream_t s;
+  const double* sx;    // per-link step scale (device) or null
 };
 
 int kick_pf(Traj& T, double dt) {
-  int rc = pf_force(T.c, fws(T.c)->mom, -dt, T.phi1, &T.P->force_solve, nullptr, T.s);
+  int rc = pf_force(T.c, fws(T.c)->mom, -dt, T.phi1, &T.P->force_solve, nullptr, T.s, T.sx);
   if (rc) return rc;
-  return schwarz_terms(T.c, fws(T.c)->mom, -dt, T.chi, &T.P->force_solve, nullptr, T.s);
+  return schwarz_terms(T.c, fws(T.c)->mom, -dt, T.chi, &T.P->force_solve, nullptr, T.s, T.sx);
 }
 int kick_g(Traj& T, double dt) {
-  launch_gauge_force(T.c->g, fws(T.c)->mom, -dt * T.P->beta / 6.0, T.c->U64, T.s);
+  launch_gauge_force(T.c->g, fws(T.c)->mom, -dt * T.P->beta / 6.0, T.c->U64, T.s, T.sx);
   SAP_HIP_CHECK(T.c, hipGetLastError());
   return SAP_OK;
 }
 int move_links(Traj& T, double dt) {
-  launch_update_links(T.c->g, T.c->U64, fws(T.c)->mom, dt, T.s);
+  launch_update_links(T.c->g, T.c->U64, fws(T.c)->mom, dt, T.s, T.sx);
   links_changed(T.c, T.s);
   SAP_HIP_CHECK(T.c, hipGetLastError());
   return SAP_OK;
@@ -349,6 +356,19 @@ int sap_plaquette(sap_ctx* c, double* plaq_out, void* stream) {
   return SAP_OK;
 }
 
+int sap_shift_gauge(sap_ctx* c, int n, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
+  hipStream_t s = (hipStream_t)stream;
+  ForceWS* w = fws(c);
+  launch_shift_links(c->g, w->Utmp, c->U64, n, s);
+  SAP_HIP_CHECK(c, hipMemcpyAsync(c->U64, w->Utmp, (size_t)72 * c->Vhp * sizeof(double2),
+                                  hipMemcpyDeviceToDevice, s));
+  links_changed(c, s);
+  SAP_HIP_CHECK(c, hipGetLastError());
+  return SAP_OK;
+}
+
 int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream);
 int sap_get_gauge(sap_ctx* ctx, double* U, void* stream);
 int sap_pack_spinor(sap_ctx* ctx, void* out, const double* in, int nrhs, sap_prec prec, void* stream);
@@ -366,8 +386,14 @@ int hmc_trajectory(sap_ctx* c, double* U, const sap_hmc_params* P, sap_hmc_info*
     return sap_fail(c, SAP_E_ARG, "tau must be > 0, beta and lambda finite");
   int rc;
   if ((rc = check_opts(c, &P->force_solve)) || (rc = check_opts(c, &P->action_solve))) return rc;
+  if (P->step_scale)
+    for (int i = 0; i < 4 * c->geom.L[0]; ++i)
+      if (!(P->step_scale[i] >= 0.0 && std::isfinite(P->step_scale[i])))
+        return sap_fail(c, SAP_E_ARG, "step_scale entries must be finite and >= 0");
   hipStream_t s = (hipStream_t)stream;
   ForceWS* w = fws(c);
+  if (P->step_scale)
+    SAP_HIP_CHECK(c, hipMemcpyAsync(w->sx, P->step_scale, (size_t)4 * c->geom.L[0] * 8, hipMemcpyHostToDevice, s));
   w->iters = 0;
   std::memset(info, 0, sizeof(*info));
   if ((rc = sap_set_gauge(c, U, stream))) return rc;
@@ -387,7 +413,7 @@ int hmc_trajectory(sap_ctx* c, double* U, const sap_hmc_params* P, sap_hmc_info*
   if ((rc = sap_pack_spinor(c, w->f[0], P->xi2, 1, SAP_F64, stream))) return rc;
   if ((rc = heat_bath(c, chi, w->f[0], &P->action_solve, s))) goto fail;
   {
-    Traj T = {c, P, phi1, chi, s};
+    Traj T = {c, P, phi1, chi, s, P->step_scale ? w->sx : nullptr};
     double K0, K1;
     if ((rc = hamiltonian(T, &K0, &info->S_G0, &info->S_W0, &info->S_R0))) goto fail;
     info->H0 = K0 + info->S_G0 + info->S_W0 + info->S_R0;
@@ -398,11 +424,9 @@ int hmc_trajectory(sap_ctx* c, double* U, const sap_hmc_params* P, sap_hmc_info*
     info->H1 = K1 + info->S_G1 + info->S_W1 + info->S_R1;
     info->dH = info->H1 - info->H0;
     info->accepted = P->u_metropolis < std::exp(-info->dH);
-    if (info->accepted) {
-      if ((rc = sap_get_gauge(c, U, stream))) goto fail;
-    } else if ((rc = sap_set_gauge(c, U, stream))) {
-      goto fail;
-    }
+    if (!info->accepted && (rc = sap_set_gauge(c, U, stream))) goto fail;
+    if (P->time_shift && (rc = sap_shift_gauge(c, P->time_shift, stream))) goto fail;
+    if ((info->accepted || P->time_shift) && (rc = sap_get_gauge(c, U, stream))) goto fail;
     info->solver_iters = w->iters;
     if ((rc = sap_plaquette(c, &info->plaq, stream))) return rc;
     return SAP_OK;

@@ -249,3 +249,35 @@ def test_hmc_trajectory_16x16x16x32(gu):
     assert abs(info.S_W0 - float(np.sum(np.abs(xi1) ** 2))) <= 1e-8 * info.S_W0
     assert abs(info.S_R0 - float(np.sum(np.abs(schwarz.Pi(xi2, L, l0)) ** 2))) <= 1e-8 * info.S_R0
     assert info.accepted == (u < np.exp(-info.dH))
+
+
+def test_hmc_step_profile_and_time_shift_match_oracle(gu):
+    """x0-dependent step sizes (Sec. 2, scheme B: one period of 8 slices, inactive links with
+    s = 0) and the x0 translation after the trajectory, against the oracle."""
+    import paper_0710_0066_amd as sap
+    L, l0, k, beta, tau = (8, 4, 2, 4), 2, 0.15, 5.6, 0.5
+    print("hmc step profile / shift vs oracle", flush=True)
+    U = synth.gauge_field(L, 0.3, 90)
+    p0, xi1, xi2 = _hmc_inputs(L, 91)
+    prof = hmc.step_profile("B", L[0])
+    mk = lambda V: schwarz.Solvers(V, k, l0, tol=1e-13)
+    phi1 = dirac.apply_W(U, xi1, k, l0)
+    chi = schwarz.heat_bath(U, xi2, k, l0, mk(U))
+    lev = hmc.schwarz_two_level(phi1, chi, k, beta, l0, 3, 2, mk)
+    U_ref, acc_ref, dH_ref, H0_ref, _ = hmc.trajectory(lev, U, p0, tau, 0.0, scale=prof, shift=3)
+    ctx = gu.make_ctx(L, l0, k, U)
+    fU = gu.dev(U).clone()
+    o = _opts(sap, tol=1e-13)
+    prm = sap.hmc_params(beta, tau, 3, 2, _mom_to_sap(ctx, gu, p0), gu.dev(xi1), gu.dev(xi2), 0.0, o, o,
+                         step_scale=prof, time_shift=3)
+    info = sap.hmc_trajectory(ctx, fU, prm)
+    print(f"  dH gpu {info.dH:.12e} oracle {dH_ref:.12e}", flush=True)
+    assert info.accepted == 1 and acc_ref
+    assert abs(info.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref))
+    assert np.max(np.abs(fU.cpu().numpy().reshape(U.shape) - U_ref)) <= 1e-9
+    # sap_shift_gauge alone
+    ctx.set_gauge(gu.dev(U))
+    sap.sap_shift_gauge(ctx, -5)
+    Uo = torch.zeros(U.size, dtype=torch.complex128, device="cuda")
+    ctx.get_gauge(Uo)
+    assert np.array_equal(Uo.cpu().numpy().reshape(U.shape), hmc.time_shift(U, -5))

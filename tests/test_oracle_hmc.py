@@ -69,3 +69,56 @@ def test_pure_gauge_trajectory_metropolis():
     assert acc and abs(dH) < 0.5
     Uo2, acc2, *_ = hmc.trajectory(lev, U, p, 1.0, u_metropolis=np.nextafter(np.exp(-dH), 2))
     assert (not acc2) and np.array_equal(Uo2, U)
+
+
+def test_step_size_schemes_match_the_paper():
+    """Sec. 2 schemes A/B/C: the tables as printed (golden fixture), the stated averages over
+    all links (A: 0.525, B and C: about 0.59), links with s = 0 stay fixed."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "step_size_schemes.json")))
+    for name in "ABC":
+        sp, tm = hmc.STEP_SCHEMES[name]
+        spec = g[name]
+        assert list(tm) == spec["time"]
+        assert list(sp) == spec.get("spatial_read", spec.get("spatial"))
+        prof = hmc.step_profile(name, spec["L0"])
+        avg = prof.mean()
+        if name == "A":
+            assert abs(avg - 0.525) < 1e-15
+            printed = np.array(spec["spatial_printed"])
+            assert abs((3 * printed.mean() + np.mean(tm)) / 4 - 0.75) < 1e-15   # the misprint
+        else:
+            assert abs(avg - 0.59) < 0.015
+    assert hmc.step_profile("B", 32).mean() == 19 / 32
+    assert hmc.step_profile("C", 32).mean() == 37 / 64
+    # active links of scheme B: 23 of 32 per period -> about 72 %
+    assert np.mean(hmc.step_profile("B", 32) > 0) == 23 / 32
+
+
+def test_step_profile_md_is_reversible_and_keeps_inactive_links():
+    L, l0, k = (8, 2, 2, 2), 2, 0.15
+    U = synth.gauge_field(L, 0.4, 80)
+    p = synth.gaussian_momenta(L, 81)
+    sc = np.tile(np.array([[0.0, 0.5, 1.0, 1.0], [0.5, 1.0, 0.25, 0.0]]), (4, 1))   # [L0, 4]
+    lev = _levels(L, U, k, l0, n_outer=2, n_inner=2)
+    U1, p1 = hmc.integrate(lev, U, p, 0.3, sc)
+    U2, p2 = hmc.integrate(lev, U1, -p1, 0.3, sc)
+    assert np.max(np.abs(U2 - U)) <= 1e-10
+    frozen = sc == 0
+    for x0, mu in zip(*np.nonzero(frozen)):
+        assert np.array_equal(U1[x0, :, :, :, mu], U[x0, :, :, :, mu])
+
+
+def test_time_shift_preserves_the_action():
+    L, l0, k = (8, 2, 2, 2), 2, 0.15
+    U = synth.gauge_field(L, 0.4, 82)
+    Ut = hmc.time_shift(U, 3)
+    assert abs(forces.gauge_action(Ut, 5.6) - forces.gauge_action(U, 5.6)) < 1e-10
+    # det M is translation invariant: |M^{-1} phi|^2 for a translated phi agrees
+    phi = synth.gaussian_spinor(L, 83)
+    S1 = forces.pf_action(U, phi, k, None, W_inv=solvers.lu_solver(U, k, None))
+    phit = np.roll(phi, -3, axis=0)
+    phit[-3:] *= -1.0                       # the antiperiodic wrap moves with the field
+    S2 = forces.pf_action(Ut, phit, k, None, W_inv=solvers.lu_solver(Ut, k, None))
+    assert abs(S1 - S2) < 1e-9 * S1
