@@ -1,0 +1,132 @@
+"""Pins of the oracle's BiCGstab, Schwarz alternating procedure and geometric series
+(Sec. 3: geometric series for the block terms, BiCGstab with even-odd and Schwarz
+preconditioning for the full-lattice term) against facts that do not come from the
+oracle: Krylov finite termination, numpy's dense solve, the exact vanishing of the SAP
+residual on the colour updated last, and the free-field spectrum, which fixes the
+convergence rate of the geometric series in closed form."""
+import numpy as np
+
+import synth
+from oracle import dirac, lattice, solvers
+
+
+def test_bicgstab_terminates_for_three_eigenvalues():
+    """A = diag(d) with d taking three distinct complex values: the minimal polynomial has
+    degree 3, so BiCGstab reaches the exact solution b / d within 3 iterations."""
+    L = (2, 2, 2, 4)
+    b = synth.gaussian_spinor(L, 7)
+    lam = np.array([1.5 + 0.5j, 0.7 - 0.2j, 2.0 + 1.0j])
+    d = lam[np.arange(b.size).reshape(b.shape) % 3]
+    x, its, res = solvers.bicgstab(lambda v: d * v, b, tol=1e-13)
+    assert its <= 3
+    assert np.max(np.abs(x - b / d)) <= 1e-12 * np.max(np.abs(b / d))
+
+
+def test_bicgstab_matches_dense_solve_with_and_without_preconditioner():
+    rng = np.random.default_rng(3)
+    L = (2, 2, 2, 2)
+    n = 12 * 16
+    A = np.eye(n) * 4 + (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(n)
+    b = synth.gaussian_spinor(L, 8, nrhs=2)
+    op = lambda v: (v.reshape(v.shape[0], n) @ A.T).reshape(v.shape)
+    ref = np.linalg.solve(A, b.reshape(2, n).T).T.reshape(b.shape)
+    Kd = 1.0 / np.diag(A)
+    K = lambda v: (v.reshape(v.shape[0], n) * Kd).reshape(v.shape)
+    for prec in (None, K):
+        x, its, res = solvers.bicgstab(op, b, tol=1e-13, K=prec)
+        assert np.all(np.asarray(res) <= 1e-13)
+        assert np.max(np.abs(x - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_eo_bicgstab_matches_dense_lu():
+    L, k = (4, 4, 4, 4), 0.155
+    U = synth.gauge_field(L, 0.5, 1001)
+    b = synth.gaussian_spinor(L, 2001)
+    for l0 in (None, 2):
+        A = dirac.dense_matrix(U, k, l0)
+        ref = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+        x, its, res = solvers.solve_eo_bicgstab(U, b, k, l0, tol=1e-12)
+        assert res <= 1e-12
+        assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= np.linalg.cond(A) * 1e-12
+
+
+def test_sap_residual_vanishes_on_the_last_colour():
+    """After a Schwarz cycle (black blocks, then white blocks, exact block solves) the
+    residual r - M x is zero on the white blocks: every hop leaving a white block ends on
+    a black site, so M and W_l0 agree on the white sites for a field supported on them."""
+    L, l0, k = (8, 2, 2, 4), 2, 0.15
+    U = synth.gauge_field(L, 0.5, 11)
+    r = synth.gaussian_spinor(L, 12)
+    x = solvers.sap_precond(U, r, k, l0, ncy=1, block_tol=1e-14)
+    res = r - dirac.apply_M(U, x, k)
+    white = lattice.site_mask(L, lattice.colour_x0_mask(L, l0, "white"))
+    black = lattice.site_mask(L, lattice.colour_x0_mask(L, l0, "black"))
+    assert np.max(np.abs(res * white)) <= 1e-12 * np.max(np.abs(r))
+    assert np.max(np.abs(res * black)) > 1e-3 * np.max(np.abs(r))
+
+
+def test_sap_cycles_converge_to_the_inverse_and_precondition_bicgstab():
+    L, l0, k = (8, 2, 2, 4), 2, 0.15
+    U = synth.gauge_field(L, 0.5, 13)
+    r = synth.gaussian_spinor(L, 14)
+    ref = np.linalg.solve(dirac.dense_matrix(U, k), r.reshape(-1)).reshape(r.shape)
+    errs = [np.linalg.norm(solvers.sap_precond(U, r, k, l0, n, 1e-14) - ref) / np.linalg.norm(ref)
+            for n in (1, 2, 4, 8)]
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-3 * errs[0], errs
+    x, its, res = solvers.solve_sap_bicgstab(U, r, k, l0, ncy=2, tol=1e-12, block_tol=1e-14)
+    assert res <= 1e-12
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1e-10
+    _, its_plain, _ = solvers.bicgstab(lambda v: dirac.apply_M(U, v, k), r, tol=1e-12)
+    assert its < its_plain
+
+
+def _free_field(L):
+    U = np.zeros(tuple(L) + (4, 3, 3), dtype=complex)
+    U[...] = np.eye(3)
+    return U
+
+
+def _free_spectral_radius(L, kappa):
+    """kappa^2 max_p |lambda(p)|^2 of D_eo D_oe on the free field: D acts on a plane wave
+    as a - i sum_mu gamma_mu b_mu with a = sum 2 cos p_mu, b_mu = 2 sin p_mu (a normal
+    matrix with eigenvalues a +/- i|b|); p_0 = (2 n + 1) pi / L0 (antiperiodic),
+    p_k = 2 pi n / L_k; D_eo D_oe has the squares of these eigenvalues."""
+    ps = [(2 * np.arange(L[0]) + 1) * np.pi / L[0]] + [2 * np.pi * np.arange(n) / n for n in L[1:]]
+    P = np.meshgrid(*ps, indexing="ij")
+    a = sum(2 * np.cos(p) for p in P)
+    b2 = sum(4 * np.sin(p) ** 2 for p in P)
+    return kappa ** 2 * np.max(a ** 2 + b2)
+
+
+def test_geometric_series_rate_is_the_free_field_spectral_radius():
+    """On the free field the residual of the series after N terms falls by the spectral
+    radius rho = kappa^2 max|lambda(D)|^2 per term (closed form from the free Wilson
+    spectrum): rho < 1 converges, rho > 1 diverges."""
+    L = (4, 4, 4, 4)
+    U = _free_field(L)
+    b = synth.gaussian_spinor(L, 21)
+    for k in (0.12, 0.13):
+        rho = _free_spectral_radius(L, k)
+        assert rho < 1.0
+        r60 = solvers.geometric_series(U, b, k, tol=0.0, maxiter=60)[2]
+        r70 = solvers.geometric_series(U, b, k, tol=0.0, maxiter=70)[2]
+        assert abs(r70 / r60 - rho ** 10) <= 2e-3 * rho ** 10, (k, r70 / r60, rho ** 10)
+    k = 0.14
+    rho = _free_spectral_radius(L, k)
+    assert rho > 1.0
+    r30 = solvers.geometric_series(U, b, k, tol=0.0, maxiter=30)[2]
+    r40 = solvers.geometric_series(U, b, k, tol=0.0, maxiter=40)[2]
+    assert r40 > r30 > 1.0
+    assert abs(r40 / r30 - rho ** 10) <= 2e-2 * rho ** 10
+
+
+def test_geometric_series_matches_dense_lu_on_blocks():
+    L, k = (4, 4, 4, 4), 0.155
+    U = synth.gauge_field(L, 0.5, 1001)
+    b = synth.gaussian_spinor(L, 2001)
+    A = dirac.dense_matrix(U, k, 2)
+    ref = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    x, n, res = solvers.geometric_series(U, b, k, 2, tol=1e-12)
+    assert res <= 1e-12 and n > 1
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= np.linalg.cond(A) * 1e-12
