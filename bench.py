@@ -49,6 +49,8 @@ def parse():
                     help="operator timed by --only-dslash (profiler runs)")
     ap.add_argument("--prec", choices=["f64", "f32"], default="f32")
     ap.add_argument("--nrhs", type=int, default=12)
+    ap.add_argument("--hop-map", type=int, default=-1,
+                    help="with --only-dslash: force this hop mapping (HOP_MAP_*) instead of the tuned one")
     ap.add_argument("--skip-solve", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--only-dslash", action="store_true",
@@ -245,7 +247,10 @@ def main():
         return lambda s: sap.apply_M(ctx, fout, fin, 1, PREC[prec])
 
     if args.only_dslash:       # one operator only, for profiler runs
-        sap.sap_tune(ctx, args.nrhs if args.op == "eo" else 1)
+        n_op = args.nrhs if args.op == "eo" else 1
+        sap.sap_tune(ctx, n_op)
+        if args.hop_map >= 0:
+            sap.sap_set_hop_map(ctx, int(args.op == "M"), PREC[args.prec], n_op, args.hop_map)
         fn = eo(args.prec, args.nrhs) if args.op == "eo" else full(args.prec)
         ms = time_op(sap, torch, fn, args.steps, args.warmup)
         print(f"[bench] {args.op} {args.prec} nrhs={args.nrhs if args.op == 'eo' else 1}: "

@@ -177,25 +177,29 @@ int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parit
                     void* stream);
 
 /* Autotuner of the hop kernel for nrhs right-hand sides (1 <= nrhs <= max_rhs): times each
- * work-item mapping (one rhs per work-item; 4 rhs sharing link loads within a wavefront;
- * 4 rhs on the 4 wavefronts of a workgroup; for the even-odd hop also an x0-streaming
- * kernel that keeps time neighbours in registers and stages each input slice in LDS) on
- * this context's lattice for the full operator and the even-odd hop in FP64 and FP32,
- * and keeps the fastest for every later call with that nrhs (apply_M, apply_W1_block,
- * apply_Dslash_eo and the solvers). us_out (host, may be NULL): 16 floats, microseconds
- * per launch (-1: not applicable), ordered [full f64 x4, full f32 x4, even-odd f64 x4,
- * even-odd f32 x4] over the mappings [site, lane4, wave4, stream]. Uses the solver
- * workspace; synchronises. Untuned calls use the 4-rhs-per-wavefront mapping. */
+ * work-item mapping on this context's lattice for the full operator and the even-odd hop
+ * in FP64 and FP32, and keeps the fastest for every later call with that nrhs (apply_M,
+ * apply_W1_block, apply_Dslash_eo and the solvers). The mappings: 0 site (one rhs per
+ * work-item), 1 lane4 (4 rhs sharing link loads within a wavefront), 2 wave4 (4 rhs on
+ * the 4 wavefronts of a workgroup), 3 stream (even-odd hop only: x0-streaming, time
+ * neighbours kept in registers, each input slice staged in LDS), 4..6 = 0..2 with the
+ * workgroups rhs-slowest, 7 / 8 reg2 / reg4 (each loaded link applied to 2 / 4 rhs held in
+ * registers), 9 / 10 reg2 / reg4 group-slowest, 11 / 12 / 13 march1 / 2 / 4 (regN with
+ * each of the 8 XCDs owning 1/8 of every x0 slice and walking the slices in increasing
+ * x0), 14 / 15 walk1 / walk2 (even-odd hop: each work-item walks 8 slices at a fixed
+ * spatial site with 1 / 2 rhs, loads every time neighbour once and carries its
+ * projection in registers; the full operator runs them as march1 / march2). us_out
+ * (host, may be NULL): 64 floats, microseconds per launch (-1: not applicable), ordered
+ * [full f64, full f32, even-odd f64, even-odd f32] x the 16 mappings. Uses the solver
+ * workspace; synchronises. Untuned calls use site for one rhs and lane4 for several. */
 int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
-/* (us_out holds 44 floats: 4 operator kinds x 11 mappings [site, lane4, wave4, stream,
- *  site+sweep, lane4+sweep, wave4+sweep, reg2, reg4, reg2+sweep, reg4+sweep]; "sweep"
- *  orders the workgroups rhs-slowest, "regN" applies each loaded link to N rhs held in
- *  registers.) */
 
 /* Set the hop mapping used for nrhs right-hand sides by hand (map: 0 site, 1 lane4,
  * 2 wave4, 3 stream (even-odd hop only, full = 0), 4..6 = 0..2 with rhs-slowest workgroup
- * order, 7 reg2, 8 reg4, 9 / 10 reg2 / reg4 group-slowest; -1 restores the default), for the full
- * operator (full = 1) or the even-odd hop (full = 0) at precision prec. */
+ * order, 7 reg2, 8 reg4, 9 / 10 reg2 / reg4 group-slowest, 11 / 12 / 13 x0-marching with
+ * 1 / 2 / 4 rhs per work-item, 14 / 15 x0-walking with 1 / 2 rhs (march1 / march2 for
+ * the full operator); -1 restores the default), for the full operator (full = 1) or the
+ * even-odd hop (full = 0) at precision prec. */
 int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);
 
 /* ---- solvers ------------------------------------------------------------------ */
@@ -257,6 +261,16 @@ int gauge_force(sap_ctx* ctx, double* F, double coef, double beta, double* S_G_o
  * U_mu(x) <- exp(i dt P_mu(x)) U_mu(x), P = sum_a p^a T^a from the sap-layout momenta p
  * (FP64 exponential, reunitarised). */
 int sap_update_links(sap_ctx* ctx, const double* p, double dt, void* stream);
+
+/* x0 profile of a force (the analogue of Sec. 4's plot of the average force on the spatial
+ * links against x0). F (device): a force / momentum field in the sap momenta layout
+ * (sap_momenta_bytes), e.g. the output of gauge_force, block_pf_force or
+ * schwarz_boundary_force. prof (host, 2*L0 doubles) receives
+ *   prof[x0]      = mean over the sites x of slice x0 and mu = 1, 2, 3 of |F(x, mu)|,
+ *   prof[L0 + x0] = mean over the sites x of slice x0 of |F(x, 0)|,
+ * |F| = (sum_a F^a F^a)^(1/2), the norm of the su(3) element in the T^a = lambda^a/2
+ * basis. Fixed-order sums (deterministic); needs no gauge field; synchronises. */
+int sap_force_profile(sap_ctx* ctx, const double* F, double* prof, void* stream);
 
 /* Translate the context's gauge field by n slices in x0: U'(x0, ...) = U(x0 + n, ...)
  * (Sec. 2: shift after each trajectory for ergodicity of the inactive links). */

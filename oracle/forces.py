@@ -134,3 +134,14 @@ def gauge_force(U, beta):
         for c in range(8):
             F[:, :, :, :, mu, c] = -beta / 3.0 * np.trace(1j * T[c] @ UA, axis1=-2, axis2=-1).real
     return F
+
+
+def force_profile(F):
+    """x0 profile of a force field F[x0, x1, x2, x3, mu, a] (Sec. 4, the plot of the average
+    force on the spatial links against x0): row 0 = mean over the sites of each slice and
+    over mu = 1, 2, 3 of |F(x, mu)|, row 1 = the same for mu = 0, where |F| is the
+    Euclidean norm of the eight components F^a."""
+    n = np.sqrt(np.sum(F ** 2, axis=-1))                 # [L0, L1, L2, L3, 4]
+    spatial = n[..., 1:].mean(axis=(1, 2, 3, 4))
+    time = n[..., 0].mean(axis=(1, 2, 3))
+    return np.stack([spatial, time])

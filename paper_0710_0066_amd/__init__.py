@@ -99,6 +99,7 @@ _SIGS = {
     "sap_update_links": ([_P, _P, _D, _P], _I),
     "sap_plaquette": ([_P, _P, _P], _I),
     "sap_shift_gauge": ([_P, _I, _P], _I),
+    "sap_force_profile": ([_P, _P, _P, _P], _I),
     "sap_tune": ([_P, _I, _P, _P], _I),
     "sap_set_hop_map": ([_P, _I, _I, _I, _I], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
@@ -215,21 +216,33 @@ def sap_plaquette(ctx):
 
 def sap_tune(ctx, nrhs):
     """Tune the hop mapping for nrhs; returns microseconds per launch per variant."""
-    us = (ctypes.c_float * 44)()
+    us = (ctypes.c_float * (4 * HOP_NMAP))()
     _check(ctx.ptr, _lib.sap_tune(ctx.ptr, nrhs, us, _stream()))
     names = ["full_f64", "full_f32", "eo_f64", "eo_f32"]
     maps = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4",
-            "reg2_sweep", "reg4_sweep"]
-    return {n: {m: us[11 * i + k] for k, m in enumerate(maps) if us[11 * i + k] >= 0}
+            "reg2_sweep", "reg4_sweep", "march1", "march2", "march4", "walk1", "walk2"]
+    return {n: {m: us[HOP_NMAP * i + k] for k, m in enumerate(maps) if us[HOP_NMAP * i + k] >= 0}
             for i, n in enumerate(names)}
 
 
 HOP_MAP_SITE, HOP_MAP_LANE4, HOP_MAP_WAVE4, HOP_MAP_STREAM, HOP_SWEEP = 0, 1, 2, 3, 4
 HOP_MAP_REG2, HOP_MAP_REG4, HOP_MAP_REG2_SWEEP, HOP_MAP_REG4_SWEEP = 7, 8, 9, 10
+HOP_MAP_MARCH1, HOP_MAP_MARCH2, HOP_MAP_MARCH4 = 11, 12, 13
+HOP_MAP_WALK1, HOP_MAP_WALK2 = 14, 15
+HOP_NMAP = 16
 
 
 def sap_set_hop_map(ctx, full, prec, nrhs, hop_map):
     _check(ctx.ptr, _lib.sap_set_hop_map(ctx.ptr, int(full), prec, nrhs, hop_map))
+
+
+def sap_force_profile(ctx, F):
+    """x0 profile of the force F (sap momenta layout): a list of two lists of L0 floats,
+    [mean |F| over the spatial links of each slice, mean |F| over its time links]."""
+    L0 = ctx.L[0]
+    out = (ctypes.c_double * (2 * L0))()
+    _check(ctx.ptr, _lib.sap_force_profile(ctx.ptr, _ptr(F), out, _stream()))
+    return [list(out[:L0]), list(out[L0:])]
 
 
 def sap_shift_gauge(ctx, n):

@@ -368,20 +368,128 @@ __global__ __launch_bounds__(S) void hop_stream_kernel(HopArgs<R> A, int T, int 
   }
 }
 
-// Register-blocked hop: one work-item per site and group of NR right-hand sides; each
-// link is loaded once and applied to the NR input spinors, so link traffic falls by NR
-// with no reliance on caches, while each rhs keeps the single-rhs access pattern (64
-// consecutive sites per wavefront). Workgroups are ordered group-fastest.
+// Pieces of the register-blocked hop on one output site j of parity p for the right-hand
+// sides r0 .. r0 + nr - 1 (nr <= NR): each loaded link is applied to the nr input spinors.
+
+// is the output site in a selected x0 block (always true without a block restriction)?
+template <class R>
+__device__ __forceinline__ bool hop_selected(const HopArgs<R>& A, int x0) {
+  if (!A.slb) return true;
+  const int blk = x0 / A.slb;
+  if (A.block >= 0) return blk == A.block;
+  return (A.colour == 0) || ((A.colour == 1) == ((blk & 1) == 1));
+}
+
+// acc[r] += the hops of direction mu (dir 0 forward, 1 backward), if present
+template <class R, int NR>
+__device__ __forceinline__ void hop_dir(const HopArgs<R>& A, int p, long long j, const Site& s, int mu, int dir,
+                                        int r0, int nr, cx<R> acc[NR][4][3]) {
+  typedef typename vec2<R>::type V2;
+  const Geo& g = A.g;
+  const bool on = dir == 0 ? !(A.lb && mu == 0 && (s.x0 % A.lb) == A.lb - 1)
+                           : !(A.lb && mu == 0 && (s.x0 % A.lb) == 0);
+  if (!on) return;
+  const V2* inb = A.in.ptr + (1 - p) * A.in.ps;
+  const bool g5i = A.g5_in != 0;
+  const long long jn = nbr(g, s, j, mu, dir == 0 ? +1 : -1);
+  cx<R> m[9];
+  if (dir == 0) load_link<R>(A.U, g.Vhp, mu, p, j, m);
+  else load_link<R>(A.U, g.Vhp, mu, 1 - p, jn, m);
+  const bool flip = mu == 0 && (dir == 0 ? s.x0 == g.L0 - 1 : s.x0 == 0);
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r < nr) {
+      cx<R> sp[4][3], h[2][3], uh[2][3];
+      load_spinor<R>(inb + (r0 + r) * A.in.rs, jn, g5i, sp);
+      project<R>(mu, dir == 1, sp, h);
+      if (dir == 0) {
+        su3_mul<R>(m, h[0], uh[0]);
+        su3_mul<R>(m, h[1], uh[1]);
+      } else {
+        su3_dag_mul<R>(m, h[0], uh[0]);
+        su3_dag_mul<R>(m, h[1], uh[1]);
+      }
+      if (flip)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+      accum_recon<R>(mu, dir == 1, uh, acc[r]);
+    }
+  }
+}
+
+template <class R> __device__ __forceinline__ void st_nt(typename vec2<R>::type* p, cx<R> a) {
+  __builtin_nontemporal_store(a.r, &p->x);
+  __builtin_nontemporal_store(a.i, &p->y);
+}
+
+// out = a x + b (g5_out) acc, or zero for an unselected site; NT: non-temporal stores
+// (the result is not read again by this launch)
+template <class R, int NR, bool NT>
+__device__ __forceinline__ void hop_store(const HopArgs<R>& A, int p, long long j, int r0, int nr, bool sel,
+                                          cx<R> acc[NR][4][3]) {
+  typedef typename vec2<R>::type V2;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) continue;
+    V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
+    const V2* xp = A.x.ptr ? A.x.ptr + (r0 + r) * A.x.rs + p * A.x.ps + tiled(j, 0, 12) : nullptr;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<R> v = {R(0), R(0)};
+        if (sel) {
+          cx<R> h = acc[r][a][c];
+          if (A.g5_out && a >= 2) h = -h;
+          v = A.b * h;
+          if (xp) {
+            const cx<R> xv = ld<R>(xp + (a * 3 + c) * TILE);
+            v.r += A.a * xv.r;
+            v.i += A.a * xv.i;
+          }
+        }
+        if (NT) st_nt<R>(o + (a * 3 + c) * TILE, v);
+        else st<R>(o + (a * 3 + c) * TILE, v);
+      }
+  }
+}
+
+// all eight hops of output site j
+template <class R, int NR>
+__device__ __forceinline__ void hop_site_rhs(const HopArgs<R>& A, int p, long long j, int r0, int nr) {
+  const Site s = decode(A.g, j, p);
+  const bool sel = hop_selected(A, s.x0);
+  cx<R> acc[NR][4][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r][a][c] = {R(0), R(0)};
+  if (sel) {
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      hop_dir<R, NR>(A, p, j, s, mu, 0, r0, nr, acc);
+      hop_dir<R, NR>(A, p, j, s, mu, 1, r0, nr, acc);
+    }
+  }
+  hop_store<R, NR, false>(A, p, j, r0, nr, sel, acc);
+}
+
+// Register-blocked kernel, chunk order: a workgroup holds 256 consecutive sites of one
+// parity (128 of each for the full operator) for one group of NR rhs; workgroups are
+// ordered group-fastest (SWEEP: group-slowest, each group sweeps the lattice like a
+// small-rhs launch) and renumbered per XCD.
 template <class R, bool FULL, int NR, bool SWEEP>
 __global__ __launch_bounds__(256) void hop_reg_kernel(HopArgs<R> A, long long nchunk) {
-  typedef typename vec2<R>::type V2;
   const long long nwg = gridDim.x;
   const long long w = xcd_logical_block(blockIdx.x, nwg);
   const int ngroups = (A.nrhs + NR - 1) / NR;
   const int r0 = (SWEEP ? (int)(w / nchunk) : (int)(w % ngroups)) * NR;
   const long long chunk = SWEEP ? w % nchunk : w / ngroups;
   if (r0 >= A.nrhs) return;
-  const int nr = min(NR, A.nrhs - r0);
   int p;
   long long j;
   if (FULL) {
@@ -391,95 +499,184 @@ __global__ __launch_bounds__(256) void hop_reg_kernel(HopArgs<R> A, long long nc
     p = A.parity_out;
     j = chunk * 256 + threadIdx.x;
   }
-  const Geo& g = A.g;
-  if (j >= g.Vh) return;
-  const long long Vhp = g.Vhp;
-  const Site s = decode(g, j, p);
-  if (A.slb) {
-    const int blk = s.x0 / A.slb;
-    bool sel;
-    if (A.block >= 0) sel = (blk == A.block);
-    else sel = (A.colour == 0) || ((A.colour == 1) == ((blk & 1) == 1));
-    if (!sel) {
-      cx<R> z = {R(0), R(0)};
-      for (int r = 0; r < nr; ++r) {
-        V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) st<R>(o + c * TILE, z);
-      }
-      return;
-    }
+  if (j >= A.g.Vh) return;
+  hop_site_rhs<R, NR>(A, p, j, r0, min(NR, A.nrhs - r0));
+}
+
+// x0-marching order. The slice-local sites s in [0, V3h) of each parity (site j =
+// x0*V3h + s) are cut into 8 contiguous pieces, one per XCD (the hardware deals
+// workgroup ids round-robin to the 8 XCDs, so id % 8 names the XCD); each XCD walks its
+// piece slice by slice in increasing x0, with all rhs groups of a chunk back to back.
+// The time neighbours of a slice then lie 1/8 of a slice of every rhs behind or ahead in
+// that XCD's stream and are still in its L2, links are shared by the rhs groups through
+// L2, and only spatial neighbours across piece boundaries are fetched by two XCDs. A
+// workgroup is 128 sites of one parity, or 64 sites of each parity for the full operator.
+template <class R, bool FULL, int NR>
+__global__ __launch_bounds__(128) void hop_march_kernel(HopArgs<R> A, int nck) {
+  const int xcd = blockIdx.x & 7;
+  const long long l = blockIdx.x >> 3;
+  const int ngroups = (A.nrhs + NR - 1) / NR;
+  const long long per_slice = (long long)nck * ngroups;
+  const int x0 = (int)(l / per_slice);
+  const long long rem = l - x0 * per_slice;
+  const int chunk = (int)(rem / ngroups);
+  const int r0 = (int)(rem - (long long)chunk * ngroups) * NR;
+  if (x0 >= A.g.L0) return;
+  const int lo = (int)((long long)A.g.V3h * xcd / 8);
+  const int hi = (int)((long long)A.g.V3h * (xcd + 1) / 8);
+  int p, s;
+  if (FULL) {
+    p = threadIdx.x >> 6;
+    s = lo + chunk * 64 + (threadIdx.x & 63);
+  } else {
+    p = A.parity_out;
+    s = lo + chunk * 128 + threadIdx.x;
   }
-  cx<R> acc[NR][4][3];
+  if (s >= hi) return;
+  hop_site_rhs<R, NR>(A, p, (long long)x0 * A.g.V3h + s, r0, min(NR, A.nrhs - r0));
+}
+
+// x0-walking even-odd hop. A work-item owns the slice-local site s (j = x0*V3h + s) of the
+// output parity for a group of NR rhs and walks the T slices x0a .. x0b - 1. The time
+// neighbours of output (x0, s) are the inputs (x0 +/- 1, s) with the same s (a step in x0
+// flips the parity and keeps the x3 bit), so each input is loaded once per walk for the
+// time hops: its (1 - g0) projection serves the forward hop of output x0 - 1 at once, and
+// its (1 + g0) projection is carried in registers to the backward hop of output x0 + 1
+// two steps later. Spatial hops read memory. The slice-local range is cut into 8 pieces,
+// one per XCD (workgroup id % 8), and the walks of an XCD run side by side, so spatial
+// neighbours are read by concurrently running workgroups of the same XCD; the result is
+// stored non-temporally. A workgroup is 128 consecutive slice-local sites.
+template <class R, int NR>
+__global__ __launch_bounds__(128) void hop_walk_kernel(HopArgs<R> A, int nck, int T) {
+  typedef typename vec2<R>::type V2;
+  const int xcd = blockIdx.x & 7;
+  const long long l = blockIdx.x >> 3;
+  const int ngroups = (A.nrhs + NR - 1) / NR;
+  const long long per_walk = (long long)nck * ngroups;
+  const int walk = (int)(l / per_walk);
+  const long long rem = l - walk * per_walk;
+  const int chunk = (int)(rem / ngroups);
+  const int r0 = (int)(rem - (long long)chunk * ngroups) * NR;
+  const Geo& g = A.g;
+  const int x0a = walk * T;
+  if (x0a >= g.L0) return;
+  const int x0b = min(x0a + T, g.L0);
+  const int lo = (int)((long long)g.V3h * xcd / 8);
+  const int hi = (int)((long long)g.V3h * (xcd + 1) / 8);
+  const int s = lo + chunk * 128 + threadIdx.x;
+  if (s >= hi) return;
+  const int nr = min(NR, A.nrhs - r0);
+  const int p = A.parity_out, q = 1 - p;
+  const V2* inb = A.in.ptr + q * A.in.ps;
+  const bool g5i = A.g5_in != 0;
+  const int lb = A.lb;
+  const long long V3h = g.V3h;
+  auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
+  auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
+  auto wrap = [&](int x) { return x < 0 ? x + g.L0 : (x >= g.L0 ? x - g.L0 : x); };
+
+  // (1 + g0) projections of the inputs on slices x0 - 1 (cp) and x0 (cc) at step x0;
+  // rotated by register moves (a runtime slot index would put the arrays in scratch)
+  cx<R> cp[NR][2][3], cc[NR][2][3];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[r][a][c] = {R(0), R(0)};
-  const V2* inb = A.in.ptr + (1 - p) * A.in.ps;
-  const bool g5i = A.g5_in != 0;
+      for (int c = 0; c < 3; ++c) cp[r][h][c] = cc[r][h][c] = {R(0), R(0)};
+  const bool need_p = bwd_on(x0a), need_c = x0a + 1 < x0b && bwd_on(x0a + 1);
 #pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
+  for (int r = 0; r < NR; ++r) {
+    if (r < nr) {
+      cx<R> sp[4][3];
+      if (need_p) {
+        load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)wrap(x0a - 1) * V3h + s, g5i, sp);
+        project<R>(0, true, sp, cp[r]);
+      }
+      if (need_c) {
+        load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)x0a * V3h + s, g5i, sp);
+        project<R>(0, true, sp, cc[r]);
+      }
+    }
+  }
+
+  for (int x0 = x0a; x0 < x0b; ++x0) {
+    const long long j = (long long)x0 * V3h + s;
+    const Site st_ = decode(g, j, p);
+    const bool sel = hop_selected(A, x0);
+    cx<R> acc[NR][4][3];
 #pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-      const bool on = dir == 0 ? !(A.lb && mu == 0 && (s.x0 % A.lb) == A.lb - 1)
-                               : !(A.lb && mu == 0 && (s.x0 % A.lb) == 0);
-      if (!on) continue;
-      const long long jn = nbr(g, s, j, mu, dir == 0 ? +1 : -1);
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r][a][c] = {R(0), R(0)};
+    // backward time hop from the carried projection of input x0 - 1
+    if (sel && bwd_on(x0)) {
       cx<R> m[9];
-      if (dir == 0) load_link<R>(A.U, Vhp, mu, p, j, m);
-      else load_link<R>(A.U, Vhp, mu, 1 - p, jn, m);
-      const bool flip = mu == 0 && (dir == 0 ? s.x0 == g.L0 - 1 : s.x0 == 0);
+      load_link<R>(A.U, g.Vhp, 0, q, (long long)wrap(x0 - 1) * V3h + s, m);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         if (r < nr) {
-          cx<R> sp[4][3], h[2][3], uh[2][3];
-          load_spinor<R>(inb + (r0 + r) * A.in.rs, jn, g5i, sp);
-          project<R>(mu, dir == 1, sp, h);
-          if (dir == 0) {
-            su3_mul<R>(m, h[0], uh[0]);
-            su3_mul<R>(m, h[1], uh[1]);
-          } else {
-            su3_dag_mul<R>(m, h[0], uh[0]);
-            su3_dag_mul<R>(m, h[1], uh[1]);
-          }
-          if (flip)
+          cx<R> uh[2][3];
+          su3_dag_mul<R>(m, cp[r][0], uh[0]);
+          su3_dag_mul<R>(m, cp[r][1], uh[1]);
+          if (x0 == 0)
 #pragma unroll
             for (int k = 0; k < 2; ++k)
 #pragma unroll
               for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
-          accum_recon<R>(mu, dir == 1, uh, acc[r]);
+          accum_recon<R>(0, true, uh, acc[r]);
         }
       }
     }
-  }
+    // input x0 + 1: forward time hop of output x0 now, carried for output x0 + 2
+    const bool use_f = sel && fwd_on(x0);
+    const bool keep = x0 + 2 < x0b && bwd_on(x0 + 2);
+    if (use_f || keep) {
+      const long long jn = (long long)wrap(x0 + 1) * V3h + s;
+      cx<R> m[9];
+      if (use_f) load_link<R>(A.U, g.Vhp, 0, p, j, m);
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    if (r >= nr) continue;
-    if (A.g5_out) {
+      for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+          cx<R> sp[4][3];
+          load_spinor<R>(inb + (r0 + r) * A.in.rs, jn, g5i, sp);
+          if (use_f) {
+            cx<R> h[2][3], uh[2][3];
+            project<R>(0, false, sp, h);
+            su3_mul<R>(m, h[0], uh[0]);
+            su3_mul<R>(m, h[1], uh[1]);
+            if (x0 == g.L0 - 1)
 #pragma unroll
-      for (int a = 2; a < 4; ++a)
+              for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[r][a][c] = -acc[r][a][c];
-    }
-    V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
-    if (A.x.ptr) {
-      const V2* xp = A.x.ptr + (r0 + r) * A.x.rs + p * A.x.ps + tiled(j, 0, 12);
+                for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+            accum_recon<R>(0, false, uh, acc[r]);
+          }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+          for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          cx<R> xv = ld<R>(xp + (a * 3 + c) * TILE);
-          cx<R> v = {A.a * xv.r + A.b * acc[r][a][c].r, A.a * xv.i + A.b * acc[r][a][c].i};
-          st<R>(o + (a * 3 + c) * TILE, v);
+            for (int c = 0; c < 3; ++c) cp[r][h][c] = cc[r][h][c];
+          if (keep) project<R>(0, true, sp, cc[r]);
         }
+      }
     } else {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) st<R>(o + (a * 3 + c) * TILE, A.b * acc[r][a][c]);
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) cp[r][h][c] = cc[r][h][c];
     }
+    if (sel) {
+#pragma unroll
+      for (int mu = 1; mu < 4; ++mu) {
+        hop_dir<R, NR>(A, p, j, st_, mu, 0, r0, nr, acc);
+        hop_dir<R, NR>(A, p, j, st_, mu, 1, r0, nr, acc);
+      }
+    }
+    hop_store<R, NR, true>(A, p, j, r0, nr, sel, acc);
   }
 }
 
@@ -493,6 +690,27 @@ template <class R, int NR, bool SWEEP> static void launch_reg(const HopArgs<R>& 
   const dim3 grid((unsigned)round8(chunks * groups)), blk(256);
   if (full) hipLaunchKernelGGL((hop_reg_kernel<R, true, NR, SWEEP>), grid, blk, 0, st, A, chunks);
   else hipLaunchKernelGGL((hop_reg_kernel<R, false, NR, SWEEP>), grid, blk, 0, st, A, chunks);
+}
+
+template <class R, int NR> static void launch_march(const HopArgs<R>& A, hipStream_t st) {
+  const bool full = A.parity_out < 0;
+  const int piece = (A.g.V3h + 7) / 8;                 // largest of the 8 pieces
+  const int per = full ? 64 : 128;
+  const int nck = (piece + per - 1) / per;
+  const long long groups = (A.nrhs + NR - 1) / NR;
+  const dim3 grid((unsigned)(8LL * A.g.L0 * nck * groups)), blk(128);
+  if (full) hipLaunchKernelGGL((hop_march_kernel<R, true, NR>), grid, blk, 0, st, A, nck);
+  else hipLaunchKernelGGL((hop_march_kernel<R, false, NR>), grid, blk, 0, st, A, nck);
+}
+
+template <class R, int NR> static void launch_walk(const HopArgs<R>& A, hipStream_t st) {
+  const int piece = (A.g.V3h + 7) / 8;
+  const int nck = (piece + 127) / 128;
+  const int T = A.g.L0 < HOP_WALK_T ? A.g.L0 : HOP_WALK_T;
+  const int nwalk = (A.g.L0 + T - 1) / T;
+  const long long groups = (A.nrhs + NR - 1) / NR;
+  const dim3 grid((unsigned)(8LL * nwalk * nck * groups)), blk(128);
+  hipLaunchKernelGGL((hop_walk_kernel<R, NR>), grid, blk, 0, st, A, nck, T);
 }
 
 template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {
@@ -511,6 +729,20 @@ template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t st) {
   if (A.map == HOP_MAP_STREAM && !full) {
     launch_stream<R>(A, st);
     return;
+  }
+  switch (A.map) {
+    case HOP_MAP_MARCH1: launch_march<R, 1>(A, st); return;
+    case HOP_MAP_MARCH2: launch_march<R, 2>(A, st); return;
+    case HOP_MAP_MARCH4: launch_march<R, 4>(A, st); return;
+    case HOP_MAP_WALK1:
+      if (full) launch_march<R, 1>(A, st);
+      else launch_walk<R, 1>(A, st);
+      return;
+    case HOP_MAP_WALK2:
+      if (full) launch_march<R, 2>(A, st);
+      else launch_walk<R, 2>(A, st);
+      return;
+    default: break;
   }
   if (A.nrhs > 1) {
     switch (A.map) {

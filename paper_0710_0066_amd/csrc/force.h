@@ -21,5 +21,9 @@ void launch_update_links(const Geo& g, double2* U, const double* P, double dt, h
 // mode 0: gamma5; 1: Pi (black-boundary projector, blocks of l0); 2: keep white blocks; 3: in - Pi in2
 void launch_spin_op(const Geo& g, int mode, int l0, double2* out, const double2* in, const double2* in2,
                     hipStream_t s);
+// x0 profile of |F| (out: [2][L0], spatial then time means; part: 2 * L0 * nck doubles
+// with nck = force_profile_nck(g))
+int force_profile_nck(const Geo& g);
+void launch_force_profile(const Geo& g, const double* F, double* part, double* out, hipStream_t s);
 void launch_axpy_mom(const Geo& g, double* p, double c, const double* F, hipStream_t s);
 }  // namespace sap

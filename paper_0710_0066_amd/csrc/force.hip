@@ -413,6 +413,55 @@ __global__ __launch_bounds__(256) void k_norm2_full(Geo g, const double2* f, dou
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// Per-(slice, chunk) partial sums of |F(x, mu)| = (sum_a F^a(x, mu)^2)^(1/2) over 128 slice
+// sites of each parity: spatial directions (mu = 1, 2, 3) and time direction (mu = 0).
+// part[2 * blockIdx.x + {0, 1}]; blockIdx.x = x0 * nck + chunk.
+__global__ __launch_bounds__(256) void k_force_profile(Geo g, const double* F, int nck, double* part) {
+  __shared__ double sh[2][4];
+  const int x0 = blockIdx.x / nck, ck = blockIdx.x - x0 * nck;
+  const int p = threadIdx.x >> 7;
+  const int s = ck * 128 + (threadIdx.x & 127);
+  double vs = 0.0, vt = 0.0;
+  if (s < g.V3h) {
+    const long long j = (long long)x0 * g.V3h + s;
+    const double* q = F + p * 32 * g.Vhp + tiled(j, 0, 32);
+    for (int mu = 0; mu < 4; ++mu) {
+      double n2 = 0.0;
+      for (int a = 0; a < 8; ++a) {
+        const double v = q[(8 * mu + a) * TILE];
+        n2 += v * v;
+      }
+      if (mu == 0) vt = sqrt(n2);
+      else vs += sqrt(n2);
+    }
+  }
+  vs = wsum(vs);
+  vt = wsum(vt);
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = vs;
+    sh[1][threadIdx.x >> 6] = vt;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int k = threadIdx.x;
+    part[2 * blockIdx.x + k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+  }
+}
+
+// out[x0] = spatial mean, out[L0 + x0] = time mean; partials summed in chunk order
+__global__ void k_force_profile_fin(Geo g, int nck, const double* part, double* out) {
+  const int x0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x0 >= g.L0) return;
+  double vs = 0.0, vt = 0.0;
+  for (int ck = 0; ck < nck; ++ck) {
+    vs += part[2 * (x0 * nck + ck)];
+    vt += part[2 * (x0 * nck + ck) + 1];
+  }
+  const double V3 = 2.0 * g.V3h;
+  out[x0] = vs / (3.0 * V3);
+  out[g.L0 + x0] = vt / V3;
+}
+
 // p += c * F over the whole momentum buffer
 __global__ void k_axpy_mom(long long n, double* p, double c, const double* F) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -451,6 +500,12 @@ void launch_update_links(const Geo& g, double2* U, const double* P, double dt, h
 void launch_spin_op(const Geo& g, int mode, int l0, double2* out, const double2* in, const double2* in2,
                     hipStream_t s) {
   hipLaunchKernelGGL(k_spin_op, dim3(site_blocks(g)), dim3(256), 0, s, g, mode, l0, out, in, in2);
+}
+int force_profile_nck(const Geo& g) { return (g.V3h + 127) / 128; }
+void launch_force_profile(const Geo& g, const double* F, double* part, double* out, hipStream_t s) {
+  const int nck = force_profile_nck(g);
+  hipLaunchKernelGGL(k_force_profile, dim3((unsigned)(g.L0 * nck)), dim3(256), 0, s, g, F, nck, part);
+  hipLaunchKernelGGL(k_force_profile_fin, dim3((unsigned)((g.L0 + 63) / 64)), dim3(64), 0, s, g, nck, part, out);
 }
 void launch_axpy_mom(const Geo& g, double* p, double c, const double* F, hipStream_t s) {
   const long long n = 64 * g.Vhp;

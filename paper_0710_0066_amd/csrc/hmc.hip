@@ -29,6 +29,7 @@ struct ForceWS {
   double* h_scal;      // pinned host mirror
   double* sx;          // per-link step scale s_mu(x0), [L0][4]
   double2* Utmp;       // gauge field scratch (translations)
+  double* prof;        // force profile: partials (2 * L0 * nck) then the result (2 * L0)
   long long iters;     // inner iterations accumulated by the drivers below
 };
 
@@ -47,6 +48,8 @@ int sap_force_create(sap_ctx* c) {
   ok = ok && hipHostMalloc((void**)&w->h_scal, 64 * 8, 0) == hipSuccess;
   ok = ok && hipMalloc((void**)&w->sx, (size_t)c->geom.L[0] * 4 * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&w->Utmp, (size_t)72 * c->Vhp * sizeof(double2)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&w->prof, (size_t)2 * c->geom.L[0] * (force_profile_nck(c->g) + 1) * 8) ==
+                 hipSuccess;
   if (!ok) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the force workspace");
   for (int i = 0; i < 9; ++i) (void)hipMemset(w->f[i], 0, fb);
   return SAP_OK;
@@ -63,6 +66,7 @@ void sap_force_destroy(sap_ctx* c) {
   if (w->h_scal) (void)hipHostFree(w->h_scal);
   if (w->sx) (void)hipFree(w->sx);
   if (w->Utmp) (void)hipFree(w->Utmp);
+  if (w->prof) (void)hipFree(w->prof);
   delete w;
   c->forces = nullptr;
 }
@@ -353,6 +357,20 @@ int sap_plaquette(sap_ctx* c, double* plaq_out, void* stream) {
   int rc = gauge_action_host(c, -3.0, &S, (hipStream_t)stream);    // S = sum Re tr U_P
   if (rc) return rc;
   *plaq_out = S / (18.0 * (double)c->V);
+  return SAP_OK;
+}
+
+int sap_force_profile(sap_ctx* c, const double* F, double* prof, void* stream) {
+  if (!c) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
+  if (!F || !prof) return sap_fail(c, SAP_E_ARG, "F or prof is NULL");
+  ForceWS* w = fws(c);
+  hipStream_t s = (hipStream_t)stream;
+  const int L0 = c->geom.L[0];
+  double* out = w->prof + (size_t)2 * L0 * force_profile_nck(c->g);
+  launch_force_profile(c->g, F, w->prof, out, s);
+  SAP_HIP_CHECK(c, hipGetLastError());
+  SAP_HIP_CHECK(c, hipMemcpyAsync(prof, out, (size_t)2 * L0 * 8, hipMemcpyDeviceToHost, s));
+  SAP_HIP_CHECK(c, hipStreamSynchronize(s));
   return SAP_OK;
 }
 

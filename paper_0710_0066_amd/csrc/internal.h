@@ -47,7 +47,13 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
        HOP_MAP_REG4 = 8,    //   link is loaded once and applied to 2 (4) rhs
        HOP_MAP_REG2_SWEEP = 9,   // REG2 / REG4 with workgroups group-slowest: each group
        HOP_MAP_REG4_SWEEP = 10,  //   of rhs sweeps the lattice like a small-rhs launch
-       HOP_NMAP = 11 };
+       HOP_MAP_MARCH1 = 11, // x0-marching: each XCD owns 1/8 of every x0 slice and walks the
+       HOP_MAP_MARCH2 = 12, //   slices in order, 1 / 2 / 4 rhs per work-item (any nrhs for
+       HOP_MAP_MARCH4 = 13, //   MARCH1)
+       HOP_MAP_WALK1 = 14,  // even-odd hop only: x0-walking, time neighbours carried in
+       HOP_MAP_WALK2 = 15,  //   registers, 1 / 2 rhs per work-item
+       HOP_NMAP = 16 };
+constexpr int HOP_WALK_T = 8;   // slices per walk
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
 

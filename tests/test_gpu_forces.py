@@ -281,3 +281,67 @@ def test_hmc_step_profile_and_time_shift_match_oracle(gu):
     Uo = torch.zeros(U.size, dtype=torch.complex128, device="cuda")
     ctx.get_gauge(Uo)
     assert np.array_equal(Uo.cpu().numpy().reshape(U.shape), hmc.time_shift(U, -5))
+
+
+def test_force_profile_matches_oracle(gu):
+    """sap_force_profile against the oracle's profile: a Gaussian momentum field on a
+    lattice with a ragged last tile, and the Schwarz force of two blocks (l0 = L0/2),
+    whose spatial profile falls from the block boundaries to the block middles."""
+    import paper_0710_0066_amd as sap
+    print("force profile", flush=True)
+    for L in [(6, 2, 4, 6), (8, 6, 2, 10)]:
+        ctx = gu.make_ctx(L, 3 if L[0] == 6 else 2, 0.15, synth.gauge_field(L, 0.5, 80))
+        p = synth.gaussian_momenta(L, 81)
+        got = np.array(sap.sap_force_profile(ctx, _mom_to_sap(ctx, gu, p)))
+        assert _rel(got, forces.force_profile(p)) <= 1e-13, L
+    L, l0, k = (16, 4, 4, 4), 8, 0.13
+    U = synth.gauge_field(L, 0.5, 61)
+    ctx = gu.make_ctx(L, l0, k, U)
+    fchi = ctx.new_field(1)
+    sap.schwarz_heat_bath(ctx, fchi, gu.to_sap(ctx, synth.noise_spinor(L, 62), 1), _opts(sap))
+    F = ctx.new_momenta()
+    sap.schwarz_boundary_force(ctx, F, 1.0, fchi, _opts(sap))
+    got = np.array(sap.sap_force_profile(ctx, F))
+    S = schwarz.Solvers(U, k, l0, tol=1e-13)
+    chi = schwarz.heat_bath(U, synth.noise_spinor(L, 62), k, l0, S)
+    ref = forces.force_profile(forces.schwarz_force(U, chi, k, l0, S))
+    assert _rel(got, ref) <= 1e-9
+
+
+def test_force_profile_16x16x16x32(gu):
+    """The x0 profile of the three forces of the two-factor action on the 16^3x32 lattice
+    with two blocks of l0 = 16 (the paper's first decomposition l0 = L0/2) at kappa = 0.13
+    on a rough field (eps = 0.5): the Schwarz force falls strictly over the first five
+    slices away from each block boundary and is more than 100x smaller in the block
+    middle than at the boundaries (it drops about tenfold per slice, so the middle values
+    are left to the solver tolerance and not ordered); the gauge force (beta = 5.6) and
+    the block pseudo-fermion force are spread over all slices (max/min of their profiles
+    below 2). Printed for the record."""
+    import paper_0710_0066_amd as sap
+    L, l0, k = (32, 16, 16, 16), 16, 0.13
+    print("force profile 16^3x32", flush=True)
+    U = synth.gauge_field(L, 0.5, 1004)
+    ctx = gu.make_ctx(L, l0, k, U)
+    o = _opts(sap, tol=1e-12)
+    fchi = ctx.new_field(1)
+    sap.schwarz_heat_bath(ctx, fchi, gu.to_sap(ctx, synth.noise_spinor(L, 4004), 1), o)
+    prof = {}
+    F = ctx.new_momenta()
+    sap.schwarz_boundary_force(ctx, F, 1.0, fchi, o)
+    prof["S_R"] = np.array(sap.sap_force_profile(ctx, F))[0]
+    F.zero_()
+    sap.block_pf_force(ctx, F, 1.0, gu.to_sap(ctx, synth.gaussian_spinor(L, 4005), 1), o)
+    prof["S_W"] = np.array(sap.sap_force_profile(ctx, F))[0]
+    F.zero_()
+    sap.gauge_force(ctx, F, 1.0, 5.6)
+    prof["S_G"] = np.array(sap.sap_force_profile(ctx, F))[0]
+    for name, v in prof.items():
+        print(f"  {name}: " + " ".join(f"{x:.3e}" for x in v), flush=True)
+    sp = prof["S_R"]
+    for b0 in range(0, L[0], l0):
+        first, last, mid = b0, b0 + l0 - 1, b0 + l0 // 2
+        assert np.all(np.diff(sp[first:first + 6]) < 0), sp
+        assert np.all(np.diff(sp[last - 5:last + 1]) > 0), sp
+        assert min(sp[first], sp[last]) > 100 * max(sp[mid - 1], sp[mid]), sp
+    for name in ("S_W", "S_G"):
+        assert prof[name].max() < 2 * prof[name].min(), (name, prof[name])

@@ -109,3 +109,48 @@ def test_directional_derivative_with_cg_solves():
     fd = (4.0 * d(5e-4) - d(1e-3)) / 3.0
     an = float(np.sum(F * omega))
     assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+def test_force_profile_closed_form():
+    """force_profile is the slice mean of the norms |F(x, mu)|: per-slice constant fields
+    of known norm, and a slice whose sites alternate between norms 1 and 3 (mean 2, where
+    the norm of the mean or the root mean square would give other values)."""
+    L = (4, 2, 2, 4)
+    rng = np.random.default_rng(5)
+    r = rng.uniform(0.5, 2.0, size=(L[0], 4))
+    d = rng.normal(size=(L[0], 4, 8))
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    F = np.broadcast_to((r[..., None] * d)[:, None, None, None], L + (4, 8)).copy()
+    F[2] = 0.0
+    e = np.zeros(8)
+    e[3] = 1.0
+    sites = np.indices(L[1:]).sum(axis=0) % 2
+    F[2, ..., 2, :] = np.where(sites[..., None] == 0, 1.0, 3.0) * e
+    P = forces.force_profile(F)
+    exp_sp = r[:, 1:].mean(axis=1)
+    exp_sp[2] = 2.0 / 3.0
+    exp_t = r[:, 0].copy()
+    exp_t[2] = 0.0
+    assert np.allclose(P[0], exp_sp, rtol=1e-14, atol=0)
+    assert np.allclose(P[1], exp_t, rtol=1e-14, atol=0)
+
+
+def test_schwarz_force_profile_decays_from_block_boundaries():
+    """Sec. 4 (plot of the average force on the spatial links against x0): the force of the
+    Schwarz term det^2(M W1^{-1}) is largest at the boundaries between the blocks and
+    smallest in the middle of a block. Two blocks of l0 = L0/2 as in the paper's first
+    decomposition, on a rough field at kappa = 0.13 (short correlation length, so the decay
+    is clean): the spatial profile falls strictly from each block boundary to the block's
+    middle, by more than a factor 100."""
+    L, l0, k = (16, 4, 4, 4), 8, 0.13
+    U = synth.gauge_field(L, 0.5, 61)
+    S = schwarz.Solvers(U, k, l0, tol=1e-11)
+    chi = schwarz.heat_bath(U, synth.noise_spinor(L, 62), k, l0, S)
+    sp = forces.force_profile(forces.schwarz_force(U, chi, k, l0, S))[0]
+    for b0 in range(0, L[0], l0):
+        first, last, mid = b0, b0 + l0 - 1, b0 + l0 // 2
+        down = sp[first:mid]                  # boundary -> middle from the first slice
+        up = sp[mid - 1:last + 1]              # middle -> boundary at the last slice
+        assert np.all(np.diff(down) < 0), sp
+        assert np.all(np.diff(up[::-1][:l0 // 2]) < 0), sp
+        assert min(sp[first], sp[last]) > 100 * min(sp[mid - 1], sp[mid]), sp
