@@ -132,7 +132,9 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=3):
       fp64_batched        the same batching, FP64 inner solve (the precision gain alone);
       fp64_rhs_loop       FP64, one rhs per call, the blocks of a level together;
       fp64_per_block_loop FP64, one block and one rhs per call (the plain, unbatched
-                          solve: 432 calls, timed once)."""
+                          solve: 432 calls, timed once);
+      mixed_batched_by_method  the mixed batched solve with the inner CG replaced by
+                          BiCGstab and by the geometric series (Sec. 3's block-term solver)."""
     import numpy as np
     import synth
     nrhs = cfg["nrhs"]
@@ -171,6 +173,14 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=3):
 
     print("[bench] block solves: mixed batched", file=sys.stderr, flush=True)
     m = run(mixed, "batched", repeats)
+    methods = {"cg": m}
+    for name, meth in (("bicgstab", sap.SAP_BICGSTAB), ("geometric_series", sap.SAP_GEOM)):
+        print(f"[bench] block solves: mixed batched {name}", file=sys.stderr, flush=True)
+        o = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F32, inner_tol=1e-5, method=meth)
+        try:
+            methods[name] = run(o, "batched", repeats)
+        except sap.SapError as e:
+            methods[name] = {"error": str(e)}
     print("[bench] block solves: fp64 batched", file=sys.stderr, flush=True)
     f = run(plain, "batched", repeats)
     print("[bench] block solves: fp64 one rhs per call", file=sys.stderr, flush=True)
@@ -179,10 +189,12 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=3):
     fb1 = run(plain, "block", 1)
     return {"systems": f"{nrhs} rhs x (12 blocks 24^3x4 + 24 blocks 24^3x2) = {nrhs * 36}",
             "tol": 1e-10, "mixed_batched": m, "fp64_batched": f, "fp64_rhs_loop": fl,
-            "fp64_per_block_loop": fb1,
+            "fp64_per_block_loop": fb1, "mixed_batched_by_method": methods,
             "speedup_vs_fp64_batched": f["seconds"] / m["seconds"],
             "speedup_vs_fp64_rhs_loop": fl["seconds"] / m["seconds"],
-            "speedup_vs_fp64_per_block_loop": fb1["seconds"] / m["seconds"]}
+            "speedup_vs_fp64_per_block_loop": fb1["seconds"] / m["seconds"],
+            "speedup_bicgstab_vs_fp64_per_block_loop":
+                fb1["seconds"] / methods["bicgstab"]["seconds"] if "seconds" in methods["bicgstab"] else None}
 
 
 def time_op(sap, torch, fn, steps, warmup):

@@ -76,12 +76,28 @@ typedef struct {
   int max_rhs;       /* largest nrhs any call will pass (sizes the workspace) */
 } sap_geom;
 
+/* Method of the inner solve (Sec. 3 names the geometric series for the block terms and
+ * BiCGstab with even-odd and Schwarz preconditioning for the full-lattice term). */
+typedef enum {
+  SAP_CG = 0,           /* CG on the normal equations of the even-odd system (CGLS form) */
+  SAP_BICGSTAB = 1,     /* BiCGstab on the even-odd system */
+  SAP_GEOM = 2,         /* geometric series of the even-odd system: x_e = sum_n (k^2 D_eo D_oe)^n
+                         * b_hat; SAP_E_NOCONV when it diverges (spectral radius >= 1) */
+  SAP_SAP_BICGSTAB = 3  /* solve_full only: FP64 BiCGstab on M, right-preconditioned by
+                         * sap_ncy cycles of the Schwarz alternating procedure on the
+                         * level-1 blocks (black, then white); the block systems are solved
+                         * with CG at inner_prec to the relative residual inner_tol */
+} sap_method;
+
 typedef struct {
   double tol;        /* stop when ||b - A x|| / ||b|| <= tol, recomputed in FP64 */
-  int max_iter;      /* cap on inner iterations summed over outer cycles */
+  int max_iter;      /* cap on inner iterations summed over outer cycles (SAP_SAP_BICGSTAB:
+                      * on BiCGstab iterations) */
   sap_prec inner_prec; /* precision of the inner Krylov solve */
   double inner_tol;  /* relative reduction asked of each inner solve (defect correction) */
-  int max_outer;     /* cap on FP64 defect-correction cycles */
+  int max_outer;     /* cap on FP64 defect-correction cycles (SAP_SAP_BICGSTAB: restarts) */
+  sap_method method; /* inner method; 0 (SAP_CG) is the default */
+  int sap_ncy;       /* SAP_SAP_BICGSTAB: Schwarz cycles per preconditioner application */
 } sap_solve_opts;
 
 typedef struct {
@@ -204,17 +220,19 @@ int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);
 
 /* ---- solvers ------------------------------------------------------------------ */
 
-/* Solve M x = b for nrhs FP64 fields (sap layout): even-odd reduced CG on the normal
- * equations (the Schur complement of Sec. 1's W_eo construction applied to M), run in
- * opts->inner_prec inside an FP64 defect-correction loop, until
- * ||b - M x|| / ||b|| <= opts->tol with M applied in FP64. x is overwritten (the
+/* Solve M x = b for nrhs FP64 fields (sap layout): the even-odd reduced system (the Schur
+ * complement of Sec. 1's W_eo construction applied to M) solved by opts->method (CG on
+ * the normal equations, BiCGstab or the geometric series) in opts->inner_prec inside an
+ * FP64 defect-correction loop, or (SAP_SAP_BICGSTAB) Schwarz-preconditioned BiCGstab on
+ * M, until ||b - M x|| / ||b|| <= opts->tol with M applied in FP64. x is overwritten (the
  * initial content is ignored). info: host array of nrhs entries (may be NULL).
  * Returns SAP_E_NOCONV if a system misses tol within the caps. Synchronises. */
 int solve_full(sap_ctx* ctx, double* x, const double* b, int nrhs, const sap_solve_opts* opts,
                sap_solve_info* info, void* stream);
 
 /* Solve W_level x = b on every selected block as an independent system (all selected
- * blocks and all nrhs fields batched in each kernel launch). block >= 0 selects that
+ * blocks and all nrhs fields batched in each kernel launch), by opts->method (SAP_CG,
+ * SAP_BICGSTAB or SAP_GEOM; SAP_SAP_BICGSTAB is rejected). block >= 0 selects that
  * single block (color is then ignored), block = -1 all blocks of the colour. Sites
  * outside the selection are set to zero in x. info: host array of nblocks(level)*nrhs
  * entries ordered [rhs][block] (entries of unselected blocks are zeroed). Synchronises. */

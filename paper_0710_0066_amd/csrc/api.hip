@@ -63,6 +63,7 @@ size_t sap_momenta_bytes(const sap_ctx* ctx) {
 }
 
 void sap_solver_destroy(sap_ctx* ctx);   // solver.hip
+void sap_sapws_destroy(sap_ctx* ctx);    // solver.hip
 int sap_solver_create(sap_ctx* ctx);     // solver.hip
 }  // extern "C"
 int sap_force_create(sap_ctx* ctx);      // hmc.hip
@@ -85,6 +86,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   c->U32 = nullptr;
   c->solver = nullptr;
   c->forces = nullptr;
+  c->sapws = nullptr;
   std::memset(c->hop_map, -1, sizeof(c->hop_map));
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -109,6 +111,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
 
 void sap_destroy(sap_ctx* ctx) {
   if (!ctx) return;
+  sap_sapws_destroy(ctx);
   sap_solver_destroy(ctx);
   sap_force_destroy(ctx);
   if (ctx->U64) (void)hipFree(ctx->U64);

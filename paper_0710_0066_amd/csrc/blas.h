@@ -18,7 +18,9 @@ struct SysGrid {
 };
 
 // Per-system scalars of the CG iteration (device arrays of nsys entries) and flags:
-// flags[0] = non-finite value seen, flags[1] = number of active systems.
+// flags[0] = non-finite value seen (the code of the finalize kernel that saw it: 1 CG init,
+// 2 CG alpha, 3 CG beta, 4 BiCGstab rho, 5 BiCGstab alpha, 6 BiCGstab omega, 7 series),
+// flags[1] = number of active systems, flags[2] = a geometric series diverged.
 struct SysScal {
   double *gam, *ss, *alpha, *beta;
   int *active, *iters, *flags;
@@ -50,5 +52,41 @@ void fin_init(const SysScal& S, int nsys, int nchunk, const double* pb, const do
 void fin_alpha(const SysScal& S, int nsys, int nchunk, const double* pq, hipStream_t s);
 void fin_beta(const SysScal& S, int nsys, int nchunk, const double* ps_, const double* pr,
               const double* target2, hipStream_t s);
+
+// ---- BiCGstab on the even-odd system: complex per-system scalars in cs[8 * sys] =
+// (rho, alpha, omega, beta) as (re, im) pairs; partials hold three values per
+// (system, chunk): re <a, b>, im <a, b>, ||c||^2.
+template <class R> void blas_cdot3(const SysGrid& G, int nrhs, Field<R> a, Field<R> b, Field<R> c, double* part,
+                                   hipStream_t s);
+// p = r + beta (p - omega v)
+template <class R> void blas_bicg_p(const SysGrid& G, int nrhs, Field<R> p, Field<R> r, Field<R> v,
+                                    const double* cs, hipStream_t s);
+// s = r - alpha v (into r), partial ||s||^2 (one per chunk)
+template <class R> void blas_bicg_s(const SysGrid& G, int nrhs, Field<R> r, Field<R> v, const double* cs,
+                                    double* part, hipStream_t s);
+// x += alpha p + omega s ; r = s - omega t (s is held in r) ; partials <r0, r>, ||r||^2
+template <class R> void blas_bicg_xr(const SysGrid& G, int nrhs, Field<R> x, Field<R> p, Field<R> r,
+                                     Field<R> t, Field<R> r0, const double* cs, double* part, hipStream_t s);
+// start (init) or close an iteration: rho_new = <r0, r>, convergence on ||r||^2, beta
+void fin_bicg_rho(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, const int* sel,
+                  const double* target2, int init, hipStream_t s);
+void fin_bicg_alpha(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, hipStream_t s);
+void fin_bicg_omega(const SysScal& S, double* cs, int nsys, int nchunk, const double* part,
+                    const double* part_s, const double* target2, hipStream_t s);
+
+// y = c0 y + c1 u + c2 w (w.ptr may be null; y is not read when c0 = 0) with complex
+// per-system coefficients
+// coef[6 * sys] = (c0, c1, c2); if part: partials <q, y>, ||y||^2 (three per chunk)
+template <class R> void blas_lin3(const SysGrid& G, int nrhs, Field<R> y, Field<R> u, Field<R> w, Field<R> q,
+                                  const double* coef, double* part, hipStream_t s);
+// out[3 * sys + k] = sum over the chunks of the three partials
+void fin_sum3(int nsys, int nchunk, const double* part, double* out, hipStream_t s);
+
+// ---- geometric series: x += t on active systems; start / close an iteration on ||t||^2
+// (flags[2] = 1 when a series diverges)
+template <class R> void blas_geom_add(const SysGrid& G, int nrhs, Field<R> x, Field<R> t, const int* active,
+                                      hipStream_t s);
+void fin_geom(const SysScal& S, int nsys, int nchunk, const double* part, const int* sel, const double* target2,
+              int init, hipStream_t s);
 
 }  // namespace sap

@@ -214,7 +214,7 @@ __global__ void k_fin_init(SysScal S, int nsys, int nchunk, const double* part_b
 __global__ void k_fin_alpha(SysScal S, int nsys, int nchunk, const double* part_q) {
   for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
     const double qq = sys_total(part_q, s, nchunk);
-    if (!isfinite(qq)) S.flags[0] = 1;
+    if (!isfinite(qq)) S.flags[0] = 2;
     S.alpha[s] = (S.active[s] && qq > 0.0) ? S.gam[s] / qq : 0.0;
   }
 }
@@ -227,7 +227,7 @@ __global__ void k_fin_beta(SysScal S, int nsys, int nchunk, const double* part_s
   for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
     const double ss = sys_total(part_s, s, nchunk);
     const double gm = sys_total(part_r, s, nchunk);
-    if (!(isfinite(ss) && isfinite(gm))) S.flags[0] = 1;
+    if (!(isfinite(ss) && isfinite(gm))) S.flags[0] = 3;
     int act = S.active[s];
     if (act) {
       S.iters[s] += 1;
@@ -237,6 +237,320 @@ __global__ void k_fin_beta(SysScal S, int nsys, int nchunk, const double* part_s
       if (ss <= target2[s] || gm == 0.0) act = 0;
     } else {
       S.beta[s] = 0.0;
+    }
+    S.active[s] = act;
+    if (act) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) S.flags[1] = cnt;
+}
+
+// ---- BiCGstab and geometric series ---------------------------------------------------
+
+// three sums over the 256 threads of a workgroup, written by thread 0 to out[0..2]
+__device__ __forceinline__ void block_sum3(double a, double b, double c, double* out) {
+  __shared__ double sh[3][4];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wid] = a;
+    sh[1][wid] = b;
+    sh[2][wid] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) out[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+}
+
+__device__ __forceinline__ cx<double> cs_get(const double* cs, long long sys, int k) {
+  return {cs[8 * sys + 2 * k], cs[8 * sys + 2 * k + 1]};
+}
+__device__ __forceinline__ void cs_set(double* cs, long long sys, int k, cx<double> v) {
+  cs[8 * sys + 2 * k] = v.r;
+  cs[8 * sys + 2 * k + 1] = v.i;
+}
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+  const double d = b.r * b.r + b.i * b.i;
+  return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+enum { CS_RHO = 0, CS_ALPHA = 1, CS_OMEGA = 2, CS_BETA = 3 };
+
+template <class R>
+__global__ __launch_bounds__(256) void k_cdot3(SysGrid G, Field<R> a, Field<R> b, Field<R> c, double* part) {
+  const Tile t = tile_of(G);
+  double sr = 0.0, si = 0.0, sc = 0.0;
+  if (t.selected) {
+    const typename vec2<R>::type* ab = a.ptr + t.rhs * a.rs;
+    const typename vec2<R>::type* bb = b.ptr + t.rhs * b.rs;
+    const typename vec2<R>::type* cb = c.ptr ? c.ptr + t.rhs * c.rs : nullptr;
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const long long o = tiled(j, k, 12);
+        const cx<R> av = ld<R>(ab + o), bv = ld<R>(bb + o);
+        sr += (double)av.r * bv.r + (double)av.i * bv.i;
+        si += (double)av.r * bv.i - (double)av.i * bv.r;
+        if (cb) {
+          const cx<R> cv = ld<R>(cb + o);
+          sc += (double)cv.r * cv.r + (double)cv.i * cv.i;
+        }
+      }
+  }
+  block_sum3(sr, si, sc, part + 3 * (t.sys * G.nchunk + blockIdx.x));
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_bicg_p(SysGrid G, Field<R> p, Field<R> r, Field<R> v, const double* cs) {
+  const Tile t = tile_of(G);
+  if (!t.selected) return;
+  const cx<double> be = cs_get(cs, t.sys, CS_BETA), om = cs_get(cs, t.sys, CS_OMEGA);
+  const cx<R> b = {(R)be.r, (R)be.i}, w = {(R)om.r, (R)om.i};
+  typename vec2<R>::type* pb = p.ptr + t.rhs * p.rs;
+  const typename vec2<R>::type* rb = r.ptr + t.rhs * r.rs;
+  const typename vec2<R>::type* vb = v.ptr + t.rhs * v.rs;
+  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const long long o = tiled(j, k, 12);
+      const cx<R> pv = ld<R>(pb + o), rv = ld<R>(rb + o), vv = ld<R>(vb + o);
+      const cx<R> d = pv - cmul(w, vv);
+      st<R>(pb + o, rv + cmul(b, d));
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_bicg_s(SysGrid G, Field<R> r, Field<R> v, const double* cs, double* part) {
+  const Tile t = tile_of(G);
+  double acc = 0.0;
+  if (t.selected) {
+    const cx<double> al = cs_get(cs, t.sys, CS_ALPHA);
+    const cx<R> a = {(R)al.r, (R)al.i};
+    typename vec2<R>::type* rb = r.ptr + t.rhs * r.rs;
+    const typename vec2<R>::type* vb = v.ptr + t.rhs * v.rs;
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const long long o = tiled(j, k, 12);
+        const cx<R> sv = ld<R>(rb + o) - cmul(a, ld<R>(vb + o));
+        st<R>(rb + o, sv);
+        acc += (double)sv.r * sv.r + (double)sv.i * sv.i;
+      }
+  }
+  const double sm = block_sum(acc);
+  if (threadIdx.x == 0) part[t.sys * G.nchunk + blockIdx.x] = sm;
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_bicg_xr(SysGrid G, Field<R> x, Field<R> p, Field<R> r, Field<R> tt,
+                                                 Field<R> r0, const double* cs, double* part) {
+  const Tile t = tile_of(G);
+  double sr = 0.0, si = 0.0, sc = 0.0;
+  if (t.selected) {
+    const cx<double> al = cs_get(cs, t.sys, CS_ALPHA), om = cs_get(cs, t.sys, CS_OMEGA);
+    const cx<R> a = {(R)al.r, (R)al.i}, w = {(R)om.r, (R)om.i};
+    typename vec2<R>::type* xb = x.ptr + t.rhs * x.rs;
+    const typename vec2<R>::type* pb = p.ptr + t.rhs * p.rs;
+    typename vec2<R>::type* rb = r.ptr + t.rhs * r.rs;
+    const typename vec2<R>::type* tb = tt.ptr + t.rhs * tt.rs;
+    const typename vec2<R>::type* qb = r0.ptr + t.rhs * r0.rs;
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const long long o = tiled(j, k, 12);
+        const cx<R> sv = ld<R>(rb + o), tv = ld<R>(tb + o);
+        st<R>(xb + o, ld<R>(xb + o) + cmul(a, ld<R>(pb + o)) + cmul(w, sv));
+        const cx<R> rn = sv - cmul(w, tv);
+        st<R>(rb + o, rn);
+        const cx<R> q = ld<R>(qb + o);
+        sr += (double)q.r * rn.r + (double)q.i * rn.i;
+        si += (double)q.r * rn.i - (double)q.i * rn.r;
+        sc += (double)rn.r * rn.r + (double)rn.i * rn.i;
+      }
+  }
+  block_sum3(sr, si, sc, part + 3 * (t.sys * G.nchunk + blockIdx.x));
+}
+
+__device__ __forceinline__ void sys_total3(const double* part, long long sys, int nchunk, double out[3]) {
+  out[0] = out[1] = out[2] = 0.0;
+  for (int c = 0; c < nchunk; ++c)
+    for (int k = 0; k < 3; ++k) out[k] += part[3 * (sys * nchunk + c) + k];
+}
+
+// Close an iteration (init: start the solve): rho_new = <r0, r>, stop on ||r||^2 <= target2,
+// beta = (rho_new / rho) (alpha / omega). A breakdown (|<r0, r>|^2 <= 1e-24 ||r0||^2 ||r||^2,
+// a zero rho or omega, or ||r|| > 1e6 ||r0||) stops the system, which the defect-correction
+// loop then restarts from its current solution.
+__global__ void k_fin_bicg_rho(SysScal S, double* cs, int nsys, int nchunk, const double* part, const int* sel,
+                               const double* target2, int init) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+    double v[3];
+    sys_total3(part, s, nchunk, v);
+    const cx<double> rn = {v[0], v[1]};
+    const double rr = v[2];
+    if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(rr))) S.flags[0] = 4;
+    int act;
+    cx<double> rho, al, om;
+    if (init) {
+      act = sel[s] && rr > target2[s];
+      rho = {1.0, 0.0};
+      al = {1.0, 0.0};
+      om = {1.0, 0.0};
+    } else {
+      act = S.active[s] && rr > target2[s];
+      rho = cs_get(cs, s, CS_RHO);
+      al = cs_get(cs, s, CS_ALPHA);
+      om = cs_get(cs, s, CS_OMEGA);
+    }
+    S.ss[s] = rr;
+    if (init) S.gam[s] = rr;   // ||r0||^2 (r0 = r at the start)
+    const double rho2 = rho.r * rho.r + rho.i * rho.i, om2 = om.r * om.r + om.i * om.i;
+    const double rn2 = rn.r * rn.r + rn.i * rn.i;
+    // breakdown: <r0, r> (nearly) orthogonal, or a vanishing rho or omega; growth of the
+    // residual beyond 1e6 ||r0|| (which would overflow FP32 iterates) stops the system too
+    if (act && (rho2 == 0.0 || om2 == 0.0 || !(rn2 > 1e-24 * S.gam[s] * rr) || rr > 1e12 * S.gam[s])) act = 0;
+    if (act) {
+      cs_set(cs, s, CS_BETA, cmul(cdiv(rn, rho), cdiv(al, om)));
+      cs_set(cs, s, CS_RHO, rn);
+      cs_set(cs, s, CS_ALPHA, al);        // (1, 0) at the start, else unchanged
+      cs_set(cs, s, CS_OMEGA, om);
+    } else {
+      const cx<double> z = {0.0, 0.0};
+      cs_set(cs, s, CS_BETA, z);
+      cs_set(cs, s, CS_ALPHA, z);
+      cs_set(cs, s, CS_OMEGA, z);
+    }
+    S.active[s] = act;
+    if (act) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) S.flags[1] = cnt;
+}
+
+__global__ void k_fin_bicg_alpha(SysScal S, double* cs, int nsys, int nchunk, const double* part) {
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+    double v[3];
+    sys_total3(part, s, nchunk, v);
+    if (!(isfinite(v[0]) && isfinite(v[1]))) S.flags[0] = 5;
+    const cx<double> den = {v[0], v[1]};
+    if (S.active[s] && (den.r != 0.0 || den.i != 0.0)) {
+      cs_set(cs, s, CS_ALPHA, cdiv(cs_get(cs, s, CS_RHO), den));
+    } else {
+      cs_set(cs, s, CS_ALPHA, {0.0, 0.0});
+      S.active[s] = 0;
+    }
+  }
+}
+
+// omega = <t, s> / ||t||^2. When ||s||^2 already meets the target the step ends with
+// x += alpha p (omega = 0, r = s); when <t, s> (nearly) vanishes the system stops after
+// that same update (breakdown, restarted by the defect-correction loop).
+__global__ void k_fin_bicg_omega(SysScal S, double* cs, int nsys, int nchunk, const double* part,
+                                 const double* part_s, const double* target2) {
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+    double v[3];
+    sys_total3(part, s, nchunk, v);
+    const double ss = sys_total(part_s, s, nchunk);
+    if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(ss))) S.flags[0] = 6;
+    cx<double> om = {0.0, 0.0};
+    if (S.active[s]) {
+      S.iters[s] += 1;
+      const double ts2 = v[0] * v[0] + v[1] * v[1];
+      if (ss <= target2[s]) {
+        // converged on s: omega stays 0
+      } else if (v[2] > 0.0 && ts2 > 1e-24 * v[2] * ss) {
+        om = {v[0] / v[2], v[1] / v[2]};
+      } else {
+        S.active[s] = 0;
+      }
+    }
+    cs_set(cs, s, CS_OMEGA, om);
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_lin3(SysGrid G, Field<R> y, Field<R> u, Field<R> w, Field<R> q,
+                                              const double* coef, double* part) {
+  const Tile t = tile_of(G);
+  double sr = 0.0, si = 0.0, sc = 0.0;
+  if (t.selected) {
+    const double* cf = coef + 6 * t.sys;
+    const cx<R> c0 = {(R)cf[0], (R)cf[1]}, c1 = {(R)cf[2], (R)cf[3]}, c2 = {(R)cf[4], (R)cf[5]};
+    const bool keep_y = cf[0] != 0.0 || cf[1] != 0.0;   // c0 = 0: y is not read (may be unset)
+    typename vec2<R>::type* yb = y.ptr + t.rhs * y.rs;
+    const typename vec2<R>::type* ub = u.ptr + t.rhs * u.rs;
+    const typename vec2<R>::type* wb = w.ptr ? w.ptr + t.rhs * w.rs : nullptr;
+    const typename vec2<R>::type* qb = q.ptr ? q.ptr + t.rhs * q.rs : nullptr;
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+#pragma unroll
+      for (int k = 0; k < 12; ++k) {
+        const long long o = tiled(j, k, 12);
+        cx<R> v = cmul(c1, ld<R>(ub + o));
+        if (keep_y) v = v + cmul(c0, ld<R>(yb + o));
+        if (wb) v = v + cmul(c2, ld<R>(wb + o));
+        st<R>(yb + o, v);
+        if (qb) {
+          const cx<R> qv = ld<R>(qb + o);
+          sr += (double)qv.r * v.r + (double)qv.i * v.i;
+          si += (double)qv.r * v.i - (double)qv.i * v.r;
+        }
+        sc += (double)v.r * v.r + (double)v.i * v.i;
+      }
+  }
+  if (part) block_sum3(sr, si, sc, part + 3 * (t.sys * G.nchunk + blockIdx.x));
+}
+
+__global__ void k_fin_sum3(int nsys, int nchunk, const double* part, double* out) {
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+    double v[3];
+    sys_total3(part, s, nchunk, v);
+    for (int k = 0; k < 3; ++k) out[3 * s + k] = v[k];
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_geom_add(SysGrid G, Field<R> x, Field<R> tf, const int* active) {
+  const Tile t = tile_of(G);
+  if (!t.selected || !active[t.sys]) return;
+  typename vec2<R>::type* xb = x.ptr + t.rhs * x.rs;
+  const typename vec2<R>::type* tb = tf.ptr + t.rhs * tf.rs;
+  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const long long o = tiled(j, k, 12);
+      st<R>(xb + o, ld<R>(xb + o) + ld<R>(tb + o));
+    }
+}
+
+// Geometric series: init marks the systems with ||t_0||^2 = ||b_hat||^2 above target
+// (ss keeps it as the divergence reference); a later call stops a system once the new
+// term satisfies ||t||^2 <= target2, and flags a divergence once ||t||^2 > 1e30 ||b_hat||^2.
+__global__ void k_fin_geom(SysScal S, int nsys, int nchunk, const double* part, const int* sel,
+                           const double* target2, int init) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+    const double tt = sys_total(part, s, nchunk);
+    if (!isfinite(tt)) S.flags[0] = 7;
+    int act;
+    if (init) {
+      act = sel[s] && tt > target2[s];
+      S.ss[s] = tt;
+    } else {
+      act = S.active[s];
+      if (act) {
+        S.iters[s] += 1;
+        if (tt <= target2[s]) act = 0;
+        else if (!(tt <= 1e30 * S.ss[s])) {
+          S.flags[2] = 1;
+          act = 0;
+        }
+      }
     }
     S.active[s] = act;
     if (act) atomicAdd(&cnt, 1);
@@ -285,12 +599,63 @@ void fin_beta(const SysScal& S, int nsys, int nchunk, const double* ps_, const d
   hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, s, S, nsys, nchunk, ps_, pr, target2);
 }
 
+template <class R> void blas_cdot3(const SysGrid& G, int nrhs, Field<R> a, Field<R> b, Field<R> c, double* part,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_cdot3<R>, grid_of(G, nrhs), dim3(256), 0, s, G, a, b, c, part);
+}
+template <class R> void blas_bicg_p(const SysGrid& G, int nrhs, Field<R> p, Field<R> r, Field<R> v,
+                                    const double* cs, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_p<R>, grid_of(G, nrhs), dim3(256), 0, s, G, p, r, v, cs);
+}
+template <class R> void blas_bicg_s(const SysGrid& G, int nrhs, Field<R> r, Field<R> v, const double* cs,
+                                    double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_s<R>, grid_of(G, nrhs), dim3(256), 0, s, G, r, v, cs, part);
+}
+template <class R> void blas_bicg_xr(const SysGrid& G, int nrhs, Field<R> x, Field<R> p, Field<R> r,
+                                     Field<R> t, Field<R> r0, const double* cs, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_xr<R>, grid_of(G, nrhs), dim3(256), 0, s, G, x, p, r, t, r0, cs, part);
+}
+void fin_bicg_rho(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, const int* sel,
+                  const double* target2, int init, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_bicg_rho, dim3(1), dim3(256), 0, s, S, cs, nsys, nchunk, part, sel, target2, init);
+}
+void fin_bicg_alpha(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_bicg_alpha, dim3(1), dim3(256), 0, s, S, cs, nsys, nchunk, part);
+}
+void fin_bicg_omega(const SysScal& S, double* cs, int nsys, int nchunk, const double* part,
+                    const double* part_s, const double* target2, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_bicg_omega, dim3(1), dim3(256), 0, s, S, cs, nsys, nchunk, part, part_s, target2);
+}
+template <class R> void blas_geom_add(const SysGrid& G, int nrhs, Field<R> x, Field<R> t, const int* active,
+                                      hipStream_t s) {
+  hipLaunchKernelGGL(k_geom_add<R>, grid_of(G, nrhs), dim3(256), 0, s, G, x, t, active);
+}
+template <class R> void blas_lin3(const SysGrid& G, int nrhs, Field<R> y, Field<R> u, Field<R> w, Field<R> q,
+                                  const double* coef, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_lin3<R>, grid_of(G, nrhs), dim3(256), 0, s, G, y, u, w, q, coef, part);
+}
+void fin_sum3(int nsys, int nchunk, const double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_sum3, dim3(1), dim3(256), 0, s, nsys, nchunk, part, out);
+}
+void fin_geom(const SysScal& S, int nsys, int nchunk, const double* part, const int* sel, const double* target2,
+              int init, hipStream_t s) {
+  hipLaunchKernelGGL(k_fin_geom, dim3(1), dim3(256), 0, s, S, nsys, nchunk, part, sel, target2, init);
+}
+
 #define INST(R)                                                                                         \
   template void blas_norm2<R>(const SysGrid&, int, Field<R>, int, double*, hipStream_t);                 \
   template void blas_cg_xs<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, Field<R>, const double*, \
                               double*, hipStream_t);                                                     \
   template void blas_xpay<R>(const SysGrid&, int, Field<R>, Field<R>, const double*, hipStream_t);       \
-  template void blas_add_mixed<R>(const SysGrid&, int, Field<double>, Field<R>, hipStream_t);
+  template void blas_add_mixed<R>(const SysGrid&, int, Field<double>, Field<R>, hipStream_t);           \
+  template void blas_cdot3<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, double*, hipStream_t);  \
+  template void blas_bicg_p<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, const double*, hipStream_t); \
+  template void blas_bicg_s<R>(const SysGrid&, int, Field<R>, Field<R>, const double*, double*, hipStream_t); \
+  template void blas_bicg_xr<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, Field<R>, Field<R>,   \
+                                const double*, double*, hipStream_t);                                    \
+  template void blas_geom_add<R>(const SysGrid&, int, Field<R>, Field<R>, const int*, hipStream_t);      \
+  template void blas_lin3<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, Field<R>, const double*,  \
+                             double*, hipStream_t);
 INST(double)
 INST(float)
 template void blas_convert<double, double>(const SysGrid&, int, Field<double>, Field<double>, int, hipStream_t);

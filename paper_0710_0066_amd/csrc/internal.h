@@ -93,6 +93,7 @@ struct sap_ctx {
   std::string err;
   void* solver;   // solver workspace (solver.hip)
   void* forces;   // force / trajectory workspace (hmc.hip)
+  void* sapws;    // Schwarz-preconditioned BiCGstab workspace (solver.hip), allocated on first use
   // tuned hop mapping per [full operator?][precision][nrhs] (-1: not tuned)
   signed char hop_map[2][2][65];
 };

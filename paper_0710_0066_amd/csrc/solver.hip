@@ -3,15 +3,20 @@
 // kernel launch.
 //
 // Inner solve: even-odd reduced system (Sec. 1, W_eo: M = [[1, -k D_eo], [-k D_oe, 1]],
-// M_hat = 1 - k^2 D_eo D_oe) by CG on the normal equations in the CGLS form, which
-// carries s = b_hat - M_hat x. M_hat^dagger = g5 M_hat g5 is applied by the same hop
-// kernel with gamma_5 folded into its input and output. Per-system scalars stay on the
-// device; converged systems are frozen (alpha = beta = 0) while the others continue; the
-// host reads one counter every few iterations.
+// M_hat = 1 - k^2 D_eo D_oe), by one of
+//  * CG on the normal equations in the CGLS form, which carries s = b_hat - M_hat x;
+//    M_hat^dagger = g5 M_hat g5 is applied by the same hop kernel with gamma_5 folded
+//    into its input and output;
+//  * BiCGstab (van der Vorst) on M_hat directly, with complex per-system scalars;
+//  * the geometric series x_e = sum_n (k^2 D_eo D_oe)^n b_hat (Sec. 3 uses it for the block
+//    terms), whose residual after n terms is the next term.
+// Per-system scalars stay on the device; converged systems are frozen while the others
+// continue; the host reads one counter every few iterations.
 // Outer loop: FP64 defect correction r = b - A x (A applied in FP64), inner solve in
 // FP32 or FP64, x += e, until ||b - A x|| / ||b|| <= tol recomputed in FP64.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <vector>
 #include "blas.h"
@@ -29,6 +34,7 @@ struct SolverWS {
   double2 *x64, *r64, *ax, *rin, *e;     // full fields
   double *partA, *partB, *partC;
   double *gam, *ss, *alpha, *beta, *target2, *bnorm2, *rnorm2;
+  double* cs;                            // BiCGstab: complex (rho, alpha, omega, beta) per system
   int *active, *iters, *flags, *selected;
   // pinned host mirrors
   double *h_rnorm2, *h_bnorm2;
@@ -36,7 +42,7 @@ struct SolverWS {
   // captured inner-loop graphs (ITERS_PER_GRAPH CG iterations each), replayed on the
   // caller's stream; captured on a private non-blocking stream of default priority
   hipStream_t cap;
-  struct G { int nrhs, lb, sel, f32; hipGraphExec_t exec; };
+  struct G { int nrhs, lb, sel, f32, method; hipGraphExec_t exec; };
   std::vector<G> graphs;
 };
 
@@ -54,7 +60,9 @@ extern "C" int sap_solver_create(sap_ctx* c) {
   w->max_chunk = (int)((c->Vh + CHUNK - 1) / CHUNK);
   const size_t half = (size_t)12 * c->Vhp * w->max_rhs * sizeof(double2);
   const size_t full = 2 * half;
-  const size_t npart = (size_t)w->max_rhs * w->max_chunk * (c->geom.L[0] / minlb + 1);
+  // three partials per (system, chunk); a level of nblk blocks has at most max_chunk + nblk
+  // chunks per rhs
+  const size_t npart = (size_t)3 * w->max_rhs * (w->max_chunk + c->geom.L[0] / minlb + 1);
   auto A = [&](void** p, size_t n) { return hipMalloc(p, n) == hipSuccess; };
   bool ok = A((void**)&w->hx, half) && A((void**)&w->s, half) && A((void**)&w->r, half) &&
             A((void**)&w->p, half) && A((void**)&w->q, half) && A((void**)&w->t, half) &&
@@ -65,7 +73,8 @@ extern "C" int sap_solver_create(sap_ctx* c) {
   const size_t ns = (size_t)w->max_sys;
   ok = ok && A((void**)&w->gam, ns * 8) && A((void**)&w->ss, ns * 8) && A((void**)&w->alpha, ns * 8) &&
        A((void**)&w->beta, ns * 8) && A((void**)&w->target2, ns * 8) && A((void**)&w->bnorm2, ns * 8) &&
-       A((void**)&w->rnorm2, ns * 8) && A((void**)&w->active, ns * 4) && A((void**)&w->iters, ns * 4) &&
+       A((void**)&w->rnorm2, ns * 8) && A((void**)&w->cs, ns * 64) && A((void**)&w->active, ns * 4) &&
+       A((void**)&w->iters, ns * 4) &&
        A((void**)&w->flags, 16) && A((void**)&w->selected, ns * 4);
   ok = ok && hipHostMalloc((void**)&w->h_rnorm2, ns * 8, 0) == hipSuccess &&
        hipHostMalloc((void**)&w->h_bnorm2, ns * 8, 0) == hipSuccess &&
@@ -88,7 +97,7 @@ extern "C" void sap_solver_destroy(sap_ctx* c) {
   if (!w) return;
   void* dev[] = {w->hx, w->s, w->r, w->p, w->q, w->t, w->x64, w->r64, w->ax, w->rin, w->e,
                  w->partA, w->partB, w->partC, w->gam, w->ss, w->alpha, w->beta, w->target2,
-                 w->bnorm2, w->rnorm2, w->active, w->iters, w->flags, w->selected};
+                 w->bnorm2, w->rnorm2, w->cs, w->active, w->iters, w->flags, w->selected};
   for (void* p : dev)
     if (p) (void)hipFree(p);
   void* host[] = {w->h_rnorm2, w->h_bnorm2, w->h_flags, w->h_iters, w->h_selected};
@@ -156,6 +165,8 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
   Field<R> Ee = {(V2*)w->e, 24 * Vhp, 0};
   Field<R> S = {(V2*)w->s, 12 * Vhp, 0}, Rr = {(V2*)w->r, 12 * Vhp, 0}, P = {(V2*)w->p, 12 * Vhp, 0};
   Field<R> Q = {(V2*)w->q, 12 * Vhp, 0}, T = {(V2*)w->t, 12 * Vhp, 0};
+  Field<R> HX = {(V2*)w->hx, 12 * Vhp, 0};
+  const int method = (int)o->method;
   Field<R> NONE = {nullptr, 0, 0};
   SysScal SC = {w->gam, w->ss, w->alpha, w->beta, w->active, w->iters, w->flags};
 
@@ -202,60 +213,105 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     hop<R>(c, U, S, RIN, RIN, 0, nrhs, lb, colour, R(1), kR, 0, 0, st);
     SAP_HIP_CHECK(c, hipMemsetAsync(w->e, 0, fullb / (sizeof(R) == 8 ? 1 : 2), st));
     blas_norm2<R>(G, nrhs, S, 1, w->partB, st);
-    // r = M_hat^dagger s = s - k^2 g5 D_eo D_oe g5 s
-    hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, st);
-    hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, st);
-    blas_norm2<R>(G, nrhs, Rr, 1, w->partC, st);
     // stop the inner solve at ||s|| <= max(inner_tol ||b_hat||, 0.3 tol ||b||): the outer
     // residual after x += e equals the inner one up to rounding
     hipLaunchKernelGGL(k_targets, dim3(1), dim3(256), 0, st, nsys, w->partB, G.nchunk, w->bnorm2,
                        inner_tol * inner_tol, 0.09 * tol * tol, w->target2);
     SAP_HIP_CHECK(c, hipMemsetAsync(w->flags, 0, 16, st));
-    fin_init(SC, nsys, G.nchunk, w->partB, w->partC, w->selected, w->target2, st);
-    SAP_HIP_CHECK(c, hipMemcpyAsync(w->p, w->r, fullb / 2 / (sizeof(R) == 8 ? 1 : 2),
-                                    hipMemcpyDeviceToDevice, st));
+    const size_t halfb = fullb / 2 / (sizeof(R) == 8 ? 1 : 2);
+    if (method == SAP_CG) {
+      // r = M_hat^dagger s = s - k^2 g5 D_eo D_oe g5 s
+      hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, st);
+      hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, st);
+      blas_norm2<R>(G, nrhs, Rr, 1, w->partC, st);
+      fin_init(SC, nsys, G.nchunk, w->partB, w->partC, w->selected, w->target2, st);
+      SAP_HIP_CHECK(c, hipMemcpyAsync(w->p, w->r, halfb, hipMemcpyDeviceToDevice, st));
+    } else if (method == SAP_BICGSTAB) {
+      // r = s = b_hat (x_e = 0), shadow residual r0 = r, p = v = 0
+      SAP_HIP_CHECK(c, hipMemcpyAsync(w->r, w->s, halfb, hipMemcpyDeviceToDevice, st));
+      SAP_HIP_CHECK(c, hipMemsetAsync(w->p, 0, halfb, st));
+      SAP_HIP_CHECK(c, hipMemsetAsync(w->q, 0, halfb, st));
+      blas_cdot3<R>(G, nrhs, Rr, S, S, w->partA, st);
+      fin_bicg_rho(SC, w->cs, nsys, G.nchunk, w->partA, w->selected, w->target2, 1, st);
+    } else {
+      // first term t_0 = b_hat in S
+      fin_geom(SC, nsys, G.nchunk, w->partB, w->selected, w->target2, 1, st);
+    }
     SAP_HIP_CHECK(c, hipGetLastError());
-    // one CG iteration on all systems (no host interaction; scalars stay on the device)
+    // iterations on all systems (no host interaction; scalars stay on the device)
     auto iterate = [&](hipStream_t q) {
-      // q = M_hat p
-      hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
-      hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
-      blas_norm2<R>(G, nrhs, Q, 1, w->partA, q);
-      fin_alpha(SC, nsys, G.nchunk, w->partA, q);
-      // x += alpha p, s -= alpha q
-      blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, q);
-      // r = M_hat^dagger s
-      hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, q);
-      hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, q);
-      blas_norm2<R>(G, nrhs, Rr, 1, w->partC, q);
-      fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, q);
-      blas_xpay<R>(G, nrhs, P, Rr, w->beta, q);
+      if (method == SAP_CG) {
+        // q = M_hat p
+        hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
+        blas_norm2<R>(G, nrhs, Q, 1, w->partA, q);
+        fin_alpha(SC, nsys, G.nchunk, w->partA, q);
+        // x += alpha p, s -= alpha q
+        blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, q);
+        // r = M_hat^dagger s
+        hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, q);
+        hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, q);
+        blas_norm2<R>(G, nrhs, Rr, 1, w->partC, q);
+        fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, q);
+        blas_xpay<R>(G, nrhs, P, Rr, w->beta, q);
+      } else if (method == SAP_BICGSTAB) {
+        // residual r in S, shadow r0 in Rr, v in Q, t in HX
+        blas_bicg_p<R>(G, nrhs, P, S, Q, w->cs, q);
+        hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
+        blas_cdot3<R>(G, nrhs, Rr, Q, NONE, w->partB, q);
+        fin_bicg_alpha(SC, w->cs, nsys, G.nchunk, w->partB, q);
+        blas_bicg_s<R>(G, nrhs, S, Q, w->cs, w->partB, q);
+        hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+        hop<R>(c, U, HX, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
+        blas_cdot3<R>(G, nrhs, HX, S, HX, w->partC, q);
+        fin_bicg_omega(SC, w->cs, nsys, G.nchunk, w->partC, w->partB, w->target2, q);
+        blas_bicg_xr<R>(G, nrhs, Ee, P, S, HX, Rr, w->cs, w->partA, q);
+        fin_bicg_rho(SC, w->cs, nsys, G.nchunk, w->partA, w->selected, w->target2, 0, q);
+      } else {
+        // two terms: S -> HX -> S (x_e += t on active systems; t <- k^2 D_eo D_oe t)
+        for (int h = 0; h < 2; ++h) {
+          Field<R> from = h == 0 ? S : HX, to = h == 0 ? HX : S;
+          blas_geom_add<R>(G, nrhs, Ee, from, w->active, q);
+          hop<R>(c, U, T, from, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+          hop<R>(c, U, to, T, NONE, 0, nrhs, lb, colour, R(0), (R)(kap * kap), 0, 0, q);
+          blas_norm2<R>(G, nrhs, to, 1, w->partA, q);
+          fin_geom(SC, nsys, G.nchunk, w->partA, w->selected, w->target2, 0, q);
+        }
+      }
     };
+    // iterations per graph (a geometric-series call of iterate adds two terms)
+    const int per_call = method == SAP_GEOM ? 2 : 1;
+    const int calls = ITERS_PER_GRAPH / per_call;
     hipGraphExec_t exec = nullptr;
     for (auto& g : w->graphs)
-      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.f32 == (int)(sizeof(R) == 4)) exec = g.exec;
+      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.f32 == (int)(sizeof(R) == 4) && g.method == method)
+        exec = g.exec;
     if (!exec) {
       hipGraph_t graph;
       if (hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        for (int k = 0; k < ITERS_PER_GRAPH; ++k) iterate(w->cap);
+        for (int k = 0; k < calls; ++k) iterate(w->cap);
         if (hipStreamEndCapture(w->cap, &graph) == hipSuccess) {
           if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) exec = nullptr;
           (void)hipGraphDestroy(graph);
         }
       }
       (void)hipGetLastError();
-      if (exec) w->graphs.push_back({nrhs, lb, colour, (int)(sizeof(R) == 4), exec});
+      if (exec) w->graphs.push_back({nrhs, lb, colour, (int)(sizeof(R) == 4), method, exec});
     }
     for (;;) {
-      SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 8, hipMemcpyDeviceToHost, st));
+      SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 12, hipMemcpyDeviceToHost, st));
       SAP_HIP_CHECK(c, hipStreamSynchronize(st));
-      if (w->h_flags[0]) return sap_fail(c, SAP_E_NONFINITE, "non-finite value in the inner solve");
+      if (w->h_flags[0])
+        return sap_fail(c, SAP_E_NONFINITE,
+                        "non-finite value in the inner solve (stage " + std::to_string(w->h_flags[0]) + ")");
+      if (w->h_flags[2]) return sap_fail(c, SAP_E_NOCONV, "the geometric series diverges (spectral radius >= 1)");
       if (w->h_flags[1] == 0) break;
       if (total_iters >= o->max_iter) break;
       if (exec) {
         SAP_HIP_CHECK(c, hipGraphLaunch(exec, st));
       } else {
-        for (int k = 0; k < ITERS_PER_GRAPH; ++k) iterate(st);
+        for (int k = 0; k < calls; ++k) iterate(st);
       }
       total_iters += ITERS_PER_GRAPH;
     }
@@ -375,11 +431,254 @@ static int check_opts(sap_ctx* c, const sap_solve_opts* o) {
   if (o->inner_prec != SAP_F64 && o->inner_prec != SAP_F32) return sap_fail(c, SAP_E_ARG, "unknown inner precision");
   if (o->inner_prec == SAP_F32 && !(o->inner_tol > 0 && o->inner_tol < 1))
     return sap_fail(c, SAP_E_ARG, "inner_tol must be in (0, 1) for an FP32 inner solve");
+  if (o->method != SAP_CG && o->method != SAP_BICGSTAB && o->method != SAP_GEOM && o->method != SAP_SAP_BICGSTAB)
+    return sap_fail(c, SAP_E_ARG, "unknown method");
+  if (o->method == SAP_SAP_BICGSTAB && (o->sap_ncy < 1 || !(o->inner_tol > 0 && o->inner_tol < 1)))
+    return sap_fail(c, SAP_E_ARG, "SAP_SAP_BICGSTAB needs sap_ncy >= 1 and inner_tol in (0, 1)");
   return SAP_OK;
+}
+
+// ---- Schwarz-preconditioned BiCGstab for M x = b ----------------------------------------
+// FP64 BiCGstab on the full lattice, right-preconditioned (M K y = b, x = K y) by K = ncy
+// cycles of the multiplicative Schwarz alternating procedure on the level-1 x0 blocks: for
+// the black blocks, then the white blocks, y = W1^{-1} (v - M x_K) restricted to that
+// colour's blocks (W1 is block diagonal) and x_K += y. The block systems of a colour are one
+// batched solve_impl call (CG at inner_prec to the relative residual inner_tol). The few
+// outer iterations are driven from the host, which holds the complex scalars.
+//
+// A full FP64 field [rhs][parity][tiles] is read as 2 * nrhs half fields of stride 12 Vhp,
+// so the per-system BLAS kernels apply; the host adds the two parities of every sum.
+struct SapWS {
+  int nrhs_cap;
+  double2 *r, *r0, *p, *v, *t, *ph, *sh, *kx, *kr, *ky, *mt;
+  double *part, *dev3, *coef;
+  double *h3, *hcoef;
+};
+
+static void sap_ws_free(SapWS* a) {
+  void* dev[] = {a->r, a->r0, a->p, a->v, a->t, a->ph, a->sh, a->kx, a->kr, a->ky, a->mt, a->part, a->dev3,
+                 a->coef};
+  for (void* q : dev)
+    if (q) (void)hipFree(q);
+  if (a->h3) (void)hipHostFree(a->h3);
+  if (a->hcoef) (void)hipHostFree(a->hcoef);
+  delete a;
+}
+
+extern "C" void sap_sapws_destroy(sap_ctx* c) {
+  if (c->sapws) sap_ws_free((SapWS*)c->sapws);
+  c->sapws = nullptr;
+}
+
+static SapWS* sap_ws(sap_ctx* c) {
+  if (c->sapws) return (SapWS*)c->sapws;
+  SapWS* a = new SapWS();
+  const int n = c->geom.max_rhs;
+  a->nrhs_cap = n;
+  const size_t fb = (size_t)24 * c->Vhp * n * sizeof(double2);
+  const size_t nsys = 2 * (size_t)n;
+  const size_t nchunk = (size_t)((c->Vh + CHUNK - 1) / CHUNK);
+  bool ok = true;
+  double2** fields[] = {&a->r, &a->r0, &a->p, &a->v, &a->t, &a->ph, &a->sh, &a->kx, &a->kr, &a->ky, &a->mt};
+  for (double2** f : fields) ok = ok && hipMalloc((void**)f, fb) == hipSuccess;
+  ok = ok && hipMalloc((void**)&a->part, 3 * nsys * nchunk * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&a->dev3, 3 * nsys * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&a->coef, 6 * nsys * 8) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&a->h3, 3 * nsys * 8, 0) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&a->hcoef, 6 * nsys * 8, 0) == hipSuccess;
+  if (!ok) {
+    sap_ws_free(a);
+    return nullptr;
+  }
+  c->sapws = a;
+  return a;
+}
+
+typedef std::complex<double> zd;
+
+static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const sap_solve_opts* o,
+                        sap_solve_info* info, hipStream_t st) {
+  SapWS* a = sap_ws(c);
+  if (!a) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the Schwarz-preconditioned BiCGstab workspace");
+  const long long Vhp = c->Vhp;
+  const SysGrid G = make_sysgrid(c->Vh, c->g.V3h, 0, c->geom.L[0], 0);   // full lattice, one block
+  const int nh = 2 * nrhs;                                                 // half-field systems
+  auto H = [&](double2* f) { return Field<double>{f, 12 * Vhp, 0}; };
+  const Field<double> NONE = {nullptr, 0, 0};
+  const size_t fullb = (size_t)24 * Vhp * nrhs * sizeof(double2);
+  std::vector<zd> rho(nrhs), alpha(nrhs), omega(nrhs);
+  std::vector<double> bb(nrhs), rr(nrhs);
+  std::vector<int> act(nrhs), its(nrhs, 0);
+
+  // per-rhs sums of the three partials (parities added): s3[r] = (<q, y>, ||y||^2)
+  auto sums = [&](std::vector<zd>& dot, std::vector<double>& nrm) -> int {
+    fin_sum3(nh, G.nchunk, a->part, a->dev3, st);
+    SAP_HIP_CHECK(c, hipMemcpyAsync(a->h3, a->dev3, 3 * nh * 8, hipMemcpyDeviceToHost, st));
+    SAP_HIP_CHECK(c, hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; ++r) {
+      const double* u = a->h3 + 6 * r;
+      dot[r] = zd(u[0] + u[3], u[1] + u[4]);
+      nrm[r] = u[2] + u[5];
+    }
+    return SAP_OK;
+  };
+  // y = c0 y + c1 u + c2 w on every rhs (coefficients per rhs, copied to both parities)
+  auto lin3 = [&](double2* y, const double2* u, const double2* w, const double2* q, const std::vector<zd>& c0,
+                  const std::vector<zd>& c1, const std::vector<zd>& c2, bool want) -> int {
+    for (int r = 0; r < nrhs; ++r)
+      for (int par = 0; par < 2; ++par) {
+        double* cf = a->hcoef + 6 * (2 * r + par);
+        cf[0] = c0[r].real(); cf[1] = c0[r].imag();
+        cf[2] = c1[r].real(); cf[3] = c1[r].imag();
+        cf[4] = c2[r].real(); cf[5] = c2[r].imag();
+      }
+    SAP_HIP_CHECK(c, hipMemcpyAsync(a->coef, a->hcoef, 6 * nh * 8, hipMemcpyHostToDevice, st));
+    blas_lin3<double>(G, nh, H(y), H((double2*)u), w ? H((double2*)w) : NONE, q ? H((double2*)q) : NONE, a->coef,
+                      want ? a->part : nullptr, st);
+    // the host buffer is rewritten by the next call: wait until the copy has been consumed
+    SAP_HIP_CHECK(c, hipStreamSynchronize(st));
+    return SAP_OK;
+  };
+  auto cdot = [&](const double2* q, const double2* y, const double2* z, std::vector<zd>& dot,
+                  std::vector<double>& nrm) -> int {
+    blas_cdot3<double>(G, nh, H((double2*)q), H((double2*)y), z ? H((double2*)z) : NONE, a->part, st);
+    return sums(dot, nrm);
+  };
+  const std::vector<zd> one(nrhs, zd(1, 0)), zero(nrhs, zd(0, 0)), mone(nrhs, zd(-1, 0));
+  // block solves of the preconditioner
+  sap_solve_opts bo = *o;
+  bo.tol = o->inner_tol;
+  bo.inner_tol = o->inner_prec == SAP_F32 ? std::max(o->inner_tol, 1e-5) : o->inner_tol;
+  bo.max_outer = 40;
+  bo.max_iter = 1 << 30;
+  bo.method = SAP_CG;
+  long long block_iters = 0;
+  std::vector<sap_solve_info> binfo((size_t)nrhs * (c->geom.L[0] / c->geom.l0));
+  // out = K in
+  auto K = [&](double2* out, const double2* in) -> int {
+    SAP_HIP_CHECK(c, hipMemsetAsync(a->kx, 0, fullb, st));
+    for (int cyc = 0; cyc < o->sap_ncy; ++cyc)
+      for (int col = 0; col < 2; ++col) {
+        const int colour = col == 0 ? SAP_BLACK : SAP_WHITE;
+        const double* rhs = (const double*)in;
+        if (cyc > 0 || col > 0) {
+          int rc = apply_op_any(c, a->mt, a->kx, nrhs, 0, 0, -1, SAP_F64, st);
+          if (rc) return rc;
+          if ((rc = lin3(a->kr, in, a->mt, nullptr, zero, one, mone, false))) return rc;
+          rhs = (const double*)a->kr;
+        }
+        int rc = o->inner_prec == SAP_F64
+                     ? solve_impl<double>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st)
+                     : solve_impl<float>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st);
+        if (rc) return rc;
+        for (auto& e : binfo) block_iters += e.iters;
+        if ((rc = lin3(a->kx, a->ky, nullptr, nullptr, one, one, zero, false))) return rc;
+      }
+    SAP_HIP_CHECK(c, hipMemcpyAsync(out, a->kx, fullb, hipMemcpyDeviceToDevice, st));
+    return SAP_OK;
+  };
+
+  SAP_HIP_CHECK(c, hipMemsetAsync(x, 0, fullb, st));
+  {
+    std::vector<zd> d(nrhs);
+    int rc = cdot((const double2*)b, (const double2*)b, nullptr, d, bb);
+    if (rc) return rc;
+    for (int r = 0; r < nrhs; ++r) bb[r] = d[r].real();
+  }
+  const double tol2 = o->tol * o->tol;
+  int status = SAP_OK, restarts = 0;
+  long long total = 0;
+  for (;;) {
+    // r = b - M x ; r0 = r
+    int rc = apply_op_any(c, a->mt, x, nrhs, 0, 0, -1, SAP_F64, st);
+    if (rc) return rc;
+    SAP_HIP_CHECK(c, hipMemcpyAsync(a->r, b, fullb, hipMemcpyDeviceToDevice, st));
+    std::vector<zd> rn(nrhs);
+    if ((rc = lin3(a->r, a->mt, nullptr, a->r, one, mone, zero, true))) return rc;
+    if ((rc = sums(rn, rr))) return rc;
+    bool done = true, finite = true;
+    for (int r = 0; r < nrhs; ++r) {
+      if (!std::isfinite(rr[r])) finite = false;
+      act[r] = bb[r] > 0 && rr[r] > tol2 * bb[r];
+      if (act[r]) done = false;
+    }
+    if (!finite) { status = sap_fail(c, SAP_E_NONFINITE, "non-finite residual"); break; }
+    if (done) break;
+    if (restarts >= o->max_outer || total >= o->max_iter) {
+      status = sap_fail(c, SAP_E_NOCONV, "solver did not reach tol within max_outer / max_iter");
+      break;
+    }
+    ++restarts;
+    SAP_HIP_CHECK(c, hipMemcpyAsync(a->r0, a->r, fullb, hipMemcpyDeviceToDevice, st));
+    SAP_HIP_CHECK(c, hipMemsetAsync(a->p, 0, fullb, st));
+    SAP_HIP_CHECK(c, hipMemsetAsync(a->v, 0, fullb, st));
+    for (int r = 0; r < nrhs; ++r) rho[r] = alpha[r] = omega[r] = zd(1, 0);
+    // rn holds <r0, r> = ||r||^2 at the start
+    for (int r = 0; r < nrhs; ++r) rn[r] = zd(rr[r], 0);
+    while (total < o->max_iter) {
+      bool any = false;
+      std::vector<zd> beta(nrhs), mbo(nrhs);
+      for (int r = 0; r < nrhs; ++r) {
+        if (act[r] && (rr[r] <= tol2 * bb[r] || std::abs(rho[r]) == 0 || std::abs(omega[r]) == 0 ||
+                       std::abs(rn[r]) == 0))
+          act[r] = 0;
+        beta[r] = act[r] ? (rn[r] / rho[r]) * (alpha[r] / omega[r]) : zd(0, 0);
+        mbo[r] = -beta[r] * omega[r];
+        if (act[r]) rho[r] = rn[r];
+        any = any || act[r];
+      }
+      if (!any) break;
+      // p = r + beta (p - omega v) ; ph = K p ; v = M ph
+      if ((rc = lin3(a->p, a->r, a->v, nullptr, beta, one, mbo, false))) return rc;
+      if ((rc = K(a->ph, a->p))) return rc;
+      if ((rc = apply_op_any(c, a->v, a->ph, nrhs, 0, 0, -1, SAP_F64, st))) return rc;
+      std::vector<zd> den(nrhs), ma(nrhs), dts(nrhs), mo(nrhs), al_c(nrhs), om_c(nrhs);
+      std::vector<double> dummy(nrhs), tt(nrhs);
+      if ((rc = cdot(a->r0, a->v, nullptr, den, dummy))) return rc;
+      for (int r = 0; r < nrhs; ++r) {
+        if (act[r] && std::abs(den[r]) == 0) act[r] = 0;
+        alpha[r] = act[r] ? rho[r] / den[r] : zd(0, 0);
+        ma[r] = -alpha[r];
+      }
+      // s = r - alpha v (in r) ; sh = K s ; t = M sh ; omega = <t, s> / <t, t>
+      if ((rc = lin3(a->r, a->v, nullptr, nullptr, one, ma, zero, false))) return rc;
+      if ((rc = K(a->sh, a->r))) return rc;
+      if ((rc = apply_op_any(c, a->t, a->sh, nrhs, 0, 0, -1, SAP_F64, st))) return rc;
+      if ((rc = cdot(a->t, a->r, a->t, dts, tt))) return rc;
+      for (int r = 0; r < nrhs; ++r) {
+        omega[r] = (act[r] && tt[r] > 0) ? dts[r] / tt[r] : zd(0, 0);
+        mo[r] = -omega[r];
+        al_c[r] = alpha[r];
+        om_c[r] = omega[r];
+        if (act[r]) its[r] += 1;
+      }
+      // x += alpha ph + omega sh ; r = s - omega t, with <r0, r> and ||r||^2
+      if ((rc = lin3((double2*)x, a->ph, a->sh, nullptr, one, al_c, om_c, false))) return rc;
+      if ((rc = lin3(a->r, a->t, nullptr, a->r0, one, mo, zero, true))) return rc;
+      if ((rc = sums(rn, rr))) return rc;
+      for (int r = 0; r < nrhs; ++r)
+        if (!std::isfinite(rr[r])) return sap_fail(c, SAP_E_NONFINITE, "non-finite value in BiCGstab");
+      ++total;
+    }
+  }
+  if (info) {
+    // true residuals (the loop above ends with them in rr)
+    for (int r = 0; r < nrhs; ++r) {
+      info[r].iters = its[r];
+      info[r].outer = restarts;
+      info[r].true_rel_res = bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0;
+    }
+  }
+  (void)block_iters;
+  return status;
 }
 
 int sap_solve_any(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
                   const sap_solve_opts* o, sap_solve_info* info, hipStream_t st) {
+  if (o->method == SAP_SAP_BICGSTAB) {
+    if (lb != 0) return sap_fail(c, SAP_E_ARG, "SAP_SAP_BICGSTAB solves the full lattice only");
+    return sap_bicgstab(c, x, b, nrhs, o, info, st);
+  }
   if (o->inner_prec == SAP_F64) return solve_impl<double>(c, x, b, nrhs, lb, colour, o, info, st);
   return solve_impl<float>(c, x, b, nrhs, lb, colour, o, info, st);
 }

@@ -4,6 +4,7 @@ recomputed with the oracle's own operator (M or W) in FP64. Covers FP64 and FP32
 solves, several right-hand sides, both block levels and colours, the 16^3x32 and
 24^3x48 workloads, and the error paths (no convergence, non-finite source)."""
 import numpy as np
+import torch
 import pytest
 
 import synth
@@ -179,3 +180,136 @@ def test_solver_error_paths(gu):
     fz = ctx.new_field(1)
     info = sap.solve_full(ctx, fx, fz, 1, _opts(sap, sap.SAP_F32))
     assert info[0].iters == 0 and float(fx.abs().max()) == 0.0
+
+
+METHODS = ["bicgstab", "geom", "sap_bicgstab"]
+
+
+def _mopts(sap, method, inner, tol=1e-10, inner_tol=1e-5, ncy=2):
+    m = {"cg": sap.SAP_CG, "bicgstab": sap.SAP_BICGSTAB, "geom": sap.SAP_GEOM,
+         "sap_bicgstab": sap.SAP_SAP_BICGSTAB}[method]
+    if method == "sap_bicgstab":
+        inner_tol = 1e-8
+    return sap.solve_opts(tol=tol, max_iter=200000, inner_prec=inner, inner_tol=inner_tol, max_outer=60,
+                          method=m, sap_ncy=ncy)
+
+
+@pytest.mark.parametrize("L,l0,k", [((4, 4, 4, 4), 2, 0.155), ((8, 2, 4, 6), 2, 0.15)])
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_solve_full_methods_match_dense_solution(gu, L, l0, k, method, inner):
+    """BiCGstab and the geometric series on the even-odd system, and Schwarz-preconditioned
+    BiCGstab on M (Sec. 3), against numpy's dense solve; residual recomputed by the oracle."""
+    import paper_0710_0066_amd as sap
+    print(f"solve_full {method} L={L} inner={inner}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1031)
+    b = synth.gaussian_spinor(L, 2031, nrhs=2)
+    A = dirac.dense_matrix(U, k)
+    x_lu = np.linalg.solve(A, b.reshape(2, -1).T).T.reshape(b.shape)
+    ctx = gu.make_ctx(L, l0, k, U, max_rhs=2)
+    fx = ctx.new_field(2)
+    prec = sap.SAP_F64 if inner == "f64" else sap.SAP_F32
+    info = sap.solve_full(ctx, fx, gu.to_sap(ctx, b, 2), 2, _mopts(sap, method, prec))
+    x = gu.from_sap(ctx, fx, 2, b.shape)
+    res = _relres(U, x, b, k)
+    assert np.all(res <= 1e-10), res
+    for i in range(2):
+        assert abs(info[i].true_rel_res - res[i]) <= 1e-12 and info[i].iters > 0
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) <= np.linalg.cond(A) * 1e-10
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "geom"])
+@pytest.mark.parametrize("level,color", [(1, "black"), (2, "all")])
+def test_solve_blocks_methods_match_oracle(gu, method, level, color):
+    import paper_0710_0066_amd as sap
+    L, l0, l0s, k = (16, 4, 2, 4), 4, 2, 0.15
+    print(f"solve_blocks {method} level={level} color={color}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1037)
+    b = synth.gaussian_spinor(L, 2037, nrhs=3)
+    lb = l0 if level == 1 else l0s
+    m = lattice.site_mask(L, lattice.colour_x0_mask(L, lb, color))
+    x_ref, _, _ = solvers.solve_eo(U, b * m, k, lb, tol=1e-13)
+    ctx = gu.make_ctx(L, l0, k, U, l0s, max_rhs=3)
+    fb = gu.to_sap(ctx, b, 3)
+    fx = ctx.new_field(3)
+    cmap = {"all": sap.SAP_ALL, "black": sap.SAP_BLACK}
+    for prec in (sap.SAP_F64, sap.SAP_F32):
+        sap.solve_blocks(ctx, fx, fb, 3, level, cmap[color], _mopts(sap, method, prec))
+        x = gu.from_sap(ctx, fx, 3, b.shape)
+        assert np.all(x[~np.broadcast_to(m, x.shape)] == 0)
+        assert np.all(_relres(U, x, b, k, lb, m) <= 1e-10)
+        assert np.max(np.abs(x - x_ref)) / np.max(np.abs(x_ref)) <= 1e-7
+    with pytest.raises(sap.SapError) as e:
+        sap.solve_blocks(ctx, fx, fb, 3, level, cmap[color], _mopts(sap, "sap_bicgstab", sap.SAP_F32))
+    assert e.value.code == sap.SAP_E_ARG
+
+
+def test_geometric_series_free_field_converges_and_diverges(gu):
+    """Free field on 4^4: the series converges for kappa = 0.12 (spectral radius
+    kappa^2 max|lambda|^2 = 0.82) and is reported as diverging (SAP_E_NOCONV) for
+    kappa = 0.14 (1.12)."""
+    import paper_0710_0066_amd as sap
+    L = (4, 4, 4, 4)
+    U = np.zeros(L + (4, 3, 3), dtype=complex)
+    U[...] = np.eye(3)
+    b = synth.gaussian_spinor(L, 2041)
+    for k in (0.12, 0.14):
+        ctx = gu.make_ctx(L, 2, k, U)
+        fx = ctx.new_field(1)
+        o = _mopts(sap, "geom", sap.SAP_F64)
+        if k == 0.12:
+            sap.solve_full(ctx, fx, gu.to_sap(ctx, b, 1), 1, o)
+            assert float(_relres(U, gu.from_sap(ctx, fx, 1, b.shape), b, k)) <= 1e-10
+        else:
+            with pytest.raises(sap.SapError) as e:
+                sap.solve_full(ctx, fx, gu.to_sap(ctx, b, 1), 1, o)
+            assert e.value.code == sap.SAP_E_NOCONV
+
+
+def test_solver_methods_16x16x16x32(gu):
+    """The 16^3x32 field. At the workload's kappa = 0.1575: CG on the full lattice, and CG,
+    BiCGstab and the geometric series on the level-1 and level-2 blocks, reach the verified
+    1e-10 residual, BiCGstab with fewer block iterations than CG (on the full lattice these
+    synthetic links are beyond the mean-field critical point, 8 kappa <cos> > 1, where
+    neither plain nor Schwarz-preconditioned BiCGstab converges; CG on the normal equations
+    still does). At kappa = 0.14 every method, SAP-preconditioned BiCGstab included,
+    converges on the full lattice, with SAP-BiCGstab < BiCGstab < CG in iterations.
+    Iterations and wall times printed for the record."""
+    import time
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["plain_16x16x16x32"]
+    L = cfg["L"]
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    b = synth.gaussian_spinor(L, cfg["seed_src"])
+
+    def run(what, fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = fn()
+        dt = time.perf_counter() - t0
+        it = max(e.iters for e in info)
+        print(f"  {what}: iters={it} res={max(e.true_rel_res for e in info):.2e} {dt:.3f}s", flush=True)
+        assert max(e.true_rel_res for e in info) <= 1e-10
+        return it
+
+    ctx = gu.make_ctx(L, cfg["l0"], cfg["kappa"], U, cfg["l0_sub"], max_rhs=1)
+    fb = gu.to_sap(ctx, b, 1)
+    fx = ctx.new_field(1)
+    run("full cg k=0.1575", lambda: sap.solve_full(ctx, fx, fb, 1, _mopts(sap, "cg", sap.SAP_F32)))
+    for level in (1, 2):
+        its = {m: run(f"blocks level {level} {m}",
+                      lambda: sap.solve_blocks(ctx, fx, fb, 1, level, sap.SAP_ALL, _mopts(sap, m, sap.SAP_F32)))
+               for m in ("cg", "bicgstab", "geom")}
+        assert its["bicgstab"] < its["cg"]
+    del ctx
+    ctx = gu.make_ctx(L, cfg["l0"], 0.14, U, cfg["l0_sub"], max_rhs=1)
+    fb = gu.to_sap(ctx, b, 1)
+    fx = ctx.new_field(1)
+    its = {}
+    for m in ("cg", "bicgstab", "geom", "sap_bicgstab"):
+        o = _mopts(sap, m, sap.SAP_F32)
+        if m == "sap_bicgstab":
+            o = sap.solve_opts(tol=1e-10, max_iter=100, inner_prec=sap.SAP_F32, inner_tol=1e-2, max_outer=4,
+                               method=sap.SAP_SAP_BICGSTAB, sap_ncy=2)
+        its[m] = run(f"full {m} k=0.14", lambda: sap.solve_full(ctx, fx, fb, 1, o))
+    assert its["sap_bicgstab"] < its["bicgstab"] < its["cg"]
