@@ -81,13 +81,13 @@ def pf_action(U, phi, kappa, l0, tol=1e-12, W_inv=None):
     return float(np.sum(np.abs(X) ** 2))
 
 
-def schwarz_force(U, chi, kappa, l0, S: "sz.Solvers"):
-    """Force of S_R = ||R_hat^{-1} chi||^2."""
+def schwarz_force(U, chi, kappa, l0, S: "sz.Solvers", outer=None):
+    """Force of S_R = ||R_hat^{-1} chi||^2 (outer operator M, or W_outer)."""
     L = U.shape[:4]
-    eta, psi = sz.apply_Rhat_inv(U, chi, kappa, l0, S)
-    xi = S.Mdag_inv(sz.Pi(eta, L, l0))
+    eta, psi = sz.apply_Rhat_inv(U, chi, kappa, l0, S, outer)
+    xi = S.Mdag_inv(sz.Pi(eta, L, l0, outer))
     _, wht = sz.black_white_masks(L, l0)
-    return pair_force(U, xi, psi, kappa) - pair_force(U, wht * xi, chi, kappa)
+    return pair_force(U, xi, psi, kappa, outer) - pair_force(U, wht * xi, chi, kappa, outer)
 
 
 def plaquette_field(U):
