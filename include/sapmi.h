@@ -134,6 +134,37 @@ typedef struct {
   long long solver_iters; /* inner iterations of every solve in the trajectory */
 } sap_hmc_info;
 
+/* Trajectory with the paper's four-part pseudo-fermion action (Sec. 1, end; Sec. 2):
+ * det^2 M = det^2(M W1^-1) det^2(W1 W2^-1) det^2(W2eo W3eo^-1) det^2(W3eo), W3eo = W2eo + rho,
+ * integrated on five levels: 0 gauge action, 1 S1 = ||W3eo^-1 phi1||^2,
+ * 2 S2 = ||phi2 + rho W2eo^-1 phi2||^2, 3 S3 (Schwarz term of W1 over the level-2
+ * blocks), 4 S4 (Schwarz term of M over the level-1 blocks). */
+typedef struct {
+  double beta, tau, lambda;
+  double rho;             /* mass-preconditioning shift of W3eo */
+  int n[5];               /* n_j: steps of level j inside one step of level j + 1
+                           * (n_4: steps per trajectory), Table 1 */
+  int scheme[5];          /* per level: 0 leap-frog, 1 Sexton-Weingarten (the paper: 1, 1,
+                           * 0, 0, 0); a Sexton-Weingarten level j > 0 needs an even n_{j-1} */
+  sap_solve_opts force_solve, action_solve;
+  const double* p0;       /* momenta, sap layout (device) */
+  const double* xi1;      /* heat-bath noise, canonical spinors (device): phi1 = W3eo P_e xi1, */
+  const double* xi2;      /*   phi2 = W3eo^-1 W2eo P_e xi2, */
+  const double* g3;       /*   chi3 = R_hat_2 Pi_2 g3, */
+  const double* g4;       /*   chi4 = R_hat Pi g4 */
+  double u_metropolis;
+  const double* step_scale; /* host [L0][4] or NULL, as in sap_hmc_params */
+  int time_shift;
+} sap_hmc4_params;
+
+typedef struct {
+  double dH, H0, H1;
+  double S0[5], S1[5];    /* (S_G, S1, S2, S3, S4) at the start and at the end */
+  double plaq;
+  int accepted;
+  long long solver_iters;
+} sap_hmc4_info;
+
 /* ---- context ---------------------------------------------------------------- */
 
 /* Version of this ABI (major*100 + minor). */
@@ -298,6 +329,31 @@ int sap_shift_gauge(sap_ctx* ctx, int n, void* stream);
  * output). Synchronises. */
 int sap_plaquette(sap_ctx* ctx, double* plaq_out, void* stream);
 
+/* ---- the four-part action (Sec. 1, end) ------------------------------------------ */
+
+/* Even-odd pseudo-fermion parts on the level-2 blocks (needs l0_sub > 0): W2eo =
+ * 1 - k^2 D_eo D_oe with the hops of the level-2 blocks, on the even sites; W3eo = W2eo +
+ * rho (rho >= 0). kind 1: S1 = ||W3eo^-1 phi||^2; kind 2: S2 = ||phi + rho W2eo^-1 phi||^2
+ * (= ||W2eo^-1 W3eo phi||^2). Fields are FP64 sap-layout spinors whose odd half is zero.
+ * Heat bath: phi = W3eo P_e xi (kind 1) or W3eo^-1 W2eo P_e xi (kind 2), so that S equals
+ * ||P_e xi||^2. Force: F += coef * dS/dw (F NULL: action only); *S_out (host, may be
+ * NULL) receives S. Solves by opts on the even-odd system (not SAP_GEOM). Synchronise. */
+int eo_pf_heat_bath(sap_ctx* ctx, double* phi, const double* xi, int kind, double rho,
+                    const sap_solve_opts* opts, void* stream);
+int eo_pf_force(sap_ctx* ctx, double* F, double coef, const double* phi, int kind, double rho,
+                const sap_solve_opts* opts, double* S_out, void* stream);
+
+/* The factor det^2(W1 W2^-1): the Schwarz term of W1 over the level-2 blocks (needs
+ * l0_sub > 0). Black level-2 blocks have odd index; Pi_2 is (1 - g0)/2 on the first and
+ * (1 + g0)/2 on the last slice of each black level-2 block where W1 has the crossing hop
+ * (a slice next to a level-1 block boundary has none and is left out).
+ * Heat bath: chi = R_hat_2 Pi_2 g. Force: F += coef * dS/dw of S = ||R_hat_2^-1 chi||^2
+ * (F NULL: action only; chi must lie in the range of Pi_2, else SAP_E_ARG). Synchronise. */
+int schwarz2_heat_bath(sap_ctx* ctx, double* chi, const double* g, const sap_solve_opts* opts,
+                       void* stream);
+int schwarz2_force(sap_ctx* ctx, double* F, double coef, const double* chi, const sap_solve_opts* opts,
+                   double* S_out, void* stream);
+
 /* ---- HMC ------------------------------------------------------------------------ */
 
 /* One HMC trajectory (Sec. 2) with two time scales: the outer level integrates
@@ -309,6 +365,15 @@ int sap_plaquette(sap_ctx* ctx, double* plaq_out, void* stream);
  * time_shift != 0); the context's gauge copies end equal to U. info: host. */
 int hmc_trajectory(sap_ctx* ctx, double* U, const sap_hmc_params* p, sap_hmc_info* info,
                    void* stream);
+
+/* One HMC trajectory with the four-part action on five time scales (Sec. 2: level j
+ * integrates S_j, n_j steps of level j in one step of level j + 1, a trajectory is n_4
+ * steps of level 4; Table 1 uses Sexton-Weingarten for levels 0, 1 and leap-frog for 2..4),
+ * heat baths from the given noise, Metropolis with u_metropolis, optional x0-dependent
+ * step sizes and translation as in hmc_trajectory. U: canonical gauge field, replaced by
+ * the resulting one. Needs l0_sub > 0. info: host. */
+int hmc_trajectory_4pf(sap_ctx* ctx, double* U, const sap_hmc4_params* p, sap_hmc4_info* info,
+                       void* stream);
 
 #ifdef __cplusplus
 }

@@ -61,6 +61,21 @@ class sap_hmc_params(ctypes.Structure):
                 ("time_shift", ctypes.c_int)]
 
 
+class sap_hmc4_params(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("tau", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("rho", ctypes.c_double), ("n", ctypes.c_int * 5), ("scheme", ctypes.c_int * 5),
+                ("force_solve", sap_solve_opts), ("action_solve", sap_solve_opts),
+                ("p0", ctypes.c_void_p), ("xi1", ctypes.c_void_p), ("xi2", ctypes.c_void_p),
+                ("g3", ctypes.c_void_p), ("g4", ctypes.c_void_p), ("u_metropolis", ctypes.c_double),
+                ("step_scale", ctypes.c_void_p), ("time_shift", ctypes.c_int)]
+
+
+class sap_hmc4_info(ctypes.Structure):
+    _fields_ = [("dH", ctypes.c_double), ("H0", ctypes.c_double), ("H1", ctypes.c_double),
+                ("S0", ctypes.c_double * 5), ("S1", ctypes.c_double * 5), ("plaq", ctypes.c_double),
+                ("accepted", ctypes.c_int), ("solver_iters", ctypes.c_longlong)]
+
+
 class sap_hmc_info(ctypes.Structure):
     _fields_ = [("dH", ctypes.c_double), ("H0", ctypes.c_double), ("H1", ctypes.c_double),
                 ("S_G0", ctypes.c_double), ("S_G1", ctypes.c_double),
@@ -104,6 +119,11 @@ _SIGS = {
     "sap_tune": ([_P, _I, _P, _P], _I),
     "sap_set_hop_map": ([_P, _I, _I, _I, _I], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
+    "hmc_trajectory_4pf": ([_P, _P, ctypes.POINTER(sap_hmc4_params), ctypes.POINTER(sap_hmc4_info), _P], _I),
+    "eo_pf_heat_bath": ([_P, _P, _P, _I, _D, ctypes.POINTER(sap_solve_opts), _P], _I),
+    "eo_pf_force": ([_P, _P, _D, _P, _I, _D, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
+    "schwarz2_heat_bath": ([_P, _P, _P, ctypes.POINTER(sap_solve_opts), _P], _I),
+    "schwarz2_force": ([_P, _P, _D, _P, ctypes.POINTER(sap_solve_opts), _P, _P], _I),
 }
 for _name, (_args, _ret) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -248,6 +268,54 @@ def sap_force_profile(ctx, F):
     out = (ctypes.c_double * (2 * L0))()
     _check(ctx.ptr, _lib.sap_force_profile(ctx.ptr, _ptr(F), out, _stream()))
     return [list(out[:L0]), list(out[L0:])]
+
+
+def eo_pf_heat_bath(ctx, phi, xi, kind, rho, opts):
+    _check(ctx.ptr, _lib.eo_pf_heat_bath(ctx.ptr, _ptr(phi), _ptr(xi), kind, rho, ctypes.byref(opts), _stream()))
+
+
+def eo_pf_force(ctx, F, coef, phi, kind, rho, opts):
+    """F += coef * dS/dw of S1 (kind 1) or S2 (kind 2); F None: action only. Returns S."""
+    S = ctypes.c_double(0.0)
+    _check(ctx.ptr, _lib.eo_pf_force(ctx.ptr, _ptr(F) if F is not None else None, coef, _ptr(phi), kind, rho,
+                                     ctypes.byref(opts), ctypes.byref(S), _stream()))
+    return S.value
+
+
+def schwarz2_heat_bath(ctx, chi, g, opts):
+    _check(ctx.ptr, _lib.schwarz2_heat_bath(ctx.ptr, _ptr(chi), _ptr(g), ctypes.byref(opts), _stream()))
+
+
+def schwarz2_force(ctx, F, coef, chi, opts):
+    """F += coef * dS/dw of the level-2 Schwarz term (S3); F None: action only. Returns S."""
+    S = ctypes.c_double(0.0)
+    _check(ctx.ptr, _lib.schwarz2_force(ctx.ptr, _ptr(F) if F is not None else None, coef, _ptr(chi),
+                                        ctypes.byref(opts), ctypes.byref(S), _stream()))
+    return S.value
+
+
+def hmc4_params(beta, tau, rho, n, p0, xi1, xi2, g3, g4, u_metropolis, force_solve, action_solve,
+                scheme=(1, 1, 0, 0, 0), lam=1.0 / 6.0, step_scale=None, time_shift=0):
+    P = sap_hmc4_params()
+    P.beta, P.tau, P.lambda_, P.rho = beta, tau, lam, rho
+    P.n = (ctypes.c_int * 5)(*n)
+    P.scheme = (ctypes.c_int * 5)(*scheme)
+    P.force_solve, P.action_solve = force_solve, action_solve
+    P.p0, P.xi1, P.xi2 = p0.data_ptr(), xi1.data_ptr(), xi2.data_ptr()
+    P.g3, P.g4 = g3.data_ptr(), g4.data_ptr()
+    P.u_metropolis = u_metropolis
+    if step_scale is not None:
+        import numpy as np
+        P._scale = np.ascontiguousarray(step_scale, dtype=np.float64)
+        P.step_scale = P._scale.ctypes.data
+    P.time_shift = time_shift
+    return P
+
+
+def hmc_trajectory_4pf(ctx, U, params):
+    info = sap_hmc4_info()
+    _check(ctx.ptr, _lib.hmc_trajectory_4pf(ctx.ptr, _ptr(U), ctypes.byref(params), ctypes.byref(info), _stream()))
+    return info
 
 
 def sap_shift_gauge(ctx, n):

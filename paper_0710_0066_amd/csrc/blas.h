@@ -44,8 +44,9 @@ template <class R> void blas_xpay(const SysGrid& G, int nrhs, Field<R> p, Field<
 template <class Ro, class Ri> void blas_convert(const SysGrid& G, int nrhs, Field<Ro> out, Field<Ri> in,
                                                 int npar, hipStream_t s);
 template <class R> void blas_add_mixed(const SysGrid& G, int nrhs, Field<double> x, Field<R> e, hipStream_t s);
+// r = b - Ax over the first npar parities (2: both; 1: the even sites), partial ||r||^2
 void blas_resid(const SysGrid& G, int nrhs, Field<double> r, Field<double> b, Field<double> Ax, double* part,
-                hipStream_t s);
+                hipStream_t s, int npar = 2);
 void fin_sum(int nsys, int nchunk, const double* part, double* out, hipStream_t s);
 void fin_init(const SysScal& S, int nsys, int nchunk, const double* pb, const double* pr, const int* sel,
               const double* target2, hipStream_t s);

@@ -154,12 +154,12 @@ __global__ __launch_bounds__(256) void k_add_mixed(SysGrid G, Field<double> x, F
   }
 }
 
-// r = b - Ax (FP64, both parities), partial ||r||^2
+// r = b - Ax (FP64, the first npar parities: 2 both, 1 even only), partial ||r||^2
 __global__ __launch_bounds__(256) void k_resid(SysGrid G, Field<double> r, Field<double> b,
-                                               Field<double> Ax, double* part) {
+                                               Field<double> Ax, double* part, int npar) {
   const Tile t = tile_of(G);
   double acc = 0.0;
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < npar; ++p) {
     double2* rb = r.ptr + t.rhs * r.rs + p * r.ps;
     const double2* bb = b.ptr + t.rhs * b.rs + p * b.ps;
     const double2* ab = Ax.ptr + t.rhs * Ax.rs + p * Ax.ps;
@@ -581,8 +581,8 @@ template <class R> void blas_add_mixed(const SysGrid& G, int nrhs, Field<double>
   hipLaunchKernelGGL(k_add_mixed<R>, grid_of(G, nrhs), dim3(256), 0, s, G, x, e);
 }
 void blas_resid(const SysGrid& G, int nrhs, Field<double> r, Field<double> b, Field<double> Ax, double* part,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_resid, grid_of(G, nrhs), dim3(256), 0, s, G, r, b, Ax, part);
+                hipStream_t s, int npar) {
+  hipLaunchKernelGGL(k_resid, grid_of(G, nrhs), dim3(256), 0, s, G, r, b, Ax, part, npar);
 }
 void fin_sum(int nsys, int nchunk, const double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(256), 0, s, nsys, nchunk, part, out);

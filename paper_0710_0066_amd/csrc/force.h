@@ -18,8 +18,12 @@ void launch_kinetic(const Geo& g, const double* P, double* part, double* out, hi
 void launch_norm2_full(const Geo& g, const double2* f, double* part, double* out, hipStream_t s);
 void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s,
                          const double* sx = nullptr);
-// mode 0: gamma5; 1: Pi (black-boundary projector, blocks of l0); 2: keep white blocks; 3: in - Pi in2
+// mode 0: gamma5; 1: Pi (black-boundary projector, blocks of l0); 2: keep white blocks; 3: in - Pi in2.
+// outer > 0: Pi keeps only the boundary slices whose crossing hop exists in W_outer.
 void launch_spin_op(const Geo& g, int mode, int l0, double2* out, const double2* in, const double2* in2,
+                    hipStream_t s, int outer = 0);
+// out = a x + b y (FP64 spinor fields, both parities)
+void launch_lincomb(const Geo& g, double2* out, double a, const double2* x, double b, const double2* y,
                     hipStream_t s);
 // x0 profile of |F| (out: [2][L0], spatial then time means; part: 2 * L0 * nck doubles
 // with nck = force_profile_nck(g))

@@ -359,8 +359,8 @@ __global__ __launch_bounds__(256) void k_shift_links(Geo g, double2* out, const 
 // elementwise helpers on full FP64 spinor fields (both parities, valid sites only)
 // mode 0: out = gamma5 in;  1: out = Pi in (black-block boundary projector);
 // mode 2: out = in on white blocks, 0 on black;  3: out = a - Pi b
-__global__ __launch_bounds__(256) void k_spin_op(Geo g, int mode, int l0, double2* out, const double2* in,
-                                                 const double2* in2) {
+__global__ __launch_bounds__(256) void k_spin_op(Geo g, int mode, int l0, int outer, double2* out,
+                                                 const double2* in, const double2* in2) {
   const int p = threadIdx.x >> 7;
   const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
   if (j >= g.Vh) return;
@@ -375,7 +375,9 @@ __global__ __launch_bounds__(256) void k_spin_op(Geo g, int mode, int l0, double
   } else if (mode == 1 || mode == 3) {
     // first slice of a black block: (1 - g0)/2 -> h = (u + d)/2, (h, h)
     // last slice of a black block:  (1 + g0)/2 -> h = (u - d)/2, (h, -h)
-    const bool first = black && r == 0, last = black && r == l0 - 1;
+    // with an outer block length, only the slices whose crossing hop exists in W_outer
+    const bool first = black && r == 0 && !(outer && s.x0 % outer == 0);
+    const bool last = black && r == l0 - 1 && !(outer && s.x0 % outer == outer - 1);
     for (int c = 0; c < 3; ++c)
       for (int k = 0; k < 2; ++k) {
         C h = {0.0, 0.0};
@@ -462,6 +464,18 @@ __global__ void k_force_profile_fin(Geo g, int nck, const double* part, double* 
   out[g.L0 + x0] = vt / V3;
 }
 
+// out = a x + b y over a whole FP64 spinor field (both parities, padding included)
+__global__ void k_lincomb(long long n, double2* out, double a, const double2* x, double b, const double2* y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double2 u = x[i], v = y[i];
+    double2 w;
+    w.x = a * u.x + b * v.x;
+    w.y = a * u.y + b * v.y;
+    out[i] = w;
+  }
+}
+
 // p += c * F over the whole momentum buffer
 __global__ void k_axpy_mom(long long n, double* p, double c, const double* F) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -498,8 +512,13 @@ void launch_update_links(const Geo& g, double2* U, const double* P, double dt, h
   hipLaunchKernelGGL(k_update_links, dim3(site_blocks(g)), dim3(256), 0, s, g, U, P, dt, sx);
 }
 void launch_spin_op(const Geo& g, int mode, int l0, double2* out, const double2* in, const double2* in2,
+                    hipStream_t s, int outer) {
+  hipLaunchKernelGGL(k_spin_op, dim3(site_blocks(g)), dim3(256), 0, s, g, mode, l0, outer, out, in, in2);
+}
+void launch_lincomb(const Geo& g, double2* out, double a, const double2* x, double b, const double2* y,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_spin_op, dim3(site_blocks(g)), dim3(256), 0, s, g, mode, l0, out, in, in2);
+  const long long n = 24 * g.Vhp;
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, out, a, x, b, y);
 }
 int force_profile_nck(const Geo& g) { return (g.V3h + 127) / 128; }
 void launch_force_profile(const Geo& g, const double* F, double* part, double* out, hipStream_t s) {

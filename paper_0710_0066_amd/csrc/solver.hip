@@ -42,7 +42,7 @@ struct SolverWS {
   // captured inner-loop graphs (ITERS_PER_GRAPH CG iterations each), replayed on the
   // caller's stream; captured on a private non-blocking stream of default priority
   hipStream_t cap;
-  struct G { int nrhs, lb, sel, f32, method; hipGraphExec_t exec; };
+  struct G { int nrhs, lb, sel, f32, method; double rho; hipGraphExec_t exec; };
   std::vector<G> graphs;
 };
 
@@ -147,8 +147,12 @@ void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int p
 }  // namespace
 
 template <class R>
+// eo_only: solve (M_hat + rho) x_e = b_e on the even sites (x and b vanish on the odd
+// sites; no reconstruction; residual on the even sites), the form the mass-preconditioned
+// action parts need. Otherwise rho must be 0.
 static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
-                      const sap_solve_opts* o, sap_solve_info* info, hipStream_t st) {
+                      const sap_solve_opts* o, sap_solve_info* info, hipStream_t st, double rho = 0.0,
+                      bool eo_only = false) {
   typedef typename vec2<R>::type V2;
   SolverWS* w = ws_of(c);
   const long long Vh = c->Vh, Vhp = c->Vhp;
@@ -157,7 +161,10 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
   const double kap = c->geom.kappa;
   const void* U = sizeof(R) == 8 ? (const void*)c->U64 : (const void*)c->U32;
   const R kR = (R)kap, k2R = (R)(-kap * kap);
+  const R aI = (R)(1.0 + rho);                 // unit term of M_hat + rho
   const size_t fullb = (size_t)24 * Vhp * nrhs * sizeof(double2);
+  if (o->method == SAP_GEOM && (eo_only || rho != 0.0))
+    return sap_fail(c, SAP_E_ARG, "the geometric series is available for the unshifted W x = b only");
 
   Field<double> X = {(double2*)x, 24 * Vhp, 12 * Vhp}, B = {(double2*)b, 24 * Vhp, 12 * Vhp};
   Field<double> R64 = {w->r64, 24 * Vhp, 12 * Vhp}, AX = {w->ax, 24 * Vhp, 12 * Vhp};
@@ -222,7 +229,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     if (method == SAP_CG) {
       // r = M_hat^dagger s = s - k^2 g5 D_eo D_oe g5 s
       hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, st);
-      hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, st);
+      hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 1, st);
       blas_norm2<R>(G, nrhs, Rr, 1, w->partC, st);
       fin_init(SC, nsys, G.nchunk, w->partB, w->partC, w->selected, w->target2, st);
       SAP_HIP_CHECK(c, hipMemcpyAsync(w->p, w->r, halfb, hipMemcpyDeviceToDevice, st));
@@ -243,14 +250,14 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
       if (method == SAP_CG) {
         // q = M_hat p
         hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
-        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
+        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
         blas_norm2<R>(G, nrhs, Q, 1, w->partA, q);
         fin_alpha(SC, nsys, G.nchunk, w->partA, q);
         // x += alpha p, s -= alpha q
         blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, q);
         // r = M_hat^dagger s
         hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, q);
-        hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 1, q);
+        hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 1, q);
         blas_norm2<R>(G, nrhs, Rr, 1, w->partC, q);
         fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, q);
         blas_xpay<R>(G, nrhs, P, Rr, w->beta, q);
@@ -258,12 +265,12 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
         // residual r in S, shadow r0 in Rr, v in Q, t in HX
         blas_bicg_p<R>(G, nrhs, P, S, Q, w->cs, q);
         hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
-        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
+        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
         blas_cdot3<R>(G, nrhs, Rr, Q, NONE, w->partB, q);
         fin_bicg_alpha(SC, w->cs, nsys, G.nchunk, w->partB, q);
         blas_bicg_s<R>(G, nrhs, S, Q, w->cs, w->partB, q);
         hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
-        hop<R>(c, U, HX, T, S, 0, nrhs, lb, colour, R(1), k2R, 0, 0, q);
+        hop<R>(c, U, HX, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
         blas_cdot3<R>(G, nrhs, HX, S, HX, w->partC, q);
         fin_bicg_omega(SC, w->cs, nsys, G.nchunk, w->partC, w->partB, w->target2, q);
         blas_bicg_xr<R>(G, nrhs, Ee, P, S, HX, Rr, w->cs, w->partA, q);
@@ -285,7 +292,8 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     const int calls = ITERS_PER_GRAPH / per_call;
     hipGraphExec_t exec = nullptr;
     for (auto& g : w->graphs)
-      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.f32 == (int)(sizeof(R) == 4) && g.method == method)
+      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.f32 == (int)(sizeof(R) == 4) && g.method == method &&
+          g.rho == rho)
         exec = g.exec;
     if (!exec) {
       hipGraph_t graph;
@@ -297,7 +305,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
         }
       }
       (void)hipGetLastError();
-      if (exec) w->graphs.push_back({nrhs, lb, colour, (int)(sizeof(R) == 4), method, exec});
+      if (exec) w->graphs.push_back({nrhs, lb, colour, (int)(sizeof(R) == 4), method, rho, exec});
     }
     for (;;) {
       SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 12, hipMemcpyDeviceToHost, st));
@@ -316,12 +324,20 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
       total_iters += ITERS_PER_GRAPH;
     }
     // e_o = r_o + k D_oe e_e ; x += e ; r = b - A x (FP64)
-    hop<R>(c, U, E, Ee, RIN, 1, nrhs, lb, colour, R(1), kR, 0, 0, st);
+    if (!eo_only) hop<R>(c, U, E, Ee, RIN, 1, nrhs, lb, colour, R(1), kR, 0, 0, st);
     blas_add_mixed<R>(G, nrhs, X, E, st);
-    int rc = apply_op_any(c, w->ax, x, nrhs, lb, colour < 3 ? colour : 0, colour < 3 ? -1 : colour - 3,
-                          SAP_F64, st);
-    if (rc) return rc;
-    blas_resid(G, nrhs, R64, B, AX, w->partA, st);
+    if (eo_only) {
+      // A x = (M_hat + rho) x_e on the even sites, via the odd half of AX
+      const Field<double> NONE64 = {nullptr, 0, 0};
+      hop<double>(c, c->U64, AX, X, NONE64, 1, nrhs, lb, colour, 0.0, 1.0, 0, 0, st);
+      hop<double>(c, c->U64, AX, AX, X, 0, nrhs, lb, colour, 1.0 + rho, -kap * kap, 0, 0, st);
+      blas_resid(G, nrhs, R64, B, AX, w->partA, st, 1);
+    } else {
+      int rc = apply_op_any(c, w->ax, x, nrhs, lb, colour < 3 ? colour : 0, colour < 3 ? -1 : colour - 3,
+                            SAP_F64, st);
+      if (rc) return rc;
+      blas_resid(G, nrhs, R64, B, AX, w->partA, st);
+    }
     fin_sum(nsys, G.nchunk, w->partA, w->rnorm2, st);
     SAP_HIP_CHECK(c, hipGetLastError());
   }
@@ -671,6 +687,14 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
   }
   (void)block_iters;
   return status;
+}
+
+// (M_hat + rho) x_e = b_e on the blocks of length lb (0: full lattice), even sites only
+int sap_solve_eo_shift(sap_ctx* c, double* x, const double* b, int nrhs, int lb, double rho,
+                       const sap_solve_opts* o, sap_solve_info* info, hipStream_t st) {
+  if (o->method == SAP_SAP_BICGSTAB) return sap_fail(c, SAP_E_ARG, "SAP_SAP_BICGSTAB solves M x = b only");
+  if (o->inner_prec == SAP_F64) return solve_impl<double>(c, x, b, nrhs, lb, 0, o, info, st, rho, true);
+  return solve_impl<float>(c, x, b, nrhs, lb, 0, o, info, st, rho, true);
 }
 
 int sap_solve_any(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
