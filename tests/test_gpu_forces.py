@@ -118,7 +118,8 @@ def _g5(f):
 
 def test_forces_match_finite_differences_16x16x16x32(gu):
     """d/dt S(exp(i t Omega) U) at t = 0 by a central difference with eps = 1e-5 against
-    sum F^a omega^a, S = S_G + ||W1^{-1} phi||^2 + S_R, beta = 5.6, kappa = 0.1575.
+    sum F^a omega^a, S = S_G + ||W1^{-1} phi||^2 + S_R, beta = 5.6, kappa = 0.1575; the
+    pseudo-fermion force is taken from the torch.autograd.Function's backward pass.
     The pseudo-fermion actions are evaluated with estimators whose error is quadratic in
     the solver error: S_W = 2 Re<phi, y> - ||W1^dag y||^2 with y = (W1 W1^dag)^{-1} phi, and
     S_R = ||eta||^2 + 2 Re<xi, M psi - v>."""
@@ -135,10 +136,13 @@ def test_forces_match_finite_differences_16x16x16x32(gu):
     fchi = ctx.new_field(1)
     sap.schwarz_heat_bath(ctx, fchi, gu.to_sap(ctx, synth.noise_spinor(L, cfg["seed_noise2"]), 1), o)
     chi = gu.from_sap(ctx, fchi, 1, phi.shape)
-    F = ctx.new_momenta()
+    # pseudo-fermion part through the torch.autograd.Function, gauge part directly
+    from paper_0710_0066_amd.autograd import pseudo_fermion_action
+    w0 = ctx.new_momenta().requires_grad_(True)
+    S_pf = pseudo_fermion_action(w0, ctx, gu.dev(U), fphi, fchi, o)
+    (grad,) = torch.autograd.grad(S_pf, w0)
+    F = grad.detach().clone()
     sap.gauge_force(ctx, F, 1.0, beta)
-    sap.block_pf_force(ctx, F, 1.0, fphi, o)
-    sap.schwarz_boundary_force(ctx, F, 1.0, fchi, o)
     an = float(np.sum(_mom_from_sap(ctx, F, L) * omega))
     fom = _mom_to_sap(ctx, gu, omega)
     dummy = ctx.new_momenta()
@@ -345,3 +349,36 @@ def test_force_profile_16x16x16x32(gu):
         assert min(sp[first], sp[last]) > 100 * max(sp[mid - 1], sp[mid]), sp
     for name in ("S_W", "S_G"):
         assert prof[name].max() < 2 * prof[name].min(), (name, prof[name])
+
+
+def test_autograd_pseudo_fermion_action_matches_oracle(gu):
+    """The torch.autograd.Function of S_pf = ||W1^{-1} phi||^2 + S_R: its value and
+    gradient at omega = 0 against the oracle's action and force, and the gradient against a
+    central difference of the function itself (Richardson, h = 1e-3) along a random
+    direction."""
+    import paper_0710_0066_amd as sap
+    from paper_0710_0066_amd.autograd import pseudo_fermion_action
+    L, l0, k = (8, 4, 2, 4), 2, 0.15
+    print("autograd pseudo-fermion action", flush=True)
+    U = synth.gauge_field(L, 0.5, 131)
+    phi = synth.gaussian_spinor(L, 132)
+    g = synth.noise_spinor(L, 133)
+    S_or = schwarz.Solvers(U, k, l0, tol=1e-13)
+    chi = schwarz.heat_bath(U, g, k, l0, S_or)
+    ctx = gu.make_ctx(L, l0, k, U)
+    o = _opts(sap)
+    fphi, fchi = gu.to_sap(ctx, phi, 1), gu.to_sap(ctx, chi, 1)
+    w0 = ctx.new_momenta().requires_grad_(True)
+    S = pseudo_fermion_action(w0, ctx, gu.dev(U), fphi, fchi, o)
+    S.backward()
+    S_ref = forces.pf_action(U, phi, k, l0, W_inv=S_or.W_inv) + schwarz.action(U, chi, k, l0, S_or)
+    assert abs(float(S) - S_ref) <= 1e-10 * S_ref
+    F_ref = forces.pf_force(U, phi, k, l0, W_inv=S_or.W_inv, Wdag_inv=S_or.Wdag_inv) \
+        + forces.schwarz_force(U, chi, k, l0, S_or)
+    assert _rel(_mom_from_sap(ctx, w0.grad, L), F_ref) <= 1e-9
+    d = _mom_to_sap(ctx, gu, synth.gaussian_momenta(L, 134))
+    f = lambda t: float(pseudo_fermion_action(t * d, ctx, gu.dev(U), fphi, fchi, o))
+    dd = lambda h: (f(h) - f(-h)) / (2 * h)
+    fd = (4 * dd(5e-4) - dd(1e-3)) / 3
+    an = float(torch.sum(w0.grad * d))
+    assert abs(fd - an) <= 1e-7 * abs(an)
