@@ -8,8 +8,8 @@ The value is the Dslash bandwidth: algorithmic bytes of one launch (every link o
 4 V x 72 B, plus each rhs's input and output half field, 2 x 48 B per site) divided by
 the time per launch, timed with HIP events on the stream the kernel runs on.
 
-Also printed in the same JSON line: the single-rhs FP64 / FP32 even-odd hop and the full
-operator M (apply_M, 960 / 480 B per site) with their own roofline fractions, the HBM
+Also printed in the same JSON line: the single-rhs FP64 / FP32 / FP16 even-odd hop and the
+full operator M (apply_M, 960 / 480 / 248 B per site) with their own roofline fractions, the HBM
 ceilings of plain kernels on this GPU, the CPU oracle baseline on a bounded sample, and
 (unless --skip-solve) the block-solve comparison: mixed-precision batched vs plain FP64
 solves to a verified 1e-10 residual.
@@ -29,15 +29,24 @@ if ROOT not in sys.path:
 METRIC = "Dslash GB/s (% HBM peak); mixed vs FP64 block-solve time to 1e-10 residual"
 WORKLOAD = "batched_24x24x24x48"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SITE = {"f64": 960.0, "f32": 480.0}   # apply_M: 18-real links once + spinor in + out
-REAL = {"f64": 8, "f32": 4}
+REAL = {"f64": 8, "f32": 4, "f16": 2}
+
+
+def spinor_site_bytes(prec):
+    """Bytes of one stored spinor site: 24 reals, plus the FP32 site norm in FP16 storage."""
+    return 24 * REAL[prec] + (4 if prec == "f16" else 0)
 
 
 def eo_bytes(V, prec, nrhs):
     """Algorithmic bytes of one even-odd hop launch: all 4V links (18 reals) once, and per
-    rhs the input half field and the output half field (V/2 sites x 24 reals each)."""
-    r = REAL[prec]
-    return 4 * V * 18 * r + nrhs * 2 * (V // 2) * 24 * r
+    rhs the input half field and the output half field (V/2 sites each)."""
+    return 4 * V * 18 * REAL[prec] + nrhs * 2 * (V // 2) * spinor_site_bytes(prec)
+
+
+def apply_M_bytes(V, prec):
+    """Algorithmic bytes of apply_M on one rhs: 4 links per site once, spinor in and out
+    (960 / 480 / 248 B per site in FP64 / FP32 / FP16)."""
+    return V * (4 * 18 * REAL[prec] + 2 * spinor_site_bytes(prec))
 
 
 def parse():
@@ -47,7 +56,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--op", choices=["eo", "M"], default="eo",
                     help="operator timed by --only-dslash (profiler runs)")
-    ap.add_argument("--prec", choices=["f64", "f32"], default="f32")
+    ap.add_argument("--prec", choices=["f64", "f32", "f16"], default="f32")
     ap.add_argument("--nrhs", type=int, default=12)
     ap.add_argument("--hop-map", type=int, default=-1,
                     help="with --only-dslash: force this hop mapping (HOP_MAP_*) instead of the tuned one")
@@ -134,7 +143,9 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=3):
       fp64_per_block_loop FP64, one block and one rhs per call (the plain, unbatched
                           solve: 432 calls, timed once);
       mixed_batched_by_method  the mixed batched solve with the inner CG replaced by
-                          BiCGstab and by the geometric series (Sec. 3's block-term solver)."""
+                          BiCGstab and by the geometric series (Sec. 3's block-term solver);
+      mixed_f16_storage_by_method  inner CG / BiCGstab on FP16-storage fields (FP32
+                          arithmetic) to a relative residual of 1e-2 per correction."""
     import numpy as np
     import synth
     nrhs = cfg["nrhs"]
@@ -181,6 +192,14 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=3):
             methods[name] = run(o, "batched", repeats)
         except sap.SapError as e:
             methods[name] = {"error": str(e)}
+    half = {}
+    for name, meth in (("cg", sap.SAP_CG), ("bicgstab", sap.SAP_BICGSTAB)):
+        print(f"[bench] block solves: FP16-storage inner {name}", file=sys.stderr, flush=True)
+        o = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F16, inner_tol=1e-2, method=meth)
+        try:
+            half[name] = run(o, "batched", repeats)
+        except sap.SapError as e:
+            half[name] = {"error": str(e)}
     print("[bench] block solves: fp64 batched", file=sys.stderr, flush=True)
     f = run(plain, "batched", repeats)
     print("[bench] block solves: fp64 one rhs per call", file=sys.stderr, flush=True)
@@ -190,6 +209,7 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=3):
     return {"systems": f"{nrhs} rhs x (12 blocks 24^3x4 + 24 blocks 24^3x2) = {nrhs * 36}",
             "tol": 1e-10, "mixed_batched": m, "fp64_batched": f, "fp64_rhs_loop": fl,
             "fp64_per_block_loop": fb1, "mixed_batched_by_method": methods,
+            "mixed_f16_storage_by_method": half,
             "speedup_vs_fp64_batched": f["seconds"] / m["seconds"],
             "speedup_vs_fp64_rhs_loop": fl["seconds"] / m["seconds"],
             "speedup_vs_fp64_per_block_loop": fb1["seconds"] / m["seconds"],
@@ -239,7 +259,7 @@ def main():
 
     ctx = sap.Context(L, l0, k, l0_sub=l0s, max_rhs=nrhs)
     ctx.set_gauge(torch.from_numpy(U).cuda())
-    PREC = {"f64": sap.SAP_F64, "f32": sap.SAP_F32}
+    PREC = {"f64": sap.SAP_F64, "f32": sap.SAP_F32, "f16": sap.SAP_F16}
     fields = {}
 
     def field(prec, n):
@@ -291,8 +311,11 @@ def main():
             ("eo_f64_1rhs", eo("f64", 1), eo_bytes(V, "f64", 1)),
             ("eo_f32_1rhs", eo("f32", 1), eo_bytes(V, "f32", 1)),
             ("eo_f64_12rhs", eo("f64", nrhs), eo_bytes(V, "f64", nrhs)),
-            ("apply_M_f64_1rhs", full("f64"), BYTES_PER_SITE["f64"] * V),
-            ("apply_M_f32_1rhs", full("f32"), BYTES_PER_SITE["f32"] * V)]:
+            ("eo_f16_1rhs", eo("f16", 1), eo_bytes(V, "f16", 1)),
+            ("eo_f16_12rhs", eo("f16", nrhs), eo_bytes(V, "f16", nrhs)),
+            ("apply_M_f64_1rhs", full("f64"), apply_M_bytes(V, "f64")),
+            ("apply_M_f32_1rhs", full("f32"), apply_M_bytes(V, "f32")),
+            ("apply_M_f16_1rhs", full("f16"), apply_M_bytes(V, "f16"))]:
         t = time_op(sap, torch, fn, max(20, args.steps // 2), args.warmup)
         g = nbytes / (t * 1e-3) / 1e9
         others[name] = {"us_per_launch": round(t * 1e3, 2), "algorithmic_bytes": nbytes,

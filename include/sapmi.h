@@ -27,6 +27,11 @@
  *   spinor  complex number (rhs, parity, c = 3*spin + colour, j) at index
  *           ((rhs*2 + parity)*12*Vhp) + ((j/64)*12 + c)*64 + j%64
  *           (complex128 for SAP_F64, complex64 for SAP_F32).
+ *           SAP_F16: the same component order with a half-precision complex (two FP16)
+ *           per entry and rhs blocks of 26*Vhp entries: parity 0 and 1 components
+ *           (24*Vhp), then one FP32 norm per (parity, j) at float index
+ *           rhs*26*Vhp + 24*Vhp + parity*Vhp + j; a component's value is the stored one
+ *           times the norm of its site (the largest component magnitude of the site).
  *   momentum / force (float64, a = 0..7) (parity, j, mu, a) at
  *           parity*32*Vhp + ((j/64)*32 + 8*mu + a)*64 + j%64.
  *   sap_field_bytes() / sap_momenta_bytes() give the sizes; sap_pack_* / sap_unpack_*
@@ -65,7 +70,9 @@ typedef enum {
   SAP_E_STATE = -6       /* call out of order (e.g. no gauge field set) */
 } sap_status;
 
-typedef enum { SAP_F64 = 0, SAP_F32 = 1 } sap_prec;            /* storage and arithmetic */
+/* storage precision; arithmetic is FP64 for SAP_F64 and FP32 for SAP_F32 and SAP_F16 (FP16
+ * spinors with a per-site FP32 norm and FP16 links, FP32 accumulation) */
+typedef enum { SAP_F64 = 0, SAP_F32 = 1, SAP_F16 = 2 } sap_prec;
 typedef enum { SAP_ALL = 0, SAP_BLACK = 1, SAP_WHITE = 2 } sap_color;
 
 typedef struct {

@@ -23,7 +23,7 @@ _lib = ctypes.CDLL(_LIB_PATH)
 
 SAP_OK, SAP_E_ARG, SAP_E_NOMEM, SAP_E_HIP, SAP_E_NOCONV, SAP_E_NONFINITE, SAP_E_STATE = \
     0, -1, -2, -3, -4, -5, -6
-SAP_F64, SAP_F32 = 0, 1
+SAP_F64, SAP_F32, SAP_F16 = 0, 1, 2   # FP16: half2 components with an FP32 norm per site
 SAP_ALL, SAP_BLACK, SAP_WHITE = 0, 1, 2
 _STATUS = {0: "SAP_OK", -1: "SAP_E_ARG", -2: "SAP_E_NOMEM", -3: "SAP_E_HIP", -4: "SAP_E_NOCONV",
            -5: "SAP_E_NONFINITE", -6: "SAP_E_STATE"}

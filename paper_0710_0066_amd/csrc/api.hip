@@ -53,6 +53,7 @@ const char* sap_last_error(const sap_ctx* ctx) {
 
 size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs) {
   if (!ctx || nrhs < 1) return 0;
+  if (prec == SAP_F16) return full_bytes<h16>(ctx->Vhp, nrhs);
   const size_t per = prec == SAP_F64 ? sizeof(double2) : sizeof(float2);
   return (size_t)ctx->Vhp * 24 * per * (size_t)nrhs;
 }
@@ -84,6 +85,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   c->have_gauge = false;
   c->U64 = nullptr;
   c->U32 = nullptr;
+  c->U16 = nullptr;
   c->solver = nullptr;
   c->forces = nullptr;
   c->sapws = nullptr;
@@ -94,7 +96,8 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   }
   const size_t nlink = (size_t)72 * c->Vhp;
   if (hipMalloc((void**)&c->U64, nlink * sizeof(double2)) != hipSuccess ||
-      hipMalloc((void**)&c->U32, nlink * sizeof(float2)) != hipSuccess) {
+      hipMalloc((void**)&c->U32, nlink * sizeof(float2)) != hipSuccess ||
+      hipMalloc((void**)&c->U16, nlink * sizeof(__half2)) != hipSuccess) {
     sap_destroy(c);
     return sap_fail(nullptr, SAP_E_NOMEM, "cannot allocate the gauge copies");
   }
@@ -116,6 +119,7 @@ void sap_destroy(sap_ctx* ctx) {
   sap_force_destroy(ctx);
   if (ctx->U64) (void)hipFree(ctx->U64);
   if (ctx->U32) (void)hipFree(ctx->U32);
+  if (ctx->U16) (void)hipFree(ctx->U16);
   delete ctx;
 }
 
@@ -124,6 +128,7 @@ int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream) {
   if (!U) return sap_fail(ctx, SAP_E_ARG, "U is NULL");
   hipStream_t s = (hipStream_t)stream;
   launch_pack_gauge(ctx->g, ctx->U64, ctx->U32, (const double2*)U, s);
+  launch_gauge_to_f32(ctx->g, ctx->U32, ctx->U16, ctx->U64, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
   ctx->have_gauge = true;
   return SAP_OK;
@@ -143,7 +148,7 @@ static int check_fields(sap_ctx* ctx, const void* a, const void* b, int nrhs, in
   if (!a || !b) return sap_fail(ctx, SAP_E_ARG, "field pointer is NULL");
   if (nrhs < 1 || nrhs > ctx->geom.max_rhs)
     return sap_fail(ctx, SAP_E_ARG, "nrhs must be in [1, max_rhs]");
-  if (prec != SAP_F64 && prec != SAP_F32) return sap_fail(ctx, SAP_E_ARG, "unknown precision");
+  if (prec != SAP_F64 && prec != SAP_F32 && prec != SAP_F16) return sap_fail(ctx, SAP_E_ARG, "unknown precision");
   return SAP_OK;
 }
 
@@ -152,7 +157,8 @@ int sap_pack_spinor(sap_ctx* ctx, void* out, const double* in, int nrhs, sap_pre
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (prec == SAP_F64) launch_pack_spinor<double>(ctx->g, (double2*)out, (const double2*)in, nrhs, s);
-  else launch_pack_spinor<float>(ctx->g, (float2*)out, (const double2*)in, nrhs, s);
+  else if (prec == SAP_F32) launch_pack_spinor<float>(ctx->g, (float2*)out, (const double2*)in, nrhs, s);
+  else launch_pack_spinor16(ctx->g, (__half2*)out, (const double2*)in, nrhs, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
   return SAP_OK;
 }
@@ -162,7 +168,8 @@ int sap_unpack_spinor(sap_ctx* ctx, double* out, const void* in, int nrhs, sap_p
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   if (prec == SAP_F64) launch_unpack_spinor<double>(ctx->g, (double2*)out, (const double2*)in, nrhs, s);
-  else launch_unpack_spinor<float>(ctx->g, (double2*)out, (const float2*)in, nrhs, s);
+  else if (prec == SAP_F32) launch_unpack_spinor<float>(ctx->g, (double2*)out, (const float2*)in, nrhs, s);
+  else launch_unpack_spinor16(ctx->g, (double2*)out, (const __half2*)in, nrhs, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
   return SAP_OK;
 }
@@ -191,12 +198,12 @@ template <class R>
 static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, int colour,
                     int block, hipStream_t s) {
   HopArgs<R> A;
-  typedef typename vec2<R>::type V2;
+  typedef typename arith<R>::type Ar;
   const long long Vhp = ctx->Vhp;
-  A.out = {(V2*)out, 24 * Vhp, 12 * Vhp};
-  A.in = {(V2*)in, 24 * Vhp, 12 * Vhp};
+  A.out = full_field<R>(out, Vhp);
+  A.in = full_field<R>((void*)in, Vhp);
   A.x = A.in;
-  A.U = (const V2*)(sizeof(R) == 8 ? (const void*)ctx->U64 : (const void*)ctx->U32);
+  A.U = gauge_of<R>(ctx);
   A.g = ctx->g;
   A.nrhs = nrhs;
   A.parity_out = -1;
@@ -204,8 +211,8 @@ static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, i
   A.slb = lb;
   A.colour = colour;
   A.block = block;
-  A.a = R(1);
-  A.b = R(-ctx->geom.kappa);
+  A.a = Ar(1);
+  A.b = Ar(-ctx->geom.kappa);
   A.g5_in = 0;
   A.g5_out = 0;
   A.map = hop_map_for(ctx, true, sizeof(R) == 4, nrhs);
@@ -215,12 +222,12 @@ static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, i
 template <class R>
 static void eo_hop(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, hipStream_t s) {
   HopArgs<R> A;
-  typedef typename vec2<R>::type V2;
+  typedef typename arith<R>::type Ar;
   const long long Vhp = ctx->Vhp;
-  A.out = {(V2*)out, 24 * Vhp, 12 * Vhp};
-  A.in = {(V2*)in, 24 * Vhp, 12 * Vhp};
-  A.x = {nullptr, 0, 0};
-  A.U = (const V2*)(sizeof(R) == 8 ? (const void*)ctx->U64 : (const void*)ctx->U32);
+  A.out = full_field<R>(out, Vhp);
+  A.in = full_field<R>((void*)in, Vhp);
+  A.x = {nullptr, 0, 0, 0};
+  A.U = gauge_of<R>(ctx);
   A.g = ctx->g;
   A.nrhs = nrhs;
   A.parity_out = parity;
@@ -228,8 +235,8 @@ static void eo_hop(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity
   A.slb = 0;
   A.colour = 0;
   A.block = -1;
-  A.a = R(0);
-  A.b = R(1);
+  A.a = Ar(0);
+  A.b = Ar(1);
   A.g5_in = 0;
   A.g5_out = 0;
   A.map = hop_map_for(ctx, false, sizeof(R) == 4, nrhs);
@@ -238,7 +245,8 @@ static void eo_hop(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity
 
 int eo_hop_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, sap_prec prec, hipStream_t s) {
   if (prec == SAP_F64) eo_hop<double>(ctx, out, in, nrhs, parity, s);
-  else eo_hop<float>(ctx, out, in, nrhs, parity, s);
+  else if (prec == SAP_F32) eo_hop<float>(ctx, out, in, nrhs, parity, s);
+  else eo_hop<h16>(ctx, out, in, nrhs, parity, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
   return SAP_OK;
 }
@@ -246,7 +254,8 @@ int eo_hop_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity, sa
 int apply_op_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, int colour, int block,
                  sap_prec prec, hipStream_t s) {
   if (prec == SAP_F64) full_op<double>(ctx, out, in, nrhs, lb, colour, block, s);
-  else full_op<float>(ctx, out, in, nrhs, lb, colour, block, s);
+  else if (prec == SAP_F32) full_op<float>(ctx, out, in, nrhs, lb, colour, block, s);
+  else full_op<h16>(ctx, out, in, nrhs, lb, colour, block, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
   return SAP_OK;
 }

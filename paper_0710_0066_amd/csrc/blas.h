@@ -15,6 +15,7 @@ struct SysGrid {
   int nchunk;       // ceil(Vb / CHUNK)
   int colour;
   long long Vh;
+  long long Vhp;     // storage sites per parity (locates the site norms of FP16 fields)
 };
 
 // Per-system scalars of the CG iteration (device arrays of nsys entries) and flags:
@@ -33,6 +34,7 @@ inline SysGrid make_sysgrid(long long Vh, int V3h, int lb, int L0, int colour) {
   G.nchunk = (int)((G.Vb + CHUNK - 1) / CHUNK);
   G.colour = lb ? colour : 0;
   G.Vh = Vh;
+  G.Vhp = (Vh + TILE - 1) / TILE * TILE;
   return G;
 }
 

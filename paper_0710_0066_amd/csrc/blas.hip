@@ -8,6 +8,7 @@
 // workgroup; the finalize kernels add the partials of a system in index order. The
 // result is bitwise reproducible run to run.
 #include "blas.h"
+#include "site_io.h"
 
 namespace sap {
 
@@ -53,15 +54,15 @@ __global__ __launch_bounds__(256) void k_norm2(SysGrid G, Field<R> a, int npar, 
   const Tile t = tile_of(G);
   double acc = 0.0;
   if (t.selected) {
-    for (int p = 0; p < npar; ++p) {
-      const typename vec2<R>::type* base = a.ptr + t.rhs * a.rs + p * a.ps;
-      for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+    for (int p = 0; p < npar; ++p)
+      for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+        const SiteR<R> av = site_r(a, t.rhs, p, j, G.Vhp);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-          cx<R> v = ld<R>(base + tiled(j, c, 12));
+          const cx<arith_t<R>> v = get(av, c);
           acc += (double)v.r * v.r + (double)v.i * v.i;
         }
-    }
+      }
   }
   double s = block_sum(acc);
   if (threadIdx.x == 0) part[t.sys * G.nchunk + blockIdx.x] = s;
@@ -71,25 +72,27 @@ __global__ __launch_bounds__(256) void k_norm2(SysGrid G, Field<R> a, int npar, 
 template <class R>
 __global__ __launch_bounds__(256) void k_cg_xs(SysGrid G, Field<R> x, Field<R> p, Field<R> s,
                                                Field<R> q, const double* alpha, double* part) {
+  typedef arith_t<R> A;
   const Tile t = tile_of(G);
   double acc = 0.0;
   if (t.selected) {
-    const R al = (R)alpha[t.sys];
-    typename vec2<R>::type* xb = x.ptr + t.rhs * x.rs;
-    const typename vec2<R>::type* pb = p.ptr + t.rhs * p.rs;
-    typename vec2<R>::type* sb = s.ptr + t.rhs * s.rs;
-    const typename vec2<R>::type* qb = q.ptr + t.rhs * q.rs;
-    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+    const A al = (A)alpha[t.sys];
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+      const SiteR<R> xr = site_r(x, t.rhs, 0, j, G.Vhp), pr = site_r(p, t.rhs, 0, j, G.Vhp);
+      const SiteR<R> sr = site_r(s, t.rhs, 0, j, G.Vhp), qr = site_r(q, t.rhs, 0, j, G.Vhp);
+      SiteW<R> xw = site_w(x, t.rhs, 0, j, G.Vhp), sw = site_w(s, t.rhs, 0, j, G.Vhp);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const long long o = tiled(j, c, 12);
-        cx<R> xv = ld<R>(xb + o), pv = ld<R>(pb + o), sv = ld<R>(sb + o), qv = ld<R>(qb + o);
+        cx<A> xv = get(xr, c), pv = get(pr, c), sv = get(sr, c), qv = get(qr, c);
         xv.r += al * pv.r; xv.i += al * pv.i;
         sv.r -= al * qv.r; sv.i -= al * qv.i;
-        st<R>(xb + o, xv);
-        st<R>(sb + o, sv);
+        put(xw, c, xv);
+        put(sw, c, sv);
         acc += (double)sv.r * sv.r + (double)sv.i * sv.i;
       }
+      close(xw);
+      close(sw);
+    }
   }
   double sm = block_sum(acc);
   if (threadIdx.x == 0) part[t.sys * G.nchunk + blockIdx.x] = sm;
@@ -98,39 +101,43 @@ __global__ __launch_bounds__(256) void k_cg_xs(SysGrid G, Field<R> x, Field<R> p
 // p = r + beta p
 template <class R>
 __global__ __launch_bounds__(256) void k_xpay(SysGrid G, Field<R> p, Field<R> r, const double* beta) {
+  typedef arith_t<R> A;
   const Tile t = tile_of(G);
   if (!t.selected) return;
-  const R be = (R)beta[t.sys];
-  typename vec2<R>::type* pb = p.ptr + t.rhs * p.rs;
-  const typename vec2<R>::type* rb = r.ptr + t.rhs * r.rs;
-  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+  const A be = (A)beta[t.sys];
+  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+    const SiteR<R> pr = site_r(p, t.rhs, 0, j, G.Vhp), rr = site_r(r, t.rhs, 0, j, G.Vhp);
+    SiteW<R> pw = site_w(p, t.rhs, 0, j, G.Vhp);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      const long long o = tiled(j, c, 12);
-      cx<R> pv = ld<R>(pb + o), rv = ld<R>(rb + o);
+      cx<A> pv = get(pr, c);
+      const cx<A> rv = get(rr, c);
       pv.r = rv.r + be * pv.r;
       pv.i = rv.i + be * pv.i;
-      st<R>(pb + o, pv);
+      put(pw, c, pv);
     }
+    close(pw);
+  }
 }
 
 // out = src (both parities if npar == 2), converting precision
 template <class Ro, class Ri>
 __global__ __launch_bounds__(256) void k_convert(SysGrid G, Field<Ro> out, Field<Ri> in, int npar) {
+  typedef arith_t<Ro> Ao;
   const Tile t = tile_of(G);
-  for (int p = 0; p < npar; ++p) {
-    typename vec2<Ro>::type* ob = out.ptr + t.rhs * out.rs + p * out.ps;
-    const typename vec2<Ri>::type* ib = in.ptr + t.rhs * in.rs + p * in.ps;
-    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+  for (int p = 0; p < npar; ++p)
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+      const SiteR<Ri> ir = site_r(in, t.rhs, p, j, G.Vhp);
+      SiteW<Ro> ow = site_w(out, t.rhs, p, j, G.Vhp);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        const long long o = tiled(j, c, 12);
-        cx<Ri> v = ld<Ri>(ib + o);
-        cx<Ro> w = {(Ro)v.r, (Ro)v.i};
-        if (!t.selected) w = {Ro(0), Ro(0)};
-        st<Ro>(ob + o, w);
+        const cx<arith_t<Ri>> v = get(ir, c);
+        cx<Ao> w = {(Ao)v.r, (Ao)v.i};
+        if (!t.selected) w = {Ao(0), Ao(0)};
+        put(ow, c, w);
       }
-  }
+      close(ow);
+    }
 }
 
 // x64 += e (both parities), e at the inner precision
@@ -140,17 +147,18 @@ __global__ __launch_bounds__(256) void k_add_mixed(SysGrid G, Field<double> x, F
   if (!t.selected) return;
   for (int p = 0; p < 2; ++p) {
     double2* xb = x.ptr + t.rhs * x.rs + p * x.ps;
-    const typename vec2<R>::type* eb = e.ptr + t.rhs * e.rs + p * e.ps;
-    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+      const SiteR<R> er = site_r(e, t.rhs, p, j, G.Vhp);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
         const long long o = tiled(j, c, 12);
         cx<double> xv = ld<double>(xb + o);
-        cx<R> ev = ld<R>(eb + o);
+        const cx<arith_t<R>> ev = get(er, c);
         xv.r += (double)ev.r;
         xv.i += (double)ev.i;
         st<double>(xb + o, xv);
       }
+    }
   }
 }
 
@@ -279,64 +287,69 @@ enum { CS_RHO = 0, CS_ALPHA = 1, CS_OMEGA = 2, CS_BETA = 3 };
 
 template <class R>
 __global__ __launch_bounds__(256) void k_cdot3(SysGrid G, Field<R> a, Field<R> b, Field<R> c, double* part) {
+  typedef arith_t<R> A;
   const Tile t = tile_of(G);
   double sr = 0.0, si = 0.0, sc = 0.0;
   if (t.selected) {
-    const typename vec2<R>::type* ab = a.ptr + t.rhs * a.rs;
-    const typename vec2<R>::type* bb = b.ptr + t.rhs * b.rs;
-    const typename vec2<R>::type* cb = c.ptr ? c.ptr + t.rhs * c.rs : nullptr;
-    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+    const bool with_c = c.ptr != nullptr;
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+      const SiteR<R> ar = site_r(a, t.rhs, 0, j, G.Vhp), br = site_r(b, t.rhs, 0, j, G.Vhp);
+      SiteR<R> cr;
+      if (with_c) cr = site_r(c, t.rhs, 0, j, G.Vhp);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
-        const long long o = tiled(j, k, 12);
-        const cx<R> av = ld<R>(ab + o), bv = ld<R>(bb + o);
+        const cx<A> av = get(ar, k), bv = get(br, k);
         sr += (double)av.r * bv.r + (double)av.i * bv.i;
         si += (double)av.r * bv.i - (double)av.i * bv.r;
-        if (cb) {
-          const cx<R> cv = ld<R>(cb + o);
+        if (with_c) {
+          const cx<A> cv = get(cr, k);
           sc += (double)cv.r * cv.r + (double)cv.i * cv.i;
         }
       }
+    }
   }
   block_sum3(sr, si, sc, part + 3 * (t.sys * G.nchunk + blockIdx.x));
 }
 
 template <class R>
 __global__ __launch_bounds__(256) void k_bicg_p(SysGrid G, Field<R> p, Field<R> r, Field<R> v, const double* cs) {
+  typedef arith_t<R> A;
   const Tile t = tile_of(G);
   if (!t.selected) return;
   const cx<double> be = cs_get(cs, t.sys, CS_BETA), om = cs_get(cs, t.sys, CS_OMEGA);
-  const cx<R> b = {(R)be.r, (R)be.i}, w = {(R)om.r, (R)om.i};
-  typename vec2<R>::type* pb = p.ptr + t.rhs * p.rs;
-  const typename vec2<R>::type* rb = r.ptr + t.rhs * r.rs;
-  const typename vec2<R>::type* vb = v.ptr + t.rhs * v.rs;
-  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+  const cx<A> b = {(A)be.r, (A)be.i}, w = {(A)om.r, (A)om.i};
+  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+    const SiteR<R> pr = site_r(p, t.rhs, 0, j, G.Vhp), rr = site_r(r, t.rhs, 0, j, G.Vhp);
+    const SiteR<R> vr = site_r(v, t.rhs, 0, j, G.Vhp);
+    SiteW<R> pw = site_w(p, t.rhs, 0, j, G.Vhp);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-      const long long o = tiled(j, k, 12);
-      const cx<R> pv = ld<R>(pb + o), rv = ld<R>(rb + o), vv = ld<R>(vb + o);
-      const cx<R> d = pv - cmul(w, vv);
-      st<R>(pb + o, rv + cmul(b, d));
+      const cx<A> d = get(pr, k) - cmul(w, get(vr, k));
+      put(pw, k, get(rr, k) + cmul(b, d));
     }
+    close(pw);
+  }
 }
 
 template <class R>
 __global__ __launch_bounds__(256) void k_bicg_s(SysGrid G, Field<R> r, Field<R> v, const double* cs, double* part) {
+  typedef arith_t<R> A;
   const Tile t = tile_of(G);
   double acc = 0.0;
   if (t.selected) {
     const cx<double> al = cs_get(cs, t.sys, CS_ALPHA);
-    const cx<R> a = {(R)al.r, (R)al.i};
-    typename vec2<R>::type* rb = r.ptr + t.rhs * r.rs;
-    const typename vec2<R>::type* vb = v.ptr + t.rhs * v.rs;
-    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+    const cx<A> a = {(A)al.r, (A)al.i};
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+      const SiteR<R> rr = site_r(r, t.rhs, 0, j, G.Vhp), vr = site_r(v, t.rhs, 0, j, G.Vhp);
+      SiteW<R> rw = site_w(r, t.rhs, 0, j, G.Vhp);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
-        const long long o = tiled(j, k, 12);
-        const cx<R> sv = ld<R>(rb + o) - cmul(a, ld<R>(vb + o));
-        st<R>(rb + o, sv);
+        const cx<A> sv = get(rr, k) - cmul(a, get(vr, k));
+        put(rw, k, sv);
         acc += (double)sv.r * sv.r + (double)sv.i * sv.i;
       }
+      close(rw);
+    }
   }
   const double sm = block_sum(acc);
   if (threadIdx.x == 0) part[t.sys * G.nchunk + blockIdx.x] = sm;
@@ -345,29 +358,31 @@ __global__ __launch_bounds__(256) void k_bicg_s(SysGrid G, Field<R> r, Field<R> 
 template <class R>
 __global__ __launch_bounds__(256) void k_bicg_xr(SysGrid G, Field<R> x, Field<R> p, Field<R> r, Field<R> tt,
                                                  Field<R> r0, const double* cs, double* part) {
+  typedef arith_t<R> A;
   const Tile t = tile_of(G);
   double sr = 0.0, si = 0.0, sc = 0.0;
   if (t.selected) {
     const cx<double> al = cs_get(cs, t.sys, CS_ALPHA), om = cs_get(cs, t.sys, CS_OMEGA);
-    const cx<R> a = {(R)al.r, (R)al.i}, w = {(R)om.r, (R)om.i};
-    typename vec2<R>::type* xb = x.ptr + t.rhs * x.rs;
-    const typename vec2<R>::type* pb = p.ptr + t.rhs * p.rs;
-    typename vec2<R>::type* rb = r.ptr + t.rhs * r.rs;
-    const typename vec2<R>::type* tb = tt.ptr + t.rhs * tt.rs;
-    const typename vec2<R>::type* qb = r0.ptr + t.rhs * r0.rs;
-    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+    const cx<A> a = {(A)al.r, (A)al.i}, w = {(A)om.r, (A)om.i};
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+      const SiteR<R> xr = site_r(x, t.rhs, 0, j, G.Vhp), pr = site_r(p, t.rhs, 0, j, G.Vhp);
+      const SiteR<R> rr = site_r(r, t.rhs, 0, j, G.Vhp), tr = site_r(tt, t.rhs, 0, j, G.Vhp);
+      const SiteR<R> qr = site_r(r0, t.rhs, 0, j, G.Vhp);
+      SiteW<R> xw = site_w(x, t.rhs, 0, j, G.Vhp), rw = site_w(r, t.rhs, 0, j, G.Vhp);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
-        const long long o = tiled(j, k, 12);
-        const cx<R> sv = ld<R>(rb + o), tv = ld<R>(tb + o);
-        st<R>(xb + o, ld<R>(xb + o) + cmul(a, ld<R>(pb + o)) + cmul(w, sv));
-        const cx<R> rn = sv - cmul(w, tv);
-        st<R>(rb + o, rn);
-        const cx<R> q = ld<R>(qb + o);
+        const cx<A> sv = get(rr, k), tv = get(tr, k);
+        put(xw, k, get(xr, k) + cmul(a, get(pr, k)) + cmul(w, sv));
+        const cx<A> rn = sv - cmul(w, tv);
+        put(rw, k, rn);
+        const cx<A> q = get(qr, k);
         sr += (double)q.r * rn.r + (double)q.i * rn.i;
         si += (double)q.r * rn.i - (double)q.i * rn.r;
         sc += (double)rn.r * rn.r + (double)rn.i * rn.i;
       }
+      close(xw);
+      close(rw);
+    }
   }
   block_sum3(sr, si, sc, part + 3 * (t.sys * G.nchunk + blockIdx.x));
 }
@@ -475,31 +490,36 @@ __global__ void k_fin_bicg_omega(SysScal S, double* cs, int nsys, int nchunk, co
 template <class R>
 __global__ __launch_bounds__(256) void k_lin3(SysGrid G, Field<R> y, Field<R> u, Field<R> w, Field<R> q,
                                               const double* coef, double* part) {
+  typedef arith_t<R> A;
   const Tile t = tile_of(G);
   double sr = 0.0, si = 0.0, sc = 0.0;
   if (t.selected) {
     const double* cf = coef + 6 * t.sys;
-    const cx<R> c0 = {(R)cf[0], (R)cf[1]}, c1 = {(R)cf[2], (R)cf[3]}, c2 = {(R)cf[4], (R)cf[5]};
+    const cx<A> c0 = {(A)cf[0], (A)cf[1]}, c1 = {(A)cf[2], (A)cf[3]}, c2 = {(A)cf[4], (A)cf[5]};
     const bool keep_y = cf[0] != 0.0 || cf[1] != 0.0;   // c0 = 0: y is not read (may be unset)
-    typename vec2<R>::type* yb = y.ptr + t.rhs * y.rs;
-    const typename vec2<R>::type* ub = u.ptr + t.rhs * u.rs;
-    const typename vec2<R>::type* wb = w.ptr ? w.ptr + t.rhs * w.rs : nullptr;
-    const typename vec2<R>::type* qb = q.ptr ? q.ptr + t.rhs * q.rs : nullptr;
-    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+    const bool with_w = w.ptr != nullptr, with_q = q.ptr != nullptr;
+    for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+      const SiteR<R> ur = site_r(u, t.rhs, 0, j, G.Vhp);
+      SiteR<R> yr, wr, qr;
+      if (keep_y) yr = site_r(y, t.rhs, 0, j, G.Vhp);
+      if (with_w) wr = site_r(w, t.rhs, 0, j, G.Vhp);
+      if (with_q) qr = site_r(q, t.rhs, 0, j, G.Vhp);
+      SiteW<R> yw = site_w(y, t.rhs, 0, j, G.Vhp);
 #pragma unroll
       for (int k = 0; k < 12; ++k) {
-        const long long o = tiled(j, k, 12);
-        cx<R> v = cmul(c1, ld<R>(ub + o));
-        if (keep_y) v = v + cmul(c0, ld<R>(yb + o));
-        if (wb) v = v + cmul(c2, ld<R>(wb + o));
-        st<R>(yb + o, v);
-        if (qb) {
-          const cx<R> qv = ld<R>(qb + o);
+        cx<A> v = cmul(c1, get(ur, k));
+        if (keep_y) v = v + cmul(c0, get(yr, k));
+        if (with_w) v = v + cmul(c2, get(wr, k));
+        put(yw, k, v);
+        if (with_q) {
+          const cx<A> qv = get(qr, k);
           sr += (double)qv.r * v.r + (double)qv.i * v.i;
           si += (double)qv.r * v.i - (double)qv.i * v.r;
         }
         sc += (double)v.r * v.r + (double)v.i * v.i;
       }
+      close(yw);
+    }
   }
   if (part) block_sum3(sr, si, sc, part + 3 * (t.sys * G.nchunk + blockIdx.x));
 }
@@ -516,14 +536,13 @@ template <class R>
 __global__ __launch_bounds__(256) void k_geom_add(SysGrid G, Field<R> x, Field<R> tf, const int* active) {
   const Tile t = tile_of(G);
   if (!t.selected || !active[t.sys]) return;
-  typename vec2<R>::type* xb = x.ptr + t.rhs * x.rs;
-  const typename vec2<R>::type* tb = tf.ptr + t.rhs * tf.rs;
-  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256)
+  for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
+    const SiteR<R> xr = site_r(x, t.rhs, 0, j, G.Vhp), tr = site_r(tf, t.rhs, 0, j, G.Vhp);
+    SiteW<R> xw = site_w(x, t.rhs, 0, j, G.Vhp);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const long long o = tiled(j, k, 12);
-      st<R>(xb + o, ld<R>(xb + o) + ld<R>(tb + o));
-    }
+    for (int k = 0; k < 12; ++k) put(xw, k, get(xr, k) + get(tr, k));
+    close(xw);
+  }
 }
 
 // Geometric series: init marks the systems with ||t_0||^2 = ||b_hat||^2 above target
@@ -658,7 +677,9 @@ void fin_geom(const SysScal& S, int nsys, int nchunk, const double* part, const 
                              double*, hipStream_t);
 INST(double)
 INST(float)
+INST(h16)
 template void blas_convert<double, double>(const SysGrid&, int, Field<double>, Field<double>, int, hipStream_t);
 template void blas_convert<float, double>(const SysGrid&, int, Field<float>, Field<double>, int, hipStream_t);
+template void blas_convert<h16, double>(const SysGrid&, int, Field<h16>, Field<double>, int, hipStream_t);
 
 }  // namespace sap

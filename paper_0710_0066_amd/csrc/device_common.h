@@ -2,6 +2,7 @@
 // site indexing of the library layout, SU(3) x colour-vector products and the
 // (1 -/+ gamma_mu) half-spinor projections of the chiral basis.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,10 +42,19 @@ template <class R> __device__ __forceinline__ cx<R> cjfma(cx<R> acc, cx<R> a, cx
   return acc;
 }
 
+// FP16 storage tag: spinor components as half2 with one FP32 norm per site (the largest
+// component magnitude of the site), links as plain half2; arithmetic in FP32
+struct h16 {};
+
 // storage vector type of one complex number
 template <class R> struct vec2;
 template <> struct vec2<double> { typedef double2 type; };
 template <> struct vec2<float> { typedef float2 type; };
+template <> struct vec2<h16> { typedef __half2 type; };
+
+// arithmetic type of a storage type
+template <class S> struct arith { typedef S type; };
+template <> struct arith<h16> { typedef float type; };
 
 template <class R> __device__ __forceinline__ cx<R> ld(const typename vec2<R>::type* p) {
   typename vec2<R>::type v = *p;
@@ -220,6 +230,15 @@ __device__ __forceinline__ void accum_recon(int mu, bool plus, const cx<R> g[2][
         break;
     }
   }
+}
+
+// Is a site on slice x0 in a selected x0 block of length slb (slb = 0: no restriction)?
+// block >= 0: only that block; else colour 0 all, 1 black (odd index), 2 white (even).
+__device__ __forceinline__ bool block_sel(int x0, int slb, int block, int colour) {
+  if (!slb) return true;
+  const int blk = x0 / slb;
+  if (block >= 0) return blk == block;
+  return colour == 0 || ((colour == 1) == ((blk & 1) == 1));
 }
 
 // Block selection code used by the block-restricted kernels: 0 all blocks, 1 black (odd

@@ -121,15 +121,7 @@ int solve1(sap_ctx* c, double2* x, const double2* b, int lb, int colour, const s
   return rc;
 }
 
-int check_opts(sap_ctx* c, const sap_solve_opts* o) {
-  if (!o) return sap_fail(c, SAP_E_ARG, "opts is NULL");
-  if (!(o->tol > 0 && o->tol < 1) || o->max_iter < 1 || o->max_outer < 1)
-    return sap_fail(c, SAP_E_ARG, "invalid solve options");
-  if (o->inner_prec != SAP_F64 && o->inner_prec != SAP_F32) return sap_fail(c, SAP_E_ARG, "unknown inner precision");
-  if (o->inner_prec == SAP_F32 && !(o->inner_tol > 0 && o->inner_tol < 1))
-    return sap_fail(c, SAP_E_ARG, "inner_tol must be in (0, 1) for an FP32 inner solve");
-  return SAP_OK;
-}
+int check_opts(sap_ctx* c, const sap_solve_opts* o) { return check_solve_opts(c, o); }
 
 int pf_force(sap_ctx* c, double* F, double coef, const double2* phi, const sap_solve_opts* o, double* S,
              hipStream_t s, const double* sx = nullptr) {
@@ -315,7 +307,7 @@ int kinetic_host(sap_ctx* c, const double* P, double* K, hipStream_t s) {
   return SAP_OK;
 }
 
-void links_changed(sap_ctx* c, hipStream_t s) { launch_gauge_to_f32(c->g, c->U32, c->U64, s); }
+void links_changed(sap_ctx* c, hipStream_t s) { launch_gauge_to_f32(c->g, c->U32, c->U16, c->U64, s); }
 
 // ---- the two-level integrator --------------------------------------------------------
 struct Traj {

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <string>
+#include <type_traits>
 #include <vector>
 #include "../../include/sapmi.h"
 #include "device_common.h"
@@ -12,6 +13,10 @@ namespace sap {
 // A spinor field in the library layout: element (rhs, parity, component c, site j) of
 // complex type at  ptr + rhs*rs + parity*ps + tiled(j, c, 12)  (in complex numbers).
 // Full fields: rs = 24*Vhp, ps = 12*Vhp. Single-parity fields: rs = 12*Vhp, ps = 0.
+// FP16 (h16) fields also hold one FP32 norm per site: the components are stored divided
+// by it, and the norms of (rhs, parity) start at  (float*)(ptr + rhs*rs + no) + parity*Vhp.
+// Full FP16 fields: rs = 26*Vhp, ps = 12*Vhp, no = 24*Vhp; single-parity: rs = 13*Vhp,
+// ps = 0, no = 12*Vhp (a half2 and a float are both 4 bytes).
 // Gauge field: link (parity p, site j, mu, entry e = 3*row + col) at
 //   p*36*Vhp + tiled(j, 9*mu + e, 36).
 // Momenta / forces (float64): (p, j, mu, a) at  p*32*Vhp + tiled(j, 8*mu + a, 32).
@@ -19,7 +24,27 @@ template <class R> struct Field {
   typename vec2<R>::type* ptr;
   long long rs;
   long long ps;
+  long long no;            // FP16 only: offset of the norms in an rhs block (complex units)
 };
+
+// field descriptors of the library's full and single-parity fields for storage type S
+template <class S> inline Field<S> full_field(void* p, long long Vhp) {
+  if constexpr (std::is_same<S, h16>::value) return {(typename vec2<S>::type*)p, 26 * Vhp, 12 * Vhp, 24 * Vhp};
+  else return {(typename vec2<S>::type*)p, 24 * Vhp, 12 * Vhp, 0};
+}
+template <class S> inline Field<S> half_field(void* p, long long Vhp) {
+  if constexpr (std::is_same<S, h16>::value) return {(typename vec2<S>::type*)p, 13 * Vhp, 0, 12 * Vhp};
+  else return {(typename vec2<S>::type*)p, 12 * Vhp, 0, 0};
+}
+// bytes of nrhs full / single-parity fields
+template <class S> inline size_t full_bytes(long long Vhp, int nrhs) {
+  if constexpr (std::is_same<S, h16>::value) return (size_t)26 * Vhp * nrhs * 4;
+  else return (size_t)24 * Vhp * nrhs * sizeof(typename vec2<S>::type);
+}
+template <class S> inline size_t half_bytes(long long Vhp, int nrhs) {
+  if constexpr (std::is_same<S, h16>::value) return (size_t)13 * Vhp * nrhs * 4;
+  else return (size_t)12 * Vhp * nrhs * sizeof(typename vec2<S>::type);
+}
 
 template <class R> struct HopArgs {
   Field<R> out, in, x;     // out = a*x + b*D(in); x.ptr may be null
@@ -31,7 +56,7 @@ template <class R> struct HopArgs {
   int slb;                 // output restricted to x0 blocks of this length (0: all sites)
   int colour;              // selection for slb: 0 all, 1 black (odd b), 2 white (even b)
   int block;               // >= 0: only this block (colour ignored)
-  R a, b;
+  typename arith<R>::type a, b;
   int g5_in, g5_out;       // multiply the hop input / the hop result by gamma_5
   int map;                 // work-item mapping (HOP_MAP_*), nrhs > 1 only
 };
@@ -56,6 +81,7 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
 constexpr int HOP_WALK_T = 8;   // slices per walk
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
+template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t s);   // half.hip
 
 // layout conversions
 template <class R>
@@ -66,7 +92,10 @@ void launch_unpack_spinor(const Geo& g, double2* out, const typename vec2<R>::ty
                           int nrhs, hipStream_t s);
 void launch_pack_gauge(const Geo& g, double2* U64, float2* U32, const double2* in, hipStream_t s);
 void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStream_t s);
-void launch_gauge_to_f32(const Geo& g, float2* U32, const double2* U64, hipStream_t s);
+// the FP32 (and, if U16 is given, FP16) link copies from the FP64 links
+void launch_gauge_to_f32(const Geo& g, float2* U32, __half2* U16, const double2* U64, hipStream_t s);
+void launch_pack_spinor16(const Geo& g, __half2* out, const double2* in, int nrhs, hipStream_t s);
+void launch_unpack_spinor16(const Geo& g, double2* out, const __half2* in, int nrhs, hipStream_t s);
 void launch_pack_momenta(const Geo& g, double* out, const double* in, hipStream_t s);
 void launch_unpack_momenta(const Geo& g, double* out, const double* in, hipStream_t s);
 
@@ -90,6 +119,7 @@ struct sap_ctx {
   bool have_gauge;
   double2* U64;   // tiled gauge layout, 72*Vhp complex
   float2* U32;
+  __half2* U16;   // FP16 copy (kept in step with U32)
   std::string err;
   void* solver;   // solver workspace (solver.hip)
   void* forces;   // force / trajectory workspace (hmc.hip)
@@ -114,3 +144,15 @@ int sap_fail(sap_ctx* ctx, int code, const std::string& msg);
     if (e_ != hipSuccess)                                                            \
       return sap_fail((ctx), SAP_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+namespace sap {
+// validation of solve options shared by every entry point that solves (solver.hip)
+int check_solve_opts(sap_ctx* c, const sap_solve_opts* o);
+}
+
+// the context's link copy for storage type S
+template <class S> inline const typename sap::vec2<S>::type* gauge_of(const sap_ctx* c) {
+  if constexpr (std::is_same<S, double>::value) return c->U64;
+  else if constexpr (std::is_same<S, float>::value) return c->U32;
+  else return c->U16;
+}

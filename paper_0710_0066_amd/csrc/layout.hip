@@ -82,11 +82,49 @@ __global__ void unpack_gauge_kernel(Geo g, double2* out, const double2* U64) {
       out[(i * 4 + mu) * 9 + e] = U64[p * 36 * g.Vhp + tiled(j, 9 * mu + e, 36)];
 }
 
-__global__ void gauge_to_f32_kernel(long long n, float2* U32, const double2* U64) {
+__global__ void gauge_to_f32_kernel(long long n, float2* U32, __half2* U16, const double2* U64) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   double2 v = U64[k];
   U32[k] = make_float2((float)v.x, (float)v.y);
+  if (U16) U16[k] = __floats2half2_rn((float)v.x, (float)v.y);
+}
+
+// FP16 spinor fields: components divided by the site norm (the largest component
+// magnitude), norm in FP32 (rhs blocks of 26*Vhp four-byte entries)
+__global__ void pack_spinor16_kernel(Geo g, __half2* out, const double2* in, int nrhs) {
+  const long long V = 2 * g.Vh;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V * nrhs) return;
+  const long long rhs = t / V, i = t - rhs * V;
+  const Lex c = lex_coords(g, i);
+  const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
+  const long long j = i >> 1;
+  __half2* blk = out + rhs * 26 * g.Vhp;
+  const double2* src = in + (rhs * V + i) * 12;
+  float m = 0.0f;
+  for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf((float)src[k].x), fabsf((float)src[k].y)));
+  const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+  for (int k = 0; k < 12; ++k)
+    blk[p * 12 * g.Vhp + tiled(j, k, 12)] = __floats2half2_rn((float)src[k].x * inv, (float)src[k].y * inv);
+  ((float*)(blk + 24 * g.Vhp))[p * g.Vhp + j] = m;
+}
+
+__global__ void unpack_spinor16_kernel(Geo g, double2* out, const __half2* in, int nrhs) {
+  const long long V = 2 * g.Vh;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= V * nrhs) return;
+  const long long rhs = t / V, i = t - rhs * V;
+  const Lex c = lex_coords(g, i);
+  const int p = (c.x0 + c.x1 + c.x2 + c.x3) & 1;
+  const long long j = i >> 1;
+  const __half2* blk = in + rhs * 26 * g.Vhp;
+  const float m = ((const float*)(blk + 24 * g.Vhp))[p * g.Vhp + j];
+  double2* o = out + (rhs * V + i) * 12;
+  for (int k = 0; k < 12; ++k) {
+    const float2 v = __half22float2(blk[p * 12 * g.Vhp + tiled(j, k, 12)]);
+    o[k] = make_double2((double)(v.x * m), (double)(v.y * m));
+  }
 }
 
 __global__ void pack_momenta_kernel(Geo g, double* out, const double* in, int to_sap) {
@@ -130,9 +168,17 @@ void launch_pack_gauge(const Geo& g, double2* U64, float2* U32, const double2* i
 void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStream_t s) {
   hipLaunchKernelGGL(unpack_gauge_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, U64);
 }
-void launch_gauge_to_f32(const Geo& g, float2* U32, const double2* U64, hipStream_t s) {
+void launch_gauge_to_f32(const Geo& g, float2* U32, __half2* U16, const double2* U64, hipStream_t s) {
   long long n = 72LL * g.Vhp;
-  hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, U32, U64);
+  hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, n, U32, U16, U64);
+}
+void launch_pack_spinor16(const Geo& g, __half2* out, const double2* in, int nrhs, hipStream_t s) {
+  long long n = 2 * g.Vh * nrhs;
+  hipLaunchKernelGGL(pack_spinor16_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, g, out, in, nrhs);
+}
+void launch_unpack_spinor16(const Geo& g, double2* out, const __half2* in, int nrhs, hipStream_t s) {
+  long long n = 2 * g.Vh * nrhs;
+  hipLaunchKernelGGL(unpack_spinor16_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, g, out, in, nrhs);
 }
 void launch_pack_momenta(const Geo& g, double* out, const double* in, hipStream_t s) {
   hipLaunchKernelGGL(pack_momenta_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, in, 1);

@@ -1,0 +1,76 @@
+// Per-site access to spinor fields of any storage type (double, float, h16). A reader
+// yields the 12 components of one site at the arithmetic precision; a writer takes them
+// one by one. For FP16 storage (h16) the components of a site are stored divided by the
+// site norm (their largest magnitude, FP32): the reader scales by it, and the writer
+// buffers the site and stores it, with its new norm, at close(). For double and float a
+// writer stores each component at once, so those kernels keep their plain access pattern.
+#pragma once
+#include <type_traits>
+#include "internal.h"
+
+namespace sap {
+
+template <class R> constexpr bool is_h16 = std::is_same<R, h16>::value;
+template <class R> using arith_t = typename arith<R>::type;
+
+// norms of block (rhs, parity p) of an FP16 field
+__device__ __forceinline__ float* norm_ptr16(const Field<h16>& f, int rhs, int p, long long Vhp) {
+  return (float*)(f.ptr + rhs * f.rs + f.no) + (f.ps ? p : 0) * Vhp;
+}
+
+template <class R> struct SiteR {
+  const typename vec2<R>::type* b;   // component 0 of the site; component c at b + c*TILE
+  float m;                           // h16: site norm
+};
+
+template <class R>
+__device__ __forceinline__ SiteR<R> site_r(const Field<R>& f, int rhs, int p, long long j, long long Vhp) {
+  SiteR<R> s;
+  s.b = f.ptr + rhs * f.rs + p * f.ps + tiled(j, 0, 12);
+  if constexpr (is_h16<R>) s.m = norm_ptr16(f, rhs, p, Vhp)[j];
+  else s.m = 1.0f;
+  return s;
+}
+
+template <class R> __device__ __forceinline__ cx<arith_t<R>> get(const SiteR<R>& s, int c) {
+  if constexpr (is_h16<R>) {
+    const float2 v = __half22float2(s.b[c * TILE]);
+    return {v.x * s.m, v.y * s.m};
+  } else {
+    return ld<R>(s.b + c * TILE);
+  }
+}
+
+template <class R> struct SiteW {
+  typename vec2<R>::type* b;
+  float* n;                              // h16: where the site norm goes
+  cx<float> v[is_h16<R> ? 12 : 1];       // h16: the buffered site
+};
+
+template <class R>
+__device__ __forceinline__ SiteW<R> site_w(const Field<R>& f, int rhs, int p, long long j, long long Vhp) {
+  SiteW<R> w;
+  w.b = f.ptr + rhs * f.rs + p * f.ps + tiled(j, 0, 12);
+  if constexpr (is_h16<R>) w.n = norm_ptr16(f, rhs, p, Vhp) + j;
+  else w.n = nullptr;
+  return w;
+}
+
+template <class R> __device__ __forceinline__ void put(SiteW<R>& w, int c, cx<arith_t<R>> a) {
+  if constexpr (is_h16<R>) w.v[c] = a;
+  else st<R>(w.b + c * TILE, a);
+}
+
+template <class R> __device__ __forceinline__ void close(SiteW<R>& w) {
+  if constexpr (is_h16<R>) {
+    float m = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(w.v[c].r), fabsf(w.v[c].i)));
+    const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) w.b[c * TILE] = __floats2half2_rn(w.v[c].r * inv, w.v[c].i * inv);
+    *w.n = m;
+  }
+}
+
+}  // namespace sap

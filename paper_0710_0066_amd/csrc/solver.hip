@@ -42,7 +42,7 @@ struct SolverWS {
   // captured inner-loop graphs (ITERS_PER_GRAPH CG iterations each), replayed on the
   // caller's stream; captured on a private non-blocking stream of default priority
   hipStream_t cap;
-  struct G { int nrhs, lb, sel, f32, method; double rho; hipGraphExec_t exec; };
+  struct G { int nrhs, lb, sel, prec, method; double rho; hipGraphExec_t exec; };
   std::vector<G> graphs;
 };
 
@@ -123,7 +123,7 @@ namespace {
 // out = a*x + b*D(in) on one parity or both, block-restricted
 template <class R>
 void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int parity_out, int nrhs, int lb,
-         int colour, R a, R b, int g5i, int g5o, hipStream_t st) {
+         int colour, typename arith<R>::type a, typename arith<R>::type b, int g5i, int g5o, hipStream_t st) {
   HopArgs<R> A;
   A.out = out;
   A.in = in;
@@ -140,8 +140,13 @@ void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int p
   A.b = b;
   A.g5_in = g5i;
   A.g5_out = g5o;
-  A.map = hop_map_for(c, parity_out < 0, sizeof(R) == 4, nrhs);
+  A.map = hop_map_for(c, parity_out < 0, std::is_same<R, float>::value, nrhs);
   launch_hop<R>(A, st);
+}
+
+// precision code of a storage type (SAP_F64 / SAP_F32 / SAP_F16)
+template <class R> constexpr int prec_code() {
+  return std::is_same<R, double>::value ? SAP_F64 : std::is_same<R, float>::value ? SAP_F32 : SAP_F16;
 }
 
 }  // namespace
@@ -153,28 +158,30 @@ template <class R>
 static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
                       const sap_solve_opts* o, sap_solve_info* info, hipStream_t st, double rho = 0.0,
                       bool eo_only = false) {
-  typedef typename vec2<R>::type V2;
+  typedef typename arith<R>::type Ar;
   SolverWS* w = ws_of(c);
   const long long Vh = c->Vh, Vhp = c->Vhp;
   const SysGrid G = make_sysgrid(Vh, c->g.V3h, lb, c->geom.L[0], colour);
   const int nsys = G.nblk * nrhs;
   const double kap = c->geom.kappa;
-  const void* U = sizeof(R) == 8 ? (const void*)c->U64 : (const void*)c->U32;
-  const R kR = (R)kap, k2R = (R)(-kap * kap);
-  const R aI = (R)(1.0 + rho);                 // unit term of M_hat + rho
+  const void* U = gauge_of<R>(c);
+  const Ar kR = (Ar)kap, k2R = (Ar)(-kap * kap);
+  const Ar aI = (Ar)(1.0 + rho);               // unit term of M_hat + rho
   const size_t fullb = (size_t)24 * Vhp * nrhs * sizeof(double2);
+  const size_t fullR = full_bytes<R>(Vhp, nrhs), halfR = half_bytes<R>(Vhp, nrhs);
   if (o->method == SAP_GEOM && (eo_only || rho != 0.0))
     return sap_fail(c, SAP_E_ARG, "the geometric series is available for the unshifted W x = b only");
 
   Field<double> X = {(double2*)x, 24 * Vhp, 12 * Vhp}, B = {(double2*)b, 24 * Vhp, 12 * Vhp};
   Field<double> R64 = {w->r64, 24 * Vhp, 12 * Vhp}, AX = {w->ax, 24 * Vhp, 12 * Vhp};
-  Field<R> RIN = {(V2*)w->rin, 24 * Vhp, 12 * Vhp}, E = {(V2*)w->e, 24 * Vhp, 12 * Vhp};
-  Field<R> Ee = {(V2*)w->e, 24 * Vhp, 0};
-  Field<R> S = {(V2*)w->s, 12 * Vhp, 0}, Rr = {(V2*)w->r, 12 * Vhp, 0}, P = {(V2*)w->p, 12 * Vhp, 0};
-  Field<R> Q = {(V2*)w->q, 12 * Vhp, 0}, T = {(V2*)w->t, 12 * Vhp, 0};
-  Field<R> HX = {(V2*)w->hx, 12 * Vhp, 0};
+  Field<R> RIN = full_field<R>(w->rin, Vhp), E = full_field<R>(w->e, Vhp);
+  Field<R> Ee = E;                             // the even half of E
+  Ee.ps = 0;
+  Field<R> S = half_field<R>(w->s, Vhp), Rr = half_field<R>(w->r, Vhp), P = half_field<R>(w->p, Vhp);
+  Field<R> Q = half_field<R>(w->q, Vhp), T = half_field<R>(w->t, Vhp);
+  Field<R> HX = half_field<R>(w->hx, Vhp);
   const int method = (int)o->method;
-  Field<R> NONE = {nullptr, 0, 0};
+  Field<R> NONE = {nullptr, 0, 0, 0};
   SysScal SC = {w->gam, w->ss, w->alpha, w->beta, w->active, w->iters, w->flags};
 
   // selection of systems
@@ -193,7 +200,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
   SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_bnorm2, w->bnorm2, nsys * 8, hipMemcpyDeviceToHost, st));
 
   const double tol = o->tol;
-  const double inner_tol = (sizeof(R) == 8 && o->inner_tol <= 0) ? tol : o->inner_tol;
+  const double inner_tol = (std::is_same<R, double>::value && o->inner_tol <= 0) ? tol : o->inner_tol;
   long long total_iters = 0;
   int outer = 0;
   int status = SAP_OK;
@@ -217,18 +224,18 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     // inner right-hand side at the inner precision
     blas_convert<R, double>(G, nrhs, RIN, R64, 2, st);
     // b_hat_e = r_e + k D_eo r_o  (into S)
-    hop<R>(c, U, S, RIN, RIN, 0, nrhs, lb, colour, R(1), kR, 0, 0, st);
-    SAP_HIP_CHECK(c, hipMemsetAsync(w->e, 0, fullb / (sizeof(R) == 8 ? 1 : 2), st));
+    hop<R>(c, U, S, RIN, RIN, 0, nrhs, lb, colour, Ar(1), kR, 0, 0, st);
+    SAP_HIP_CHECK(c, hipMemsetAsync(w->e, 0, fullR, st));
     blas_norm2<R>(G, nrhs, S, 1, w->partB, st);
     // stop the inner solve at ||s|| <= max(inner_tol ||b_hat||, 0.3 tol ||b||): the outer
     // residual after x += e equals the inner one up to rounding
     hipLaunchKernelGGL(k_targets, dim3(1), dim3(256), 0, st, nsys, w->partB, G.nchunk, w->bnorm2,
                        inner_tol * inner_tol, 0.09 * tol * tol, w->target2);
     SAP_HIP_CHECK(c, hipMemsetAsync(w->flags, 0, 16, st));
-    const size_t halfb = fullb / 2 / (sizeof(R) == 8 ? 1 : 2);
+    const size_t halfb = halfR;
     if (method == SAP_CG) {
       // r = M_hat^dagger s = s - k^2 g5 D_eo D_oe g5 s
-      hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, st);
+      hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 1, 0, st);
       hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 1, st);
       blas_norm2<R>(G, nrhs, Rr, 1, w->partC, st);
       fin_init(SC, nsys, G.nchunk, w->partB, w->partC, w->selected, w->target2, st);
@@ -249,14 +256,14 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     auto iterate = [&](hipStream_t q) {
       if (method == SAP_CG) {
         // q = M_hat p
-        hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+        hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 0, 0, q);
         hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
         blas_norm2<R>(G, nrhs, Q, 1, w->partA, q);
         fin_alpha(SC, nsys, G.nchunk, w->partA, q);
         // x += alpha p, s -= alpha q
         blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, q);
         // r = M_hat^dagger s
-        hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 1, 0, q);
+        hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 1, 0, q);
         hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 1, q);
         blas_norm2<R>(G, nrhs, Rr, 1, w->partC, q);
         fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, q);
@@ -264,12 +271,12 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
       } else if (method == SAP_BICGSTAB) {
         // residual r in S, shadow r0 in Rr, v in Q, t in HX
         blas_bicg_p<R>(G, nrhs, P, S, Q, w->cs, q);
-        hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+        hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 0, 0, q);
         hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
         blas_cdot3<R>(G, nrhs, Rr, Q, NONE, w->partB, q);
         fin_bicg_alpha(SC, w->cs, nsys, G.nchunk, w->partB, q);
         blas_bicg_s<R>(G, nrhs, S, Q, w->cs, w->partB, q);
-        hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
+        hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 0, 0, q);
         hop<R>(c, U, HX, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
         blas_cdot3<R>(G, nrhs, HX, S, HX, w->partC, q);
         fin_bicg_omega(SC, w->cs, nsys, G.nchunk, w->partC, w->partB, w->target2, q);
@@ -280,8 +287,8 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
         for (int h = 0; h < 2; ++h) {
           Field<R> from = h == 0 ? S : HX, to = h == 0 ? HX : S;
           blas_geom_add<R>(G, nrhs, Ee, from, w->active, q);
-          hop<R>(c, U, T, from, NONE, 1, nrhs, lb, colour, R(0), R(1), 0, 0, q);
-          hop<R>(c, U, to, T, NONE, 0, nrhs, lb, colour, R(0), (R)(kap * kap), 0, 0, q);
+          hop<R>(c, U, T, from, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 0, 0, q);
+          hop<R>(c, U, to, T, NONE, 0, nrhs, lb, colour, Ar(0), (Ar)(kap * kap), 0, 0, q);
           blas_norm2<R>(G, nrhs, to, 1, w->partA, q);
           fin_geom(SC, nsys, G.nchunk, w->partA, w->selected, w->target2, 0, q);
         }
@@ -292,7 +299,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     const int calls = ITERS_PER_GRAPH / per_call;
     hipGraphExec_t exec = nullptr;
     for (auto& g : w->graphs)
-      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.f32 == (int)(sizeof(R) == 4) && g.method == method &&
+      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.prec == prec_code<R>() && g.method == method &&
           g.rho == rho)
         exec = g.exec;
     if (!exec) {
@@ -305,7 +312,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
         }
       }
       (void)hipGetLastError();
-      if (exec) w->graphs.push_back({nrhs, lb, colour, (int)(sizeof(R) == 4), method, rho, exec});
+      if (exec) w->graphs.push_back({nrhs, lb, colour, prec_code<R>(), method, rho, exec});
     }
     for (;;) {
       SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 12, hipMemcpyDeviceToHost, st));
@@ -324,7 +331,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
       total_iters += ITERS_PER_GRAPH;
     }
     // e_o = r_o + k D_oe e_e ; x += e ; r = b - A x (FP64)
-    if (!eo_only) hop<R>(c, U, E, Ee, RIN, 1, nrhs, lb, colour, R(1), kR, 0, 0, st);
+    if (!eo_only) hop<R>(c, U, E, Ee, RIN, 1, nrhs, lb, colour, Ar(1), kR, 0, 0, st);
     blas_add_mixed<R>(G, nrhs, X, E, st);
     if (eo_only) {
       // A x = (M_hat + rho) x_e on the even sites, via the odd half of AX
@@ -440,13 +447,14 @@ extern "C" int sap_set_hop_map(sap_ctx* c, int full, sap_prec prec, int nrhs, in
   return SAP_OK;
 }
 
-static int check_opts(sap_ctx* c, const sap_solve_opts* o) {
+int sap::check_solve_opts(sap_ctx* c, const sap_solve_opts* o) {
   if (!o) return sap_fail(c, SAP_E_ARG, "opts is NULL");
   if (!(o->tol > 0 && o->tol < 1)) return sap_fail(c, SAP_E_ARG, "tol must be in (0, 1)");
   if (o->max_iter < 1 || o->max_outer < 1) return sap_fail(c, SAP_E_ARG, "max_iter and max_outer must be >= 1");
-  if (o->inner_prec != SAP_F64 && o->inner_prec != SAP_F32) return sap_fail(c, SAP_E_ARG, "unknown inner precision");
-  if (o->inner_prec == SAP_F32 && !(o->inner_tol > 0 && o->inner_tol < 1))
-    return sap_fail(c, SAP_E_ARG, "inner_tol must be in (0, 1) for an FP32 inner solve");
+  if (o->inner_prec != SAP_F64 && o->inner_prec != SAP_F32 && o->inner_prec != SAP_F16)
+    return sap_fail(c, SAP_E_ARG, "unknown inner precision");
+  if (o->inner_prec != SAP_F64 && !(o->inner_tol > 0 && o->inner_tol < 1))
+    return sap_fail(c, SAP_E_ARG, "inner_tol must be in (0, 1) for an FP32 or FP16 inner solve");
   if (o->method != SAP_CG && o->method != SAP_BICGSTAB && o->method != SAP_GEOM && o->method != SAP_SAP_BICGSTAB)
     return sap_fail(c, SAP_E_ARG, "unknown method");
   if (o->method == SAP_SAP_BICGSTAB && (o->sap_ncy < 1 || !(o->inner_tol > 0 && o->inner_tol < 1)))
@@ -564,7 +572,9 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
   // block solves of the preconditioner
   sap_solve_opts bo = *o;
   bo.tol = o->inner_tol;
-  bo.inner_tol = o->inner_prec == SAP_F32 ? std::max(o->inner_tol, 1e-5) : o->inner_tol;
+  bo.inner_tol = o->inner_prec == SAP_F32   ? std::max(o->inner_tol, 1e-5)
+                 : o->inner_prec == SAP_F16 ? std::max(o->inner_tol, 1e-2)
+                                            : o->inner_tol;
   bo.max_outer = 40;
   bo.max_iter = 1 << 30;
   bo.method = SAP_CG;
@@ -585,7 +595,9 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
         }
         int rc = o->inner_prec == SAP_F64
                      ? solve_impl<double>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st)
-                     : solve_impl<float>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st);
+                 : o->inner_prec == SAP_F32
+                     ? solve_impl<float>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st)
+                     : solve_impl<h16>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st);
         if (rc) return rc;
         for (auto& e : binfo) block_iters += e.iters;
         if ((rc = lin3(a->kx, a->ky, nullptr, nullptr, one, one, zero, false))) return rc;
@@ -694,7 +706,8 @@ int sap_solve_eo_shift(sap_ctx* c, double* x, const double* b, int nrhs, int lb,
                        const sap_solve_opts* o, sap_solve_info* info, hipStream_t st) {
   if (o->method == SAP_SAP_BICGSTAB) return sap_fail(c, SAP_E_ARG, "SAP_SAP_BICGSTAB solves M x = b only");
   if (o->inner_prec == SAP_F64) return solve_impl<double>(c, x, b, nrhs, lb, 0, o, info, st, rho, true);
-  return solve_impl<float>(c, x, b, nrhs, lb, 0, o, info, st, rho, true);
+  if (o->inner_prec == SAP_F32) return solve_impl<float>(c, x, b, nrhs, lb, 0, o, info, st, rho, true);
+  return solve_impl<h16>(c, x, b, nrhs, lb, 0, o, info, st, rho, true);
 }
 
 int sap_solve_any(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int colour,
@@ -704,7 +717,8 @@ int sap_solve_any(sap_ctx* c, double* x, const double* b, int nrhs, int lb, int 
     return sap_bicgstab(c, x, b, nrhs, o, info, st);
   }
   if (o->inner_prec == SAP_F64) return solve_impl<double>(c, x, b, nrhs, lb, colour, o, info, st);
-  return solve_impl<float>(c, x, b, nrhs, lb, colour, o, info, st);
+  if (o->inner_prec == SAP_F32) return solve_impl<float>(c, x, b, nrhs, lb, colour, o, info, st);
+  return solve_impl<h16>(c, x, b, nrhs, lb, colour, o, info, st);
 }
 
 extern "C" {
@@ -715,7 +729,7 @@ int solve_full(sap_ctx* c, double* x, const double* b, int nrhs, const sap_solve
   if (!x || !b) return sap_fail(c, SAP_E_ARG, "x or b is NULL");
   if (x == b) return sap_fail(c, SAP_E_ARG, "x and b must not alias");
   if (nrhs < 1 || nrhs > c->geom.max_rhs) return sap_fail(c, SAP_E_ARG, "nrhs must be in [1, max_rhs]");
-  int rc = check_opts(c, o);
+  int rc = check_solve_opts(c, o);
   if (rc) return rc;
   if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
   return sap_solve_any(c, x, b, nrhs, 0, 0, o, info, (hipStream_t)stream);
@@ -734,7 +748,7 @@ int solve_blocks(sap_ctx* c, double* x, const double* b, int nrhs, int level, sa
   if (color != SAP_ALL && color != SAP_BLACK && color != SAP_WHITE)
     return sap_fail(c, SAP_E_ARG, "unknown colour");
   if (block < -1 || block >= c->geom.L[0] / lb) return sap_fail(c, SAP_E_ARG, "block out of range");
-  int rc = check_opts(c, o);
+  int rc = check_solve_opts(c, o);
   if (rc) return rc;
   if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
   const int sel = block >= 0 ? 3 + block : (int)color;
