@@ -242,9 +242,12 @@ int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parit
  * each of the 8 XCDs owning 1/8 of every x0 slice and walking the slices in increasing
  * x0), 14 / 15 walk1 / walk2 (even-odd hop: each work-item walks 8 slices at a fixed
  * spatial site with 1 / 2 rhs, loads every time neighbour once and carries its
- * projection in registers; the full operator runs them as march1 / march2). us_out
- * (host, may be NULL): 64 floats, microseconds per launch (-1: not applicable), ordered
- * [full f64, full f32, even-odd f64, even-odd f32] x the 16 mappings. Uses the solver
+ * projection in registers; the full operator runs them as march1 / march2), 16 band1
+ * (even-odd hop: each XCD owns a band of x0 slices and each work-item steps through it at
+ * a fixed spatial site, loading every input once and carrying the time hops in registers;
+ * the full operator runs it as march1). us_out (host, may be NULL): 68 floats,
+ * microseconds per launch (-1: not applicable), ordered [full f64, full f32, even-odd
+ * f64, even-odd f32] x the 17 mappings. Uses the solver
  * workspace; synchronises. Untuned calls use site for one rhs and lane4 for several. */
 int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
 

@@ -245,7 +245,7 @@ def sap_tune(ctx, nrhs):
     _check(ctx.ptr, _lib.sap_tune(ctx.ptr, nrhs, us, _stream()))
     names = ["full_f64", "full_f32", "eo_f64", "eo_f32"]
     maps = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4",
-            "reg2_sweep", "reg4_sweep", "march1", "march2", "march4", "walk1", "walk2"]
+            "reg2_sweep", "reg4_sweep", "march1", "march2", "march4", "walk1", "walk2", "band1"]
     return {n: {m: us[HOP_NMAP * i + k] for k, m in enumerate(maps) if us[HOP_NMAP * i + k] >= 0}
             for i, n in enumerate(names)}
 
@@ -254,7 +254,8 @@ HOP_MAP_SITE, HOP_MAP_LANE4, HOP_MAP_WAVE4, HOP_MAP_STREAM, HOP_SWEEP = 0, 1, 2,
 HOP_MAP_REG2, HOP_MAP_REG4, HOP_MAP_REG2_SWEEP, HOP_MAP_REG4_SWEEP = 7, 8, 9, 10
 HOP_MAP_MARCH1, HOP_MAP_MARCH2, HOP_MAP_MARCH4 = 11, 12, 13
 HOP_MAP_WALK1, HOP_MAP_WALK2 = 14, 15
-HOP_NMAP = 16
+HOP_MAP_BAND1 = 16
+HOP_NMAP = 17
 
 
 def sap_set_hop_map(ctx, full, prec, nrhs, hop_map):

@@ -680,6 +680,144 @@ __global__ __launch_bounds__(128) void hop_walk_kernel(HopArgs<R> A, int nck, in
   }
 }
 
+// x0-band even-odd hop. XCD k (workgroup id % 8) owns the output slices
+// [L0 k / 8, L0 (k + 1) / 8) and every slice-local site of them; a work-item owns the site
+// s (j = x0*V3h + s) for a group of NR rhs and steps through the input slices x = x0a - 1
+// .. x0b. At step x it loads the input (x, s) once: its (1 - g0) projection completes
+// output (x - 1, s) with the forward time hop, and its (1 + g0) projection times
+// U_0(x, s)^+ is carried in registers to output (x + 1, s) (a step in x0 keeps s and flips
+// the parity). The spatial hops of output (x, s) read the inputs (x, s +/- mu), which the
+// neighbouring work-items load in the same step, so an input site is fetched once per
+// band and reused through L2 while it is in flight, not across steps. The band edges add
+// two input slices per XCD. A workgroup is 128 consecutive slice-local sites; the result
+// is stored non-temporally.
+template <class R, int NR>
+__global__ __launch_bounds__(128) void hop_band_kernel(HopArgs<R> A, int nck) {
+  typedef typename vec2<R>::type V2;
+  const int xcd = blockIdx.x & 7;
+  const long long l = blockIdx.x >> 3;
+  const int ngroups = (A.nrhs + NR - 1) / NR;
+  const int chunk = (int)(l / ngroups);
+  const int r0 = (int)(l - (long long)chunk * ngroups) * NR;
+  const Geo& g = A.g;
+  const int x0a = (int)((long long)g.L0 * xcd / 8), x0b = (int)((long long)g.L0 * (xcd + 1) / 8);
+  const int s = chunk * 128 + threadIdx.x;
+  if (chunk >= nck || x0a >= x0b || s >= g.V3h || r0 >= A.nrhs) return;
+  const int nr = min(NR, A.nrhs - r0);
+  const int p = A.parity_out, q = 1 - p;
+  const V2* inb = A.in.ptr + q * A.in.ps;
+  const bool g5i = A.g5_in != 0;
+  const int lb = A.lb;
+  const long long V3h = g.V3h;
+  auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
+  auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
+
+  cx<R> accp[NR][4][3];   // output x - 1: spatial and backward time hops done
+  cx<R> carry[NR][2][3];  // U_0^+ (1 + g0) input (x - 1), for the backward time hop of output x
+  bool have_carry = false;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) accp[r][a][c] = {R(0), R(0)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) carry[r][h][c] = {R(0), R(0)};
+  }
+
+  for (int x = x0a - 1; x <= x0b; ++x) {
+    const bool out_prev = x - 1 >= x0a;
+    const bool out_cur = x >= x0a && x < x0b;
+    const bool sel_prev = out_prev && hop_selected(A, x - 1);
+    const bool sel_cur = out_cur && hop_selected(A, x);
+    const bool need_f = sel_prev && fwd_on(x - 1);
+    const bool need_b = x + 1 < x0b && hop_selected(A, x + 1) && bwd_on(x + 1);
+    const int xw = x < 0 ? x + g.L0 : (x >= g.L0 ? x - g.L0 : x);
+    const long long jin = (long long)xw * V3h + s;
+    // input (x, s): both time projections; the forward one completes output x - 1
+    cx<R> hb[NR][2][3];
+    if (need_f || need_b) {
+      cx<R> hf[NR][2][3];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+          cx<R> sp[4][3];
+          load_spinor<R>(inb + (r0 + r) * A.in.rs, jin, g5i, sp);
+          project<R>(0, false, sp, hf[r]);
+          project<R>(0, true, sp, hb[r]);
+        }
+      }
+      if (need_f) {
+        cx<R> m[9];
+        load_link<R>(A.U, g.Vhp, 0, p, (long long)(x - 1) * V3h + s, m);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            cx<R> uh[2][3];
+            su3_mul<R>(m, hf[r][0], uh[0]);
+            su3_mul<R>(m, hf[r][1], uh[1]);
+            if (x - 1 == g.L0 - 1)
+#pragma unroll
+              for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+            accum_recon<R>(0, false, uh, accp[r]);
+          }
+        }
+      }
+    }
+    if (out_prev) hop_store<R, NR, true>(A, p, (long long)(x - 1) * V3h + s, r0, nr, sel_prev, accp);
+    // output x starts from the backward time hop carried from input x - 1
+    cx<R> acc[NR][4][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[r][a][c] = {R(0), R(0)};
+    if (sel_cur && have_carry)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) accum_recon<R>(0, true, carry[r], acc[r]);
+    // the backward time hop of output x + 1 from input x
+    if (need_b) {
+      cx<R> m[9];
+      load_link<R>(A.U, g.Vhp, 0, q, jin, m);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r < nr) {
+          su3_dag_mul<R>(m, hb[r][0], carry[r][0]);
+          su3_dag_mul<R>(m, hb[r][1], carry[r][1]);
+          if (x + 1 == 0)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) carry[r][k][c] = -carry[r][k][c];
+        }
+      }
+    }
+    have_carry = need_b;
+    if (out_cur) {
+      const long long j = (long long)x * V3h + s;
+      if (sel_cur) {
+        const Site st_ = decode(g, j, p);
+#pragma unroll
+        for (int mu = 1; mu < 4; ++mu) {
+          hop_dir<R, NR>(A, p, j, st_, mu, 0, r0, nr, acc);
+          hop_dir<R, NR>(A, p, j, st_, mu, 1, r0, nr, acc);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) accp[r][a][c] = acc[r][a][c];
+    }
+  }
+}
+
 static inline long long round8(long long n) { return (n + 7) / 8 * 8; }
 
 template <class R, int NR, bool SWEEP> static void launch_reg(const HopArgs<R>& A, hipStream_t st) {
@@ -713,6 +851,13 @@ template <class R, int NR> static void launch_walk(const HopArgs<R>& A, hipStrea
   hipLaunchKernelGGL((hop_walk_kernel<R, NR>), grid, blk, 0, st, A, nck, T);
 }
 
+template <class R, int NR> static void launch_band(const HopArgs<R>& A, hipStream_t st) {
+  const int nck = (A.g.V3h + 127) / 128;
+  const long long groups = (A.nrhs + NR - 1) / NR;
+  const dim3 grid((unsigned)(8LL * nck * groups)), blk(128);
+  hipLaunchKernelGGL((hop_band_kernel<R, NR>), grid, blk, 0, st, A, nck);
+}
+
 template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {
   typedef typename vec2<R>::type V2;
   constexpr int S = sizeof(R) == 8 ? 128 : 256;     // 48 KB of LDS either way
@@ -741,6 +886,10 @@ template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t st) {
     case HOP_MAP_WALK2:
       if (full) launch_march<R, 2>(A, st);
       else launch_walk<R, 2>(A, st);
+      return;
+    case HOP_MAP_BAND1:
+      if (full) launch_march<R, 1>(A, st);
+      else launch_band<R, 1>(A, st);
       return;
     default: break;
   }

@@ -77,7 +77,9 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
        HOP_MAP_MARCH4 = 13, //   MARCH1)
        HOP_MAP_WALK1 = 14,  // even-odd hop only: x0-walking, time neighbours carried in
        HOP_MAP_WALK2 = 15,  //   registers, 1 / 2 rhs per work-item
-       HOP_NMAP = 16 };
+       HOP_MAP_BAND1 = 16,  // even-odd hop only: each XCD owns a band of x0 slices, time
+                            //   hops carried in registers, 1 rhs per work-item
+       HOP_NMAP = 17 };
 constexpr int HOP_WALK_T = 8;   // slices per walk
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);

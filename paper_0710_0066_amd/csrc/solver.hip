@@ -389,12 +389,14 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
   float best_ms = 1e30f;
   for (int m = 0; m < HOP_NMAP; ++m) {
     const bool one_rhs_alias = m == HOP_MAP_LANE4 || m == HOP_MAP_WAVE4 ||
-                               (m >= HOP_SWEEP && m != HOP_MAP_MARCH1 && m != HOP_MAP_WALK1);
+                               (m >= HOP_SWEEP && m != HOP_MAP_MARCH1 && m != HOP_MAP_WALK1 &&
+                                m != HOP_MAP_BAND1);
     const bool half_only = m == HOP_MAP_STREAM || m >= HOP_MAP_WALK1;
     if ((full && half_only) || (nrhs == 1 && one_rhs_alias)) {
-      // the streaming and walking kernels exist for half hops only (the full operator runs
-      // the walking maps as MARCH1 / MARCH2); with one rhs the grouped and sweep orders
-      // coincide with SITE, MARCH2 / MARCH4 with MARCH1 and WALK2 with WALK1
+      // the streaming, walking and band kernels exist for half hops only (the full
+      // operator runs the walking and band maps as MARCH1 / MARCH2); with one rhs the
+      // grouped and sweep orders coincide with SITE, MARCH2 / MARCH4 with MARCH1 and
+      // WALK2 with WALK1
       if (us_out) us_out[m] = -1.0f;
       continue;
     }

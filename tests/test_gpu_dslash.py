@@ -94,13 +94,14 @@ def test_apply_Dslash_eo_matches_oracle(gu, L, l0, l0_sub, k, nrhs):
             assert gu.rel_err(got * m_out, ref) <= tol, (parity, prec)
 
 
-@pytest.mark.parametrize("hop_map", list(range(16)))
+@pytest.mark.parametrize("hop_map", list(range(17)))
 @pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15)])
 def test_every_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
     """Each work-item mapping of the hop kernel (site, lane4, wave4, their rhs-slowest
     orders, register-blocked 2 / 4 rhs, x0-marching per XCD and, for the even-odd hop, the
-    x0-streaming kernel with LDS staging and the x0-walking kernels with time neighbours
-    carried in registers) gives the oracle's D_eo, M and W, with
+    x0-streaming kernel with LDS staging, the x0-walking kernels with time neighbours
+    carried in registers and the x0-band kernel with one band of slices per XCD) gives
+    the oracle's D_eo, M and W, with
     1 and 5 right-hand sides, including the gamma_5-folded and block-restricted forms the
     solvers use (through solve_blocks)."""
     import paper_0710_0066_amd as sap
