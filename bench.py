@@ -108,10 +108,13 @@ def hbm_probe(torch, gib=2):
             "bytes": n * 8}
 
 
+KERNEL_SOURCES = ("dslash.hip", "half.hip", "site_io.h", "device_common.h", "internal.h")
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("dslash.hip", "device_common.h", "internal.h"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_0710_0066_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -197,3 +197,46 @@ def test_f16_links_follow_gauge_updates(gu):
     sap.apply_M(ctx, fout, gu.to_sap(ctx, psi, 1, sap.SAP_F16), 1, sap.SAP_F16)
     got = gu.from_sap(ctx, fout, 1, psi.shape, sap.SAP_F16)
     assert _err_vs_input(got, dirac.apply_M(U1, psi, k), psi) <= F16_TOL
+
+
+def test_f16_16x16x16x32_operator_error_and_solves(gu):
+    """The 16^3x32 workload (kappa = 0.1575) in FP16 storage: apply_M and apply_W1 against
+    the FP64 oracle on every element, and full and block solves whose inner iterations
+    run on FP16 fields, to a 1e-10 residual recomputed by the oracle; the FP16-inner
+    solution is compared with the FP64-inner one. The errors are printed."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["plain_16x16x16x32"]
+    L, k, l0 = cfg["L"], cfg["kappa"], cfg["l0"]
+    print("f16 16^3x32", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    psi = synth.gaussian_spinor(L, cfg["seed_src"])
+    ctx = gu.make_ctx(L, l0, k, U, cfg["l0_sub"], max_rhs=1)
+    fin = gu.to_sap(ctx, psi, 1, sap.SAP_F16)
+    fout = ctx.new_field(1, sap.SAP_F16)
+    sap.apply_M(ctx, fout, fin, 1, sap.SAP_F16)
+    eM = _err_vs_input(gu.from_sap(ctx, fout, 1, psi.shape, sap.SAP_F16), dirac.apply_M(U, psi, k), psi)
+    sap.apply_W1_block(ctx, fout, fin, 1, 1, -1, sap.SAP_ALL, sap.SAP_F16)
+    eW = _err_vs_input(gu.from_sap(ctx, fout, 1, psi.shape, sap.SAP_F16), dirac.apply_W(U, psi, k, l0), psi)
+    print(f"  apply_M f16 max error / max|psi| = {eM:.2e}, apply_W1 {eW:.2e}", flush=True)
+    assert eM <= F16_TOL and eW <= F16_TOL
+    fb = gu.to_sap(ctx, psi, 1)
+    x = {}
+    for name, prec, itol in (("f64", sap.SAP_F64, 0.0), ("f16", sap.SAP_F16, 1e-2)):
+        fx = ctx.new_field(1)
+        o = sap.solve_opts(tol=1e-10, max_iter=500000, inner_prec=prec, inner_tol=itol, max_outer=200)
+        info = sap.solve_full(ctx, fx, fb, 1, o)
+        x[name] = gu.from_sap(ctx, fx, 1, psi.shape)
+        res = float(_relres(U, x[name], psi, k))
+        print(f"  solve_full inner={name}: iters={info[0].iters} outer={info[0].outer} res={res:.2e}", flush=True)
+        assert res <= 1e-10
+    d = float(np.linalg.norm(x["f16"] - x["f64"]) / np.linalg.norm(x["f64"]))
+    print(f"  |x_f16 - x_f64| / |x_f64| = {d:.2e}", flush=True)
+    assert d <= 1e-7
+    fx = ctx.new_field(1)
+    o = sap.solve_opts(tol=1e-10, max_iter=500000, inner_prec=sap.SAP_F16, inner_tol=1e-2, max_outer=80)
+    info = sap.solve_blocks(ctx, fx, fb, 1, 1, sap.SAP_ALL, o)
+    xb = gu.from_sap(ctx, fx, 1, psi.shape)
+    res = float(np.max(_relres(U, xb, psi, k, l0)))
+    print(f"  solve_blocks inner=f16: max iters={max(i.iters for i in info)} "
+          f"outer={max(i.outer for i in info)} res={res:.2e}", flush=True)
+    assert res <= 1e-10
