@@ -245,18 +245,21 @@ int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parit
  * projection in registers; the full operator runs them as march1 / march2), 16 band1
  * (even-odd hop: each XCD owns a band of x0 slices and each work-item steps through it at
  * a fixed spatial site, loading every input once and carrying the time hops in registers;
- * the full operator runs it as march1). us_out (host, may be NULL): 68 floats,
+ * the full operator runs it as march1). FP16 storage has site and march1 / 2 / 4 only
+ * (the other maps run as one of these). us_out (host, may be NULL): 102 floats,
  * microseconds per launch (-1: not applicable), ordered [full f64, full f32, even-odd
- * f64, even-odd f32] x the 17 mappings. Uses the solver
- * workspace; synchronises. Untuned calls use site for one rhs and lane4 for several. */
+ * f64, even-odd f32, full f16, even-odd f16] x the 17 mappings. Uses the solver
+ * workspace; synchronises. Untuned calls use site for one rhs and lane4 (FP16: site) for
+ * several. */
 int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
 
 /* Set the hop mapping used for nrhs right-hand sides by hand (map: 0 site, 1 lane4,
  * 2 wave4, 3 stream (even-odd hop only, full = 0), 4..6 = 0..2 with rhs-slowest workgroup
  * order, 7 reg2, 8 reg4, 9 / 10 reg2 / reg4 group-slowest, 11 / 12 / 13 x0-marching with
  * 1 / 2 / 4 rhs per work-item, 14 / 15 x0-walking with 1 / 2 rhs (march1 / march2 for
- * the full operator); -1 restores the default), for the full operator (full = 1) or the
- * even-odd hop (full = 0) at precision prec. */
+ * the full operator), 16 x0-band (march1 for the full operator); -1 restores the
+ * default), for the full operator (full = 1) or the even-odd hop (full = 0) at precision
+ * prec. */
 int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);
 
 /* ---- solvers ------------------------------------------------------------------ */

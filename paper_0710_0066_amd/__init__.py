@@ -241,9 +241,9 @@ def sap_plaquette(ctx):
 
 def sap_tune(ctx, nrhs):
     """Tune the hop mapping for nrhs; returns microseconds per launch per variant."""
-    us = (ctypes.c_float * (4 * HOP_NMAP))()
+    us = (ctypes.c_float * (6 * HOP_NMAP))()
     _check(ctx.ptr, _lib.sap_tune(ctx.ptr, nrhs, us, _stream()))
-    names = ["full_f64", "full_f32", "eo_f64", "eo_f32"]
+    names = ["full_f64", "full_f32", "eo_f64", "eo_f32", "full_f16", "eo_f16"]
     maps = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4",
             "reg2_sweep", "reg4_sweep", "march1", "march2", "march4", "walk1", "walk2", "band1"]
     return {n: {m: us[HOP_NMAP * i + k] for k, m in enumerate(maps) if us[HOP_NMAP * i + k] >= 0}

@@ -215,7 +215,7 @@ static void full_op(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, i
   A.b = Ar(-ctx->geom.kappa);
   A.g5_in = 0;
   A.g5_out = 0;
-  A.map = hop_map_for(ctx, true, sizeof(R) == 4, nrhs);
+  A.map = hop_map_for(ctx, true, prec_of<R>(), nrhs);
   launch_hop<R>(A, s);
 }
 
@@ -239,7 +239,7 @@ static void eo_hop(sap_ctx* ctx, void* out, const void* in, int nrhs, int parity
   A.b = Ar(1);
   A.g5_in = 0;
   A.g5_out = 0;
-  A.map = hop_map_for(ctx, false, sizeof(R) == 4, nrhs);
+  A.map = hop_map_for(ctx, false, prec_of<R>(), nrhs);
   launch_hop<R>(A, s);
 }
 

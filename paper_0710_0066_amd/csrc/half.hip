@@ -1,8 +1,12 @@
 // FP16 storage: the Wilson hop on FP16 spinors (per-site FP32 norm) and FP16 links with
-// FP32 arithmetic (Sec. 1, eq. 2; the same operator as dslash.hip), one work-item per
-// (output site, rhs) with workgroups rhs-fastest and renumbered per XCD. Loads and stores
-// are per site: a site's 12 components are scaled by its norm on load, and on store the
-// norm is recomputed as the largest component magnitude.
+// FP32 arithmetic (Sec. 1, eq. 2; the same operator as dslash.hip). Loads and stores are
+// per site: a site's 12 components are scaled by its norm on load, and on store the norm
+// is recomputed as the largest component magnitude.
+//
+// Two work-item mappings: one (output site, rhs) per work-item with workgroups
+// rhs-fastest and renumbered per XCD (SITE), and the x0-marching order of dslash.hip with
+// NR = 1, 2 or 4 rhs per work-item sharing every link load (MARCH1/2/4; the walking and
+// band maps, which exist for FP32/FP64 only, fall back to the marching order).
 #include "internal.h"
 #include "site_io.h"
 
@@ -15,6 +19,86 @@ __device__ __forceinline__ void load_link16(const __half2* U, long long Vhp, int
   for (int e = 0; e < 9; ++e) {
     const float2 v = __half22float2(p[e * TILE]);
     m[e] = {v.x, v.y};
+  }
+}
+
+// all eight hops of output site j of parity p for the rhs r0 .. r0 + nr - 1 (nr <= NR):
+// out = a x + b (g5_out) D (g5_in in), zero on unselected sites; each link is loaded once
+template <int NR>
+__device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long long j, int r0, int nr) {
+  const Geo& g = A.g;
+  const long long Vhp = g.Vhp;
+  const Site s = decode(g, j, p);
+  const bool sel = block_sel(s.x0, A.slb, A.block, A.colour);
+  cx<float> acc[NR][4][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r][a][c] = {0.0f, 0.0f};
+  if (sel) {
+    const bool g5i = A.g5_in != 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+#pragma unroll
+      for (int dir = 0; dir < 2; ++dir) {
+        const bool on = dir == 0 ? !(A.lb && mu == 0 && (s.x0 % A.lb) == A.lb - 1)
+                                 : !(A.lb && mu == 0 && (s.x0 % A.lb) == 0);
+        if (!on) continue;
+        const long long jn = nbr(g, s, j, mu, dir == 0 ? +1 : -1);
+        cx<float> m[9];
+        if (dir == 0) load_link16(A.U, Vhp, mu, p, j, m);
+        else load_link16(A.U, Vhp, mu, 1 - p, jn, m);
+        const bool flip = mu == 0 && (dir == 0 ? s.x0 == g.L0 - 1 : s.x0 == 0);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r >= nr) continue;
+          cx<float> sp[4][3], h[2][3], uh[2][3];
+          const SiteR<h16> in = site_r(A.in, r0 + r, 1 - p, jn, Vhp);
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const cx<float> v = get(in, 3 * a + c);
+              sp[a][c] = (g5i && a >= 2) ? -v : v;
+            }
+          project<float>(mu, dir == 1, sp, h);
+          if (dir == 0) {
+            su3_mul<float>(m, h[0], uh[0]);
+            su3_mul<float>(m, h[1], uh[1]);
+          } else {
+            su3_dag_mul<float>(m, h[0], uh[0]);
+            su3_dag_mul<float>(m, h[1], uh[1]);
+          }
+          if (flip)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+          accum_recon<float>(mu, dir == 1, uh, acc[r]);
+        }
+      }
+    }
+  }
+  const bool with_x = sel && A.x.ptr;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    if (r >= nr) continue;
+    SiteR<h16> xr;
+    if (with_x) xr = site_r(A.x, r0 + r, p, j, Vhp);
+    SiteW<h16> ow = site_w(A.out, r0 + r, p, j, Vhp);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<float> hv = acc[r][a][c];
+        if (A.g5_out && a >= 2) hv = -hv;
+        cx<float> v = A.b * hv;
+        if (with_x) v = v + A.a * get(xr, 3 * a + c);
+        put(ow, 3 * a + c, sel ? v : cx<float>{0.0f, 0.0f});
+      }
+    close(ow);
   }
 }
 
@@ -33,74 +117,60 @@ __global__ __launch_bounds__(256) void hop16_kernel(HopArgs<h16> A) {
     p = A.parity_out;
     j = chunk * 256 + threadIdx.x;
   }
-  const Geo& g = A.g;
-  if (j >= g.Vh) return;
-  const long long Vhp = g.Vhp;
-  const Site s = decode(g, j, p);
-  const bool sel = block_sel(s.x0, A.slb, A.block, A.colour);
-  cx<float> acc[4][3];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[a][c] = {0.0f, 0.0f};
-  if (sel) {
-    const bool g5i = A.g5_in != 0;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-#pragma unroll
-      for (int dir = 0; dir < 2; ++dir) {
-        const bool on = dir == 0 ? !(A.lb && mu == 0 && (s.x0 % A.lb) == A.lb - 1)
-                                 : !(A.lb && mu == 0 && (s.x0 % A.lb) == 0);
-        if (!on) continue;
-        const long long jn = nbr(g, s, j, mu, dir == 0 ? +1 : -1);
-        cx<float> sp[4][3], h[2][3], uh[2][3], m[9];
-        {
-          const SiteR<h16> r = site_r(A.in, rhs, 1 - p, jn, Vhp);
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const cx<float> v = get(r, 3 * a + c);
-              sp[a][c] = (g5i && a >= 2) ? -v : v;
-            }
-        }
-        project<float>(mu, dir == 1, sp, h);
-        if (dir == 0) {
-          load_link16(A.U, Vhp, mu, p, j, m);
-          su3_mul<float>(m, h[0], uh[0]);
-          su3_mul<float>(m, h[1], uh[1]);
-        } else {
-          load_link16(A.U, Vhp, mu, 1 - p, jn, m);
-          su3_dag_mul<float>(m, h[0], uh[0]);
-          su3_dag_mul<float>(m, h[1], uh[1]);
-        }
-        if (mu == 0 && (dir == 0 ? s.x0 == g.L0 - 1 : s.x0 == 0))
-#pragma unroll
-          for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
-        accum_recon<float>(mu, dir == 1, uh, acc);
-      }
-    }
+  if (j >= A.g.Vh) return;
+  hop16_site<1>(A, p, j, rhs, 1);
+}
+
+// x0-marching order (as hop_march_kernel in dslash.hip): the slice-local sites of each
+// parity are cut into 8 contiguous pieces, one per XCD (workgroup id % 8), and each XCD
+// walks its piece slice by slice in increasing x0 with the rhs groups of a chunk back to
+// back. A workgroup is 128 sites of one parity, or 64 sites of each parity (full operator).
+template <bool FULL, int NR>
+__global__ __launch_bounds__(128) void hop16_march_kernel(HopArgs<h16> A, int nck) {
+  const int xcd = blockIdx.x & 7;
+  const long long l = blockIdx.x >> 3;
+  const int ngroups = (A.nrhs + NR - 1) / NR;
+  const long long per_slice = (long long)nck * ngroups;
+  const int x0 = (int)(l / per_slice);
+  const long long rem = l - x0 * per_slice;
+  const int chunk = (int)(rem / ngroups);
+  const int r0 = (int)(rem - (long long)chunk * ngroups) * NR;
+  if (x0 >= A.g.L0) return;
+  const int lo = (int)((long long)A.g.V3h * xcd / 8);
+  const int hi = (int)((long long)A.g.V3h * (xcd + 1) / 8);
+  int p, s;
+  if (FULL) {
+    p = threadIdx.x >> 6;
+    s = lo + chunk * 64 + (threadIdx.x & 63);
+  } else {
+    p = A.parity_out;
+    s = lo + chunk * 128 + threadIdx.x;
   }
-  const bool with_x = sel && A.x.ptr;
-  SiteR<h16> xr;
-  if (with_x) xr = site_r(A.x, rhs, p, j, Vhp);
-  SiteW<h16> ow = site_w(A.out, rhs, p, j, Vhp);
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      cx<float> hv = acc[a][c];
-      if (A.g5_out && a >= 2) hv = -hv;
-      cx<float> r = A.b * hv;
-      if (with_x) r = r + A.a * get(xr, 3 * a + c);
-      put(ow, 3 * a + c, sel ? r : cx<float>{0.0f, 0.0f});
-    }
-  close(ow);
+  if (s >= hi) return;
+  hop16_site<NR>(A, p, (long long)x0 * A.g.V3h + s, r0, min(NR, A.nrhs - r0));
+}
+
+template <int NR> static void launch_march16(const HopArgs<h16>& A, hipStream_t st) {
+  const bool full = A.parity_out < 0;
+  const int piece = (A.g.V3h + 7) / 8;
+  const int per = full ? 64 : 128;
+  const int nck = (piece + per - 1) / per;
+  const long long groups = (A.nrhs + NR - 1) / NR;
+  const dim3 grid((unsigned)(8LL * A.g.L0 * nck * groups)), blk(128);
+  if (full) hipLaunchKernelGGL((hop16_march_kernel<true, NR>), grid, blk, 0, st, A, nck);
+  else hipLaunchKernelGGL((hop16_march_kernel<false, NR>), grid, blk, 0, st, A, nck);
 }
 
 template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t st) {
+  switch (A.map) {
+    case HOP_MAP_MARCH1:
+    case HOP_MAP_WALK1:
+    case HOP_MAP_BAND1: launch_march16<1>(A, st); return;
+    case HOP_MAP_MARCH2:
+    case HOP_MAP_WALK2: launch_march16<2>(A, st); return;
+    case HOP_MAP_MARCH4: launch_march16<4>(A, st); return;
+    default: break;
+  }
   const bool full = A.parity_out < 0;
   const long long per = full ? 128 : 256;
   const long long chunks = (A.g.Vh + per - 1) / per;

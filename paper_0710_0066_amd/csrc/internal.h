@@ -126,14 +126,19 @@ struct sap_ctx {
   void* solver;   // solver workspace (solver.hip)
   void* forces;   // force / trajectory workspace (hmc.hip)
   void* sapws;    // Schwarz-preconditioned BiCGstab workspace (solver.hip), allocated on first use
-  // tuned hop mapping per [full operator?][precision][nrhs] (-1: not tuned)
-  signed char hop_map[2][2][65];
+  // tuned hop mapping per [full operator?][precision (sap_prec)][nrhs] (-1: not tuned)
+  signed char hop_map[2][3][65];
 };
 
+// precision code (sap_prec) of a storage type
+template <class S> constexpr int prec_of() {
+  return std::is_same<S, double>::value ? SAP_F64 : std::is_same<S, float>::value ? SAP_F32 : SAP_F16;
+}
+
 // mapping used for a hop launch: the tuned (or set) one, else SITE for one rhs and LANE4
-// for several
-inline int hop_map_for(const sap_ctx* c, bool full, int prec_is_f32, int nrhs) {
-  const int m = c->hop_map[full ? 1 : 0][prec_is_f32][nrhs > 64 ? 64 : nrhs];
+// for several (LANE4 is SITE for FP16 storage)
+inline int hop_map_for(const sap_ctx* c, bool full, int prec, int nrhs) {
+  const int m = c->hop_map[full ? 1 : 0][prec][nrhs > 64 ? 64 : nrhs];
   if (m >= 0) return m;
   return nrhs <= 1 ? sap::HOP_MAP_SITE : sap::HOP_MAP_LANE4;
 }

@@ -140,13 +140,8 @@ void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int p
   A.b = b;
   A.g5_in = g5i;
   A.g5_out = g5o;
-  A.map = hop_map_for(c, parity_out < 0, std::is_same<R, float>::value, nrhs);
+  A.map = hop_map_for(c, parity_out < 0, prec_of<R>(), nrhs);
   launch_hop<R>(A, st);
-}
-
-// precision code of a storage type (SAP_F64 / SAP_F32 / SAP_F16)
-template <class R> constexpr int prec_code() {
-  return std::is_same<R, double>::value ? SAP_F64 : std::is_same<R, float>::value ? SAP_F32 : SAP_F16;
 }
 
 }  // namespace
@@ -299,7 +294,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     const int calls = ITERS_PER_GRAPH / per_call;
     hipGraphExec_t exec = nullptr;
     for (auto& g : w->graphs)
-      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.prec == prec_code<R>() && g.method == method &&
+      if (g.nrhs == nrhs && g.lb == lb && g.sel == colour && g.prec == prec_of<R>() && g.method == method &&
           g.rho == rho)
         exec = g.exec;
     if (!exec) {
@@ -312,7 +307,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
         }
       }
       (void)hipGetLastError();
-      if (exec) w->graphs.push_back({nrhs, lb, colour, prec_code<R>(), method, rho, exec});
+      if (exec) w->graphs.push_back({nrhs, lb, colour, prec_of<R>(), method, rho, exec});
     }
     for (;;) {
       SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_flags, w->flags, 12, hipMemcpyDeviceToHost, st));
@@ -366,21 +361,22 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
 template <class R>
 static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_out) {
   SolverWS* w = ws_of(c);
-  typedef typename vec2<R>::type V2;
+  typedef typename arith<R>::type Ar;
   const long long Vhp = c->Vhp;
+  const bool f16 = std::is_same<R, h16>::value;
   HopArgs<R> A;
-  A.out = {(V2*)w->ax, 24 * Vhp, 12 * Vhp};
-  A.in = {(V2*)w->r64, 24 * Vhp, 12 * Vhp};
-  A.x = full ? A.in : Field<R>{nullptr, 0, 0};
-  A.U = (const V2*)(sizeof(R) == 8 ? (const void*)c->U64 : (const void*)c->U32);
+  A.out = full_field<R>(w->ax, Vhp);
+  A.in = full_field<R>(w->r64, Vhp);
+  A.x = full ? A.in : Field<R>{nullptr, 0, 0, 0};
+  A.U = gauge_of<R>(c);
   A.g = c->g;
   A.nrhs = nrhs;
   A.parity_out = full ? -1 : 0;
   A.lb = A.slb = 0;
   A.colour = 0;
   A.block = -1;
-  A.a = R(1);
-  A.b = R(-c->geom.kappa);
+  A.a = Ar(1);
+  A.b = Ar(-c->geom.kappa);
   A.g5_in = A.g5_out = 0;
   hipEvent_t e0, e1;
   SAP_HIP_CHECK(c, hipEventCreate(&e0));
@@ -392,7 +388,10 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
                                (m >= HOP_SWEEP && m != HOP_MAP_MARCH1 && m != HOP_MAP_WALK1 &&
                                 m != HOP_MAP_BAND1);
     const bool half_only = m == HOP_MAP_STREAM || m >= HOP_MAP_WALK1;
-    if ((full && half_only) || (nrhs == 1 && one_rhs_alias)) {
+    // FP16 storage has the site and marching kernels only
+    const bool f16_alias = f16 && m != HOP_MAP_SITE && m != HOP_MAP_MARCH1 && m != HOP_MAP_MARCH2 &&
+                           m != HOP_MAP_MARCH4;
+    if ((full && half_only) || (nrhs == 1 && one_rhs_alias) || f16_alias) {
       // the streaming, walking and band kernels exist for half hops only (the full
       // operator runs the walking and band maps as MARCH1 / MARCH2); with one rhs the
       // grouped and sweep orders coincide with SITE, MARCH2 / MARCH4 with MARCH1 and
@@ -416,7 +415,7 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->hop_map[full ? 1 : 0][sizeof(R) == 4 ? 1 : 0][nrhs] = (signed char)best;
+  c->hop_map[full ? 1 : 0][prec_of<R>()][nrhs] = (signed char)best;
   return SAP_OK;
 }
 
@@ -435,6 +434,8 @@ extern "C" int sap_tune(sap_ctx* c, int nrhs, float* us_out, void* stream) {
   if ((rc = tune_one<float>(c, true, nrhs, st, us_out ? us_out + 1 * HOP_NMAP : nullptr))) return rc;
   if ((rc = tune_one<double>(c, false, nrhs, st, us_out ? us_out + 2 * HOP_NMAP : nullptr))) return rc;
   if ((rc = tune_one<float>(c, false, nrhs, st, us_out ? us_out + 3 * HOP_NMAP : nullptr))) return rc;
+  if ((rc = tune_one<h16>(c, true, nrhs, st, us_out ? us_out + 4 * HOP_NMAP : nullptr))) return rc;
+  if ((rc = tune_one<h16>(c, false, nrhs, st, us_out ? us_out + 5 * HOP_NMAP : nullptr))) return rc;
   return SAP_OK;
 }
 
@@ -443,9 +444,9 @@ extern "C" int sap_set_hop_map(sap_ctx* c, int full, sap_prec prec, int nrhs, in
   if (nrhs < 1 || nrhs > 64) return sap_fail(c, SAP_E_ARG, "nrhs must be in [1, 64]");
   if (map < -1 || map >= HOP_NMAP) return sap_fail(c, SAP_E_ARG, "unknown mapping");
   if (full && map == HOP_MAP_STREAM) return sap_fail(c, SAP_E_ARG, "the streaming mapping is for the even-odd hop only");
-  if (prec != SAP_F64 && prec != SAP_F32) return sap_fail(c, SAP_E_ARG, "unknown precision");
+  if (prec != SAP_F64 && prec != SAP_F32 && prec != SAP_F16) return sap_fail(c, SAP_E_ARG, "unknown precision");
   if (c->solver) drop_graphs(ws_of(c));
-  c->hop_map[full ? 1 : 0][prec == SAP_F32 ? 1 : 0][nrhs] = (signed char)map;
+  c->hop_map[full ? 1 : 0][prec][nrhs] = (signed char)map;
   return SAP_OK;
 }
 

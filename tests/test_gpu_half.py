@@ -199,44 +199,90 @@ def test_f16_links_follow_gauge_updates(gu):
     assert _err_vs_input(got, dirac.apply_M(U1, psi, k), psi) <= F16_TOL
 
 
-def test_f16_16x16x16x32_operator_error_and_solves(gu):
-    """The 16^3x32 workload (kappa = 0.1575) in FP16 storage: apply_M and apply_W1 against
-    the FP64 oracle on every element, and full and block solves whose inner iterations
-    run on FP16 fields, to a 1e-10 residual recomputed by the oracle; the FP16-inner
-    solution is compared with the FP64-inner one. The errors are printed."""
+F32_TOL = 64 * 2.0 ** -24      # the same bound with FP32 rounding, plus FP32 accumulation
+
+
+@pytest.mark.parametrize("prec_name", ["f32", "f16"])
+def test_precision_16x16x16x32_operator_error_and_solves(gu, prec_name):
+    """The 16^3x32 workload (kappa = 0.1575) in FP32 and FP16 storage: apply_M and apply_W1
+    against the FP64 oracle on every element, and full and block solves whose inner
+    iterations run at that storage precision, to a 1e-10 residual recomputed by the
+    oracle; the reduced-precision solution is compared with the FP64-inner one. The errors
+    are printed."""
     import paper_0710_0066_amd as sap
-    cfg = synth.CONFIGS["plain_16x16x16x32"]
+    prec = {"f32": sap.SAP_F32, "f16": sap.SAP_F16}[prec_name]
+    tol = {"f32": F32_TOL, "f16": F16_TOL}[prec_name]
+    itol = {"f32": 1e-5, "f16": 1e-2}[prec_name]
+    cfg = synth.CONFIGS["precision_16x16x16x32"]
     L, k, l0 = cfg["L"], cfg["kappa"], cfg["l0"]
-    print("f16 16^3x32", flush=True)
+    print(f"{prec_name} 16^3x32", flush=True)
     U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
     psi = synth.gaussian_spinor(L, cfg["seed_src"])
     ctx = gu.make_ctx(L, l0, k, U, cfg["l0_sub"], max_rhs=1)
-    fin = gu.to_sap(ctx, psi, 1, sap.SAP_F16)
-    fout = ctx.new_field(1, sap.SAP_F16)
-    sap.apply_M(ctx, fout, fin, 1, sap.SAP_F16)
-    eM = _err_vs_input(gu.from_sap(ctx, fout, 1, psi.shape, sap.SAP_F16), dirac.apply_M(U, psi, k), psi)
-    sap.apply_W1_block(ctx, fout, fin, 1, 1, -1, sap.SAP_ALL, sap.SAP_F16)
-    eW = _err_vs_input(gu.from_sap(ctx, fout, 1, psi.shape, sap.SAP_F16), dirac.apply_W(U, psi, k, l0), psi)
-    print(f"  apply_M f16 max error / max|psi| = {eM:.2e}, apply_W1 {eW:.2e}", flush=True)
-    assert eM <= F16_TOL and eW <= F16_TOL
+    fin = gu.to_sap(ctx, psi, 1, prec)
+    fout = ctx.new_field(1, prec)
+    sap.apply_M(ctx, fout, fin, 1, prec)
+    eM = _err_vs_input(gu.from_sap(ctx, fout, 1, psi.shape, prec), dirac.apply_M(U, psi, k), psi)
+    sap.apply_W1_block(ctx, fout, fin, 1, 1, -1, sap.SAP_ALL, prec)
+    eW = _err_vs_input(gu.from_sap(ctx, fout, 1, psi.shape, prec), dirac.apply_W(U, psi, k, l0), psi)
+    print(f"  apply_M {prec_name} max error / max|psi| = {eM:.2e}, apply_W1 {eW:.2e}", flush=True)
+    assert eM <= tol and eW <= tol
     fb = gu.to_sap(ctx, psi, 1)
     x = {}
-    for name, prec, itol in (("f64", sap.SAP_F64, 0.0), ("f16", sap.SAP_F16, 1e-2)):
+    for name, p, it in (("f64", sap.SAP_F64, 0.0), (prec_name, prec, itol)):
         fx = ctx.new_field(1)
-        o = sap.solve_opts(tol=1e-10, max_iter=500000, inner_prec=prec, inner_tol=itol, max_outer=200)
+        o = sap.solve_opts(tol=1e-10, max_iter=500000, inner_prec=p, inner_tol=it, max_outer=200)
         info = sap.solve_full(ctx, fx, fb, 1, o)
         x[name] = gu.from_sap(ctx, fx, 1, psi.shape)
         res = float(_relres(U, x[name], psi, k))
         print(f"  solve_full inner={name}: iters={info[0].iters} outer={info[0].outer} res={res:.2e}", flush=True)
         assert res <= 1e-10
-    d = float(np.linalg.norm(x["f16"] - x["f64"]) / np.linalg.norm(x["f64"]))
-    print(f"  |x_f16 - x_f64| / |x_f64| = {d:.2e}", flush=True)
+    d = float(np.linalg.norm(x[prec_name] - x["f64"]) / np.linalg.norm(x["f64"]))
+    print(f"  |x_{prec_name} - x_f64| / |x_f64| = {d:.2e}", flush=True)
     assert d <= 1e-7
     fx = ctx.new_field(1)
-    o = sap.solve_opts(tol=1e-10, max_iter=500000, inner_prec=sap.SAP_F16, inner_tol=1e-2, max_outer=80)
+    o = sap.solve_opts(tol=1e-10, max_iter=500000, inner_prec=prec, inner_tol=itol, max_outer=80)
     info = sap.solve_blocks(ctx, fx, fb, 1, 1, sap.SAP_ALL, o)
     xb = gu.from_sap(ctx, fx, 1, psi.shape)
     res = float(np.max(_relres(U, xb, psi, k, l0)))
-    print(f"  solve_blocks inner=f16: max iters={max(i.iters for i in info)} "
+    print(f"  solve_blocks inner={prec_name}: max iters={max(i.iters for i in info)} "
           f"outer={max(i.outer for i in info)} res={res:.2e}", flush=True)
     assert res <= 1e-10
+
+
+@pytest.mark.parametrize("hop_map", [0, 11, 12, 13, 14])
+@pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15)])
+def test_every_f16_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
+    """The FP16 hop with each of its work-item mappings (site, x0-marching with 1 / 2 / 4
+    rhs per work-item; walk1 runs as march1) gives the oracle's D_eo and M with 1 and 5
+    right-hand sides, and the block solves that use the gamma_5-folded, block-restricted
+    and colour-selected forms reach a 1e-10 residual."""
+    import paper_0710_0066_amd as sap
+    print(f"f16 hop map {hop_map} L={L}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1121)
+    par = lattice.parity(L)
+    for nrhs in (1, 5):
+        psi = synth.gaussian_spinor(L, 2121 + nrhs, nrhs=nrhs)
+        ctx = gu.make_ctx(L, l0, k, U, l0_sub, max_rhs=nrhs)
+        sap.sap_set_hop_map(ctx, 0, sap.SAP_F16, nrhs, hop_map)
+        sap.sap_set_hop_map(ctx, 1, sap.SAP_F16, nrhs, hop_map)
+        fin = gu.to_sap(ctx, psi, nrhs, sap.SAP_F16)
+        fout = ctx.new_field(nrhs, sap.SAP_F16)
+        for parity in (0, 1):
+            m_out = lattice.site_mask(L, par == parity)
+            ref = dirac.hop(U, psi * lattice.site_mask(L, par != parity)) * m_out
+            sap.apply_Dslash_eo(ctx, fout, fin, nrhs, parity, sap.SAP_F16)
+            got = gu.from_sap(ctx, fout, nrhs, psi.shape, sap.SAP_F16) * m_out
+            assert _err_vs_input(got, ref, psi) <= F16_TOL / 0.16, (nrhs, parity)
+        sap.apply_M(ctx, fout, fin, nrhs, sap.SAP_F16)
+        got = gu.from_sap(ctx, fout, nrhs, psi.shape, sap.SAP_F16)
+        assert _err_vs_input(got, dirac.apply_M(U, psi, k), psi) <= F16_TOL, nrhs
+        fb = gu.to_sap(ctx, psi, nrhs)
+        fx = ctx.new_field(nrhs)
+        opts = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F16, inner_tol=1e-2, max_outer=80)
+        cases = [(1, l0, sap.SAP_BLACK, "black")] + ([(2, l0_sub, sap.SAP_ALL, "all")] if l0_sub else [])
+        for level, lb, colour, cname in cases:
+            sap.solve_blocks(ctx, fx, fb, nrhs, level, colour, opts)
+            x = gu.from_sap(ctx, fx, nrhs, psi.shape)
+            msk = lattice.site_mask(L, lattice.colour_x0_mask(L, lb, cname))
+            assert np.all(_relres(U, x, psi, k, lb, msk) <= 1e-10), (nrhs, level)
