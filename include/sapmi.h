@@ -93,15 +93,19 @@ typedef enum {
   SAP_SAP_BICGSTAB = 3  /* solve_full only: FP64 BiCGstab on M, right-preconditioned by
                          * sap_ncy cycles of the Schwarz alternating procedure on the
                          * level-1 blocks (black, then white); the block systems are solved
-                         * with CG at inner_prec to the relative residual inner_tol */
+                         * with CG at inner_prec to the relative residual inner_tol
+                         * (raised to 1e-5 for SAP_F32 and 1e-2 for SAP_F16) */
 } sap_method;
 
 typedef struct {
   double tol;        /* stop when ||b - A x|| / ||b|| <= tol, recomputed in FP64 */
   int max_iter;      /* cap on inner iterations summed over outer cycles (SAP_SAP_BICGSTAB:
                       * on BiCGstab iterations) */
-  sap_prec inner_prec; /* precision of the inner Krylov solve */
-  double inner_tol;  /* relative reduction asked of each inner solve (defect correction) */
+  sap_prec inner_prec; /* storage precision of the inner Krylov solve (FP32 arithmetic for
+                        * SAP_F32 and SAP_F16) */
+  double inner_tol;  /* relative reduction asked of each inner solve (defect correction);
+                      * must lie in (0, 1) for SAP_F32 and SAP_F16 (about 1e-5 and 1e-2
+                      * suit their rounding); <= 0 with SAP_F64 means tol */
   int max_outer;     /* cap on FP64 defect-correction cycles (SAP_SAP_BICGSTAB: restarts) */
   sap_method method; /* inner method; 0 (SAP_CG) is the default */
   int sap_ncy;       /* SAP_SAP_BICGSTAB: Schwarz cycles per preconditioner application */
@@ -192,7 +196,7 @@ size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs);
 size_t sap_momenta_bytes(const sap_ctx* ctx);
 
 /* Load the gauge field from the canonical layout (device, complex128) into the
- * context's FP64 and FP32 copies. */
+ * context's FP64, FP32 and FP16 copies. */
 int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream);
 /* Copy the context's FP64 gauge field back to the canonical layout. */
 int sap_get_gauge(sap_ctx* ctx, double* U, void* stream);
@@ -209,8 +213,9 @@ int sap_unpack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream
 /* ---- operators ---------------------------------------------------------------- */
 
 /* out = M in (Sec. 1, eq. 2) for nrhs fields in the sap layout at precision prec
- * (FP64: float64 arithmetic; FP32: float32 storage and arithmetic). out and in must
- * not overlap. */
+ * (FP64: float64 arithmetic; FP32: float32 storage and arithmetic; FP16: FP16 storage
+ * with per-site norms and FP16 links, float32 arithmetic, each output site rounded once).
+ * out and in must not overlap. */
 int apply_M(sap_ctx* ctx, void* out, const void* in, int nrhs, sap_prec prec, void* stream);
 
 /* out = W_level in: M with every hop between different x0 blocks of the given level
