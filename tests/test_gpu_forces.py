@@ -227,6 +227,36 @@ def test_hmc_trajectory_matches_oracle(gu):
     assert info2.accepted == 0 and torch.equal(fU2, gu.dev(U))
 
 
+@pytest.mark.parametrize("inner", ["f32", "f16"])
+def test_hmc_trajectory_reduced_precision_solves_match_oracle(gu, inner):
+    """The trajectory of test_hmc_trajectory_matches_oracle with every force and action
+    solve run as FP32 or FP16 inner iterations inside the FP64 defect correction (to
+    1e-12): dH and the final links agree with the FP64 oracle to the accuracy the solver
+    tolerance leaves."""
+    import paper_0710_0066_amd as sap
+    L, l0, k, beta, tau = (8, 4, 2, 4), 2, 0.15, 5.6, 0.5
+    print(f"hmc {inner} inner solves vs oracle", flush=True)
+    U = synth.gauge_field(L, 0.3, 77)
+    p0, xi1, xi2 = _hmc_inputs(L, 78)
+    mk = lambda V: schwarz.Solvers(V, k, l0, tol=1e-13)
+    phi1 = dirac.apply_W(U, xi1, k, l0)
+    chi = schwarz.heat_bath(U, xi2, k, l0, mk(U))
+    lev = hmc.schwarz_two_level(phi1, chi, k, beta, l0, 3, 2, mk)
+    U_ref, acc_ref, dH_ref, H0_ref, H1_ref = hmc.trajectory(lev, U, p0, tau, u_metropolis=0.0)
+    ctx = gu.make_ctx(L, l0, k, U)
+    fU = gu.dev(U).clone()
+    prec = {"f32": sap.SAP_F32, "f16": sap.SAP_F16}[inner]
+    o = sap.solve_opts(tol=1e-12, max_iter=500000, inner_prec=prec, inner_tol={"f32": 1e-5, "f16": 1e-2}[inner],
+                       max_outer=200)
+    prm = sap.hmc_params(beta, tau, 3, 2, _mom_to_sap(ctx, gu, p0), gu.dev(xi1), gu.dev(xi2), 0.0, o, o)
+    info = sap.hmc_trajectory(ctx, fU, prm)
+    print(f"  dH gpu {info.dH:.12e} oracle {dH_ref:.12e}", flush=True)
+    assert info.accepted == 1 and acc_ref
+    assert abs(info.H0 - H0_ref) <= 1e-8 * abs(H0_ref)
+    assert abs(info.dH - dH_ref) <= 1e-6 * max(1.0, abs(dH_ref))
+    assert np.max(np.abs(fU.cpu().numpy().reshape(U.shape) - U_ref)) <= 1e-8
+
+
 def test_hmc_trajectory_16x16x16x32(gu):
     """One tau = 1 trajectory on the 16^3x32 workload (beta = 5.6, kappa = 0.1575), two
     Sexton-Weingarten levels (8 pseudo-fermion steps, 4 gauge steps each), mixed-precision
