@@ -151,7 +151,7 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=5):
       mixed_batched_by_method  the mixed batched solve with the inner CG replaced by
                           BiCGstab and by the geometric series (Sec. 3's block-term solver);
       mixed_f16_storage_by_method  inner CG / BiCGstab on FP16-storage fields (FP32
-                          arithmetic) to a relative residual of 1e-2 per correction."""
+                          arithmetic) to a relative residual of 2e-3 per correction."""
     import numpy as np
     import synth
     nrhs = cfg["nrhs"]
@@ -203,7 +203,7 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=5):
     half = {}
     for name, meth in (("cg", sap.SAP_CG), ("bicgstab", sap.SAP_BICGSTAB)):
         print(f"[bench] block solves: FP16-storage inner {name}", file=sys.stderr, flush=True)
-        o = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F16, inner_tol=1e-2, method=meth)
+        o = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F16, inner_tol=2e-3, method=meth)
         try:
             half[name] = run(o, "batched", repeats)
         except sap.SapError as e:
@@ -294,7 +294,7 @@ def main():
 
     if args.only_solve:        # one batched block solve of both levels, for profiler runs
         meth, p = args.only_solve.split("_")
-        o = sap.solve_opts(tol=1e-10, inner_prec=PREC[p], inner_tol={"f64": 0.0, "f32": 1e-5, "f16": 1e-2}[p],
+        o = sap.solve_opts(tol=1e-10, inner_prec=PREC[p], inner_tol={"f64": 0.0, "f32": 1e-5, "f16": 2e-3}[p],
                            method={"cg": sap.SAP_CG, "bicgstab": sap.SAP_BICGSTAB}[meth])
         sap.sap_tune(ctx, nrhs)
         fb = ctx.new_field(nrhs)

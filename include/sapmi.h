@@ -94,7 +94,7 @@ typedef enum {
                          * sap_ncy cycles of the Schwarz alternating procedure on the
                          * level-1 blocks (black, then white); the block systems are solved
                          * with CG at inner_prec to the relative residual inner_tol
-                         * (raised to 1e-5 for SAP_F32 and 1e-2 for SAP_F16) */
+                         * (raised to 1e-5 for SAP_F32 and 2e-3 for SAP_F16) */
 } sap_method;
 
 typedef struct {
@@ -104,7 +104,7 @@ typedef struct {
   sap_prec inner_prec; /* storage precision of the inner Krylov solve (FP32 arithmetic for
                         * SAP_F32 and SAP_F16) */
   double inner_tol;  /* relative reduction asked of each inner solve (defect correction);
-                      * must lie in (0, 1) for SAP_F32 and SAP_F16 (about 1e-5 and 1e-2
+                      * must lie in (0, 1) for SAP_F32 and SAP_F16 (about 1e-5 and 2e-3
                       * suit their rounding); <= 0 with SAP_F64 means tol */
   int max_outer;     /* cap on FP64 defect-correction cycles (SAP_SAP_BICGSTAB: restarts) */
   sap_method method; /* inner method; 0 (SAP_CG) is the default */

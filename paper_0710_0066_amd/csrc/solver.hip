@@ -576,7 +576,7 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
   sap_solve_opts bo = *o;
   bo.tol = o->inner_tol;
   bo.inner_tol = o->inner_prec == SAP_F32   ? std::max(o->inner_tol, 1e-5)
-                 : o->inner_prec == SAP_F16 ? std::max(o->inner_tol, 1e-2)
+                 : o->inner_prec == SAP_F16 ? std::max(o->inner_tol, 2e-3)
                                             : o->inner_tol;
   bo.max_outer = 40;
   bo.max_iter = 1 << 30;
