@@ -163,6 +163,40 @@ def test_apply_M_and_W_full_size(gu, name):
         assert gu.rel_err(gu.from_sap(ctx, fout, 1, psi.shape, prec), refW) <= tol
 
 
+def test_benchmark_launch_24x24x24x48_12rhs(gu):
+    """The benchmark's own launches: the even-odd hop on all 12 right-hand sides of the
+    24^3x48 workload after sap_tune, in FP64, FP32 and FP16 storage, both output parities.
+    Right-hand sides 0, 5 and 11 (the first, a middle and the last rhs group of every
+    mapping) are compared with the oracle's hop on every site; for the others, the rhs
+    must differ from each other as their sources do (no group reads another's input)."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["batched_24x24x24x48"]
+    L, k, l0, nrhs = cfg["L"], cfg["kappa"], cfg["l0"], cfg["nrhs"]
+    print("benchmark launch 24^3x48, 12 rhs", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    psi = synth.gaussian_spinor(L, cfg["seed_src"], nrhs=nrhs)
+    ctx = gu.make_ctx(L, l0, k, U, cfg["l0_sub"], max_rhs=nrhs)
+    tuned = sap.sap_tune(ctx, nrhs)
+    print(f"  tuned even-odd maps: f32 {min(tuned['eo_f32'], key=tuned['eo_f32'].get)}, "
+          f"f64 {min(tuned['eo_f64'], key=tuned['eo_f64'].get)}, f16 {min(tuned['eo_f16'], key=tuned['eo_f16'].get)}",
+          flush=True)
+    check = (0, 5, nrhs - 1)
+    ref = {r: dirac.hop(U, psi[r]) for r in check}
+    par = lattice.parity(L)
+    f16_tol = 16 * 2.0 ** -12 / 0.16
+    for prec, tol in [(sap.SAP_F64, F64_TOL), (sap.SAP_F32, F32_TOL), (sap.SAP_F16, f16_tol)]:
+        fin = gu.to_sap(ctx, psi, nrhs, prec)
+        fout = ctx.new_field(nrhs, prec)
+        for parity in (0, 1):
+            sap.apply_Dslash_eo(ctx, fout, fin, nrhs, parity, prec)
+        got = gu.from_sap(ctx, fout, nrhs, psi.shape, prec)
+        for r in check:
+            err = float(np.max(np.abs(got[r] - ref[r])) / np.max(np.abs(psi[r] if prec == sap.SAP_F16 else ref[r])))
+            assert err <= tol, (prec, r, err)
+        assert all(not np.allclose(got[r], got[r + 1]) for r in range(nrhs - 1))
+        del fin, fout, got
+
+
 def test_pack_unpack_roundtrip(gu):
     import paper_0710_0066_amd as sap
     L = (6, 2, 4, 6)
