@@ -63,6 +63,8 @@ def parse():
                     help="with --only-dslash: force this hop mapping (HOP_MAP_*) instead of the tuned one")
     ap.add_argument("--skip-solve", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-extended", action="store_true",
+                    help="also time the oracle's apply_M / apply_W1 / CGLS iterations on the host")
     ap.add_argument("--only-dslash", action="store_true",
                     help="time only the Dslash loop (for profiler runs)")
     ap.add_argument("--only-solve", choices=["cg_f32", "bicgstab_f32", "cg_f16", "bicgstab_f16", "cg_f64"],
@@ -91,6 +93,52 @@ def cpu_baseline(U, psi, V, budget_s=20.0):
             "kind": "oracle",
             "sample": f"{n} applications of the even-odd hop (FP64 numpy oracle, 1 rhs) on 24^3x48, "
                       f"{per:.2f} s each; GB/s over the same algorithmic bytes (768 B per site)"}
+
+
+def cpu_extended():
+    """Further timings of the FP64 oracle on the host cores (opt-in, about a minute):
+    apply_M and apply_W1 on the 16^3x32 and 24^3x48 workloads, and the cost of one CGLS
+    iteration of the even-odd solve on 16^3x32 for one 16^3x4 block and for the full
+    lattice (10 iterations timed, less the set-up; whole solves take 100-200 iterations).
+    The oracle works on full-lattice arrays, so its block iteration costs full-lattice
+    operator applications."""
+    import numpy as np
+    import synth
+    from oracle import dirac, lattice, solvers
+
+    def timed(fn):
+        c0, w0 = time.process_time(), time.perf_counter()
+        fn()
+        w = time.perf_counter() - w0
+        return w, max(1, round((time.process_time() - c0) / w))
+
+    res = {"host_cpus": os.cpu_count()}
+    for name in ("plain_16x16x16x32", "batched_24x24x24x48"):
+        cfg = synth.CONFIGS[name]
+        L, k, l0 = cfg["L"], cfg["kappa"], cfg["l0"]
+        U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+        psi = synth.gaussian_spinor(L, cfg["seed_src"])
+        tm, cm = timed(lambda: dirac.apply_M(U, psi, k))
+        tw, cw = timed(lambda: dirac.apply_W(U, psi, k, l0))
+        res[name] = {"apply_M_seconds": round(tm, 3), "apply_W1_seconds": round(tw, 3), "cores": max(cm, cw)}
+        print(f"[bench] oracle {name}: apply_M {tm:.2f} s, apply_W1 {tw:.2f} s", file=sys.stderr, flush=True)
+        if name == "plain_16x16x16x32":
+            even = dirac.parity_masks(L)[0]
+
+            def per_iteration(lb, src):
+                A = lambda v: dirac.apply_Mhat(U, v, k, lb, False)
+                Ad = lambda v: dirac.apply_Mhat(U, v, k, lb, True)
+                t10, c = timed(lambda: solvers.cgls(A, Ad, even * src, tol=1e-30, maxiter=10, max_restarts=0))
+                t0, _ = timed(lambda: solvers.cgls(A, Ad, even * src, tol=1e-30, maxiter=0, max_restarts=0))
+                return (t10 - t0) / 10, c
+
+            tb, cb = per_iteration(l0, psi * lattice.site_mask(L, lattice.single_block_mask(L, l0, 0)))
+            tf, cf = per_iteration(None, psi)
+            res[name].update({"block_cg_seconds_per_iteration": round(tb, 3),
+                              "full_cg_seconds_per_iteration": round(tf, 3), "solve_cores": max(cb, cf)})
+            print(f"[bench] oracle {name}: CGLS iteration, one block {tb:.2f} s, full {tf:.2f} s",
+                  file=sys.stderr, flush=True)
+    return res
 
 
 def hbm_probe(torch, gib=2):
@@ -367,6 +415,9 @@ def main():
     if not args.skip_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(U, psi[0], V)
+        if args.cpu_extended:
+            print("[bench] timing further oracle operations", file=sys.stderr, flush=True)
+            result["cpu_extended"] = cpu_extended()
     print(json.dumps(result), flush=True)
 
 
