@@ -177,12 +177,14 @@ def solve_eo_bicgstab(U, b, kappa, l0=None, tol=1e-12, maxiter=20000):
     return x, its, res
 
 
-def sap_precond(U, r, kappa, l0, ncy, block_tol=1e-12):
+def sap_precond(U, r, kappa, l0, ncy, block_tol=1e-12, block_terms=0):
     """ncy cycles of the multiplicative Schwarz alternating procedure for M x = r on the x0
     blocks of length l0: for the black blocks, then the white blocks, add the solution of
     the block system W_l0 y = (r - M x) restricted to the blocks of that colour (W_l0 is
     block diagonal, so y stays on those blocks). Block systems: ``solve_eo`` to
-    block_tol."""
+    block_tol, or, with block_terms = N > 0, the first N terms of their even-odd geometric
+    series (``geometric_series`` with no stopping test), which makes every cycle a fixed
+    linear map of r."""
     from .lattice import site_mask, colour_x0_mask
     L = U.shape[:4]
     x = np.zeros_like(r)
@@ -190,16 +192,19 @@ def sap_precond(U, r, kappa, l0, ncy, block_tol=1e-12):
         for colour in ("black", "white"):
             m = site_mask(L, colour_x0_mask(L, l0, colour))
             rho = (r - apply_op(U, x, kappa)) * m
-            y, _, _ = solve_eo(U, rho, kappa, l0, tol=block_tol)
+            if block_terms > 0:
+                y, _, _ = geometric_series(U, rho, kappa, l0, tol=0.0, maxiter=block_terms)
+            else:
+                y, _, _ = solve_eo(U, rho, kappa, l0, tol=block_tol)
             x = x + y
     return x
 
 
-def solve_sap_bicgstab(U, b, kappa, l0, ncy=1, tol=1e-12, block_tol=1e-12, maxiter=2000):
+def solve_sap_bicgstab(U, b, kappa, l0, ncy=1, tol=1e-12, block_tol=1e-12, maxiter=2000, block_terms=0):
     """M x = b by BiCGstab on the full lattice, right-preconditioned by ncy Schwarz
     cycles (``sap_precond``) whose block systems are solved in the even-odd form."""
     A = lambda v: apply_op(U, v, kappa)
-    K = lambda v: sap_precond(U, v, kappa, l0, ncy, block_tol)
+    K = lambda v: sap_precond(U, v, kappa, l0, ncy, block_tol, block_terms)
     return bicgstab(A, b, tol=tol, maxiter=maxiter, K=K)
 
 

@@ -130,3 +130,27 @@ def test_geometric_series_matches_dense_lu_on_blocks():
     x, n, res = solvers.geometric_series(U, b, k, 2, tol=1e-12)
     assert res <= 1e-12 and n > 1
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= np.linalg.cond(A) * 1e-12
+
+
+def test_sap_with_series_block_solves_is_linear_and_converges():
+    """Schwarz cycles whose block systems take N terms of the even-odd geometric series:
+    (i) the preconditioner is a linear map (K(a u + v) = a K(u) + K(v) to rounding), which
+    an adaptive block solve is not; (ii) as N grows the block solves approach the exact
+    ones (the series converges at kappa = 0.12), so K approaches the exact-block cycles;
+    (iii) BiCGstab right-preconditioned by it reaches the dense solution."""
+    L, l0, k = (8, 2, 2, 4), 2, 0.12
+    U = synth.gauge_field(L, 0.5, 15)
+    u = synth.gaussian_spinor(L, 16)
+    v = synth.gaussian_spinor(L, 17)
+    a = 0.7 - 1.3j
+    K = lambda w, n: solvers.sap_precond(U, w, k, l0, 2, block_terms=n)
+    lhs, rhs = K(a * u + v, 6), a * K(u, 6) + K(v, 6)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-13 * np.max(np.abs(rhs))
+    exact = solvers.sap_precond(U, u, k, l0, 2, block_tol=1e-14)
+    errs = [np.linalg.norm(K(u, n) - exact) / np.linalg.norm(exact) for n in (2, 8, 32, 128)]
+    assert all(b < a_ for a_, b in zip(errs, errs[1:])), errs
+    assert errs[-1] <= 1e-10, errs
+    ref = np.linalg.solve(dirac.dense_matrix(U, k), u.reshape(-1)).reshape(u.shape)
+    x, its, res = solvers.solve_sap_bicgstab(U, u, k, l0, ncy=2, tol=1e-12, block_terms=6)
+    assert res <= 1e-12
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1e-10
