@@ -94,7 +94,8 @@ typedef enum {
                          * sap_ncy cycles of the Schwarz alternating procedure on the
                          * level-1 blocks (black, then white); the block systems are solved
                          * with CG at inner_prec to the relative residual inner_tol
-                         * (raised to 1e-5 for SAP_F32 and 2e-3 for SAP_F16) */
+                         * (raised to 1e-5 for SAP_F32 and 2e-3 for SAP_F16), or by
+                         * sap_block_terms terms of their geometric series */
 } sap_method;
 
 typedef struct {
@@ -109,6 +110,10 @@ typedef struct {
   int max_outer;     /* cap on FP64 defect-correction cycles (SAP_SAP_BICGSTAB: restarts) */
   sap_method method; /* inner method; 0 (SAP_CG) is the default */
   int sap_ncy;       /* SAP_SAP_BICGSTAB: Schwarz cycles per preconditioner application */
+  int sap_block_terms; /* SAP_SAP_BICGSTAB: 0 solves every block system to inner_tol; N > 0
+                        * applies the first N terms of the block systems' even-odd
+                        * geometric series in FP64 instead (a fixed linear approximation
+                        * of the block inverse; inner_prec and inner_tol are then unused) */
 } sap_solve_opts;
 
 typedef struct {

@@ -44,7 +44,7 @@ class sap_geom(ctypes.Structure):
 class sap_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("inner_prec", ctypes.c_int),
                 ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("method", ctypes.c_int),
-                ("sap_ncy", ctypes.c_int)]
+                ("sap_ncy", ctypes.c_int), ("sap_block_terms", ctypes.c_int)]
 
 
 class sap_solve_info(ctypes.Structure):
@@ -163,8 +163,8 @@ SAP_CG, SAP_BICGSTAB, SAP_GEOM, SAP_SAP_BICGSTAB = 0, 1, 2, 3
 
 
 def solve_opts(tol=1e-10, max_iter=100000, inner_prec=SAP_F32, inner_tol=1e-5, max_outer=50, method=SAP_CG,
-               sap_ncy=1):
-    return sap_solve_opts(tol, max_iter, inner_prec, inner_tol, max_outer, method, sap_ncy)
+               sap_ncy=1, sap_block_terms=0):
+    return sap_solve_opts(tol, max_iter, inner_prec, inner_tol, max_outer, method, sap_ncy, sap_block_terms)
 
 
 # ---- C entry points with their own names -------------------------------------------

@@ -460,8 +460,12 @@ int sap::check_solve_opts(sap_ctx* c, const sap_solve_opts* o) {
     return sap_fail(c, SAP_E_ARG, "inner_tol must be in (0, 1) for an FP32 or FP16 inner solve");
   if (o->method != SAP_CG && o->method != SAP_BICGSTAB && o->method != SAP_GEOM && o->method != SAP_SAP_BICGSTAB)
     return sap_fail(c, SAP_E_ARG, "unknown method");
-  if (o->method == SAP_SAP_BICGSTAB && (o->sap_ncy < 1 || !(o->inner_tol > 0 && o->inner_tol < 1)))
-    return sap_fail(c, SAP_E_ARG, "SAP_SAP_BICGSTAB needs sap_ncy >= 1 and inner_tol in (0, 1)");
+  if (o->sap_block_terms < 0 || o->sap_block_terms > 100000)
+    return sap_fail(c, SAP_E_ARG, "sap_block_terms must be in [0, 100000]");
+  if (o->method == SAP_SAP_BICGSTAB &&
+      (o->sap_ncy < 1 || !(o->sap_block_terms > 0 || (o->inner_tol > 0 && o->inner_tol < 1))))
+    return sap_fail(c, SAP_E_ARG,
+                    "SAP_SAP_BICGSTAB needs sap_ncy >= 1 and inner_tol in (0, 1) or sap_block_terms > 0");
   return SAP_OK;
 }
 
@@ -478,12 +482,13 @@ int sap::check_solve_opts(sap_ctx* c, const sap_solve_opts* o) {
 struct SapWS {
   int nrhs_cap;
   double2 *r, *r0, *p, *v, *t, *ph, *sh, *kx, *kr, *ky, *mt;
+  double2 *g1, *g2;     // series block solves: b_hat (even half), D_oe y (odd half)
   double *part, *dev3, *coef;
   double *h3, *hcoef;
 };
 
 static void sap_ws_free(SapWS* a) {
-  void* dev[] = {a->r, a->r0, a->p, a->v, a->t, a->ph, a->sh, a->kx, a->kr, a->ky, a->mt, a->part, a->dev3,
+  void* dev[] = {a->r, a->r0, a->p, a->v, a->t, a->ph, a->sh, a->kx, a->kr, a->ky, a->mt, a->g1, a->g2, a->part, a->dev3,
                  a->coef};
   for (void* q : dev)
     if (q) (void)hipFree(q);
@@ -506,7 +511,8 @@ static SapWS* sap_ws(sap_ctx* c) {
   const size_t nsys = 2 * (size_t)n;
   const size_t nchunk = (size_t)((c->Vh + CHUNK - 1) / CHUNK);
   bool ok = true;
-  double2** fields[] = {&a->r, &a->r0, &a->p, &a->v, &a->t, &a->ph, &a->sh, &a->kx, &a->kr, &a->ky, &a->mt};
+  double2** fields[] = {&a->r, &a->r0, &a->p, &a->v, &a->t, &a->ph, &a->sh, &a->kx, &a->kr, &a->ky, &a->mt,
+                        &a->g1, &a->g2};
   for (double2** f : fields) ok = ok && hipMalloc((void**)f, fb) == hipSuccess;
   ok = ok && hipMalloc((void**)&a->part, 3 * nsys * nchunk * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&a->dev3, 3 * nsys * 8) == hipSuccess;
@@ -596,13 +602,33 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
           if ((rc = lin3(a->kr, in, a->mt, nullptr, zero, one, mone, false))) return rc;
           rhs = (const double*)a->kr;
         }
-        int rc = o->inner_prec == SAP_F64
-                     ? solve_impl<double>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st)
-                 : o->inner_prec == SAP_F32
-                     ? solve_impl<float>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st)
-                     : solve_impl<h16>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st);
-        if (rc) return rc;
-        for (auto& e : binfo) block_iters += e.iters;
+        if (o->sap_block_terms > 0) {
+          // y = the first N terms of the even-odd geometric series of W1 y = rhs on the blocks
+          // of this colour (Horner form y_e <- b_hat_e + k^2 D_eo D_oe y_e), then
+          // y_o = rhs_o + k D_oe y_e; every other block of y is set to zero
+          const Field<double> RHS = full_field<double>((void*)rhs, Vhp), Y = full_field<double>(a->ky, Vhp);
+          const Field<double> BH = full_field<double>(a->g1, Vhp), Z = full_field<double>(a->g2, Vhp);
+          const Field<double> NONE64 = {nullptr, 0, 0, 0};
+          const double kap = c->geom.kappa;
+          const int lb = c->geom.l0;
+          hop<double>(c, c->U64, BH, RHS, RHS, 0, nrhs, lb, colour, 1.0, kap, 0, 0, st);
+          hop<double>(c, c->U64, Y, RHS, RHS, 0, nrhs, lb, colour, 1.0, kap, 0, 0, st);
+          for (int n = 1; n < o->sap_block_terms; ++n) {
+            hop<double>(c, c->U64, Z, Y, NONE64, 1, nrhs, lb, colour, 0.0, 1.0, 0, 0, st);
+            hop<double>(c, c->U64, Y, Z, BH, 0, nrhs, lb, colour, 1.0, kap * kap, 0, 0, st);
+          }
+          hop<double>(c, c->U64, Y, Y, RHS, 1, nrhs, lb, colour, 1.0, kap, 0, 0, st);
+          SAP_HIP_CHECK(c, hipGetLastError());
+        } else {
+          int rc = o->inner_prec == SAP_F64
+                       ? solve_impl<double>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st)
+                   : o->inner_prec == SAP_F32
+                       ? solve_impl<float>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st)
+                       : solve_impl<h16>(c, (double*)a->ky, rhs, nrhs, c->geom.l0, colour, &bo, binfo.data(), st);
+          if (rc) return rc;
+          for (auto& e : binfo) block_iters += e.iters;
+        }
+        int rc;
         if ((rc = lin3(a->kx, a->ky, nullptr, nullptr, one, one, zero, false))) return rc;
       }
     SAP_HIP_CHECK(c, hipMemcpyAsync(out, a->kx, fullb, hipMemcpyDeviceToDevice, st));

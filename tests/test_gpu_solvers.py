@@ -313,3 +313,39 @@ def test_solver_methods_16x16x16x32(gu):
                                method=sap.SAP_SAP_BICGSTAB, sap_ncy=2)
         its[m] = run(f"full {m} k=0.14", lambda: sap.solve_full(ctx, fx, fb, 1, o))
     assert its["sap_bicgstab"] < its["bicgstab"] < its["cg"]
+    # Schwarz cycles with N-term series block solves (a fixed linear preconditioner)
+    for n in (4, 8, 16):
+        o = sap.solve_opts(tol=1e-10, max_iter=1000, max_outer=20, method=sap.SAP_SAP_BICGSTAB, sap_ncy=2,
+                           sap_block_terms=n)
+        its[f"sap_series{n}"] = run(f"full sap_bicgstab, {n}-term block series, k=0.14",
+                                    lambda: sap.solve_full(ctx, fx, fb, 1, o))
+    assert its["sap_series16"] < its["bicgstab"]
+
+
+@pytest.mark.parametrize("L,l0,k", [((4, 4, 4, 4), 2, 0.12), ((8, 2, 4, 6), 2, 0.14)])
+@pytest.mark.parametrize("terms", [1, 6])
+def test_sap_series_block_solves_match_dense_solution(gu, L, l0, k, terms):
+    """Schwarz-preconditioned BiCGstab whose block systems take `terms` terms of their
+    geometric series (the oracle's sap_precond with block_terms): the solution against
+    numpy's dense solve, the residual recomputed by the oracle, and the oracle's own
+    preconditioned BiCGstab reaching the same solution."""
+    import paper_0710_0066_amd as sap
+    print(f"sap series L={L} terms={terms}", flush=True)
+    U = synth.gauge_field(L, 0.5, 1041)
+    b = synth.gaussian_spinor(L, 2041, nrhs=2)
+    A = dirac.dense_matrix(U, k)
+    x_lu = np.linalg.solve(A, b.reshape(2, -1).T).T.reshape(b.shape)
+    ctx = gu.make_ctx(L, l0, k, U, max_rhs=2)
+    fx = ctx.new_field(2)
+    o = sap.solve_opts(tol=1e-10, max_iter=2000, max_outer=20, method=sap.SAP_SAP_BICGSTAB, sap_ncy=2,
+                       sap_block_terms=terms)
+    info = sap.solve_full(ctx, fx, gu.to_sap(ctx, b, 2), 2, o)
+    x = gu.from_sap(ctx, fx, 2, b.shape)
+    res = _relres(U, x, b, k)
+    assert np.all(res <= 1e-10), res
+    for i in range(2):
+        assert abs(info[i].true_rel_res - res[i]) <= 1e-12 and info[i].iters > 0
+    assert np.linalg.norm(x - x_lu) / np.linalg.norm(x_lu) <= np.linalg.cond(A) * 1e-10
+    x_or, _, res_or = solvers.solve_sap_bicgstab(U, b[0], k, l0, ncy=2, tol=1e-11, block_terms=terms)
+    assert res_or <= 1e-11
+    assert np.linalg.norm(x[0] - x_or) / np.linalg.norm(x_or) <= np.linalg.cond(A) * 2e-10
