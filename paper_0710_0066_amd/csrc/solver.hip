@@ -484,12 +484,13 @@ struct SapWS {
   double2 *r, *r0, *p, *v, *t, *ph, *sh, *kx, *kr, *ky, *mt;
   double2 *g1, *g2;     // series block solves: b_hat (even half), D_oe y (odd half)
   double *part, *dev3, *coef;
+  double *ck_res, *ck_add;   // device coefficients of the preconditioner's two fixed updates
   double *h3, *hcoef;
 };
 
 static void sap_ws_free(SapWS* a) {
   void* dev[] = {a->r, a->r0, a->p, a->v, a->t, a->ph, a->sh, a->kx, a->kr, a->ky, a->mt, a->g1, a->g2, a->part, a->dev3,
-                 a->coef};
+                 a->coef, a->ck_res, a->ck_add};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   if (a->h3) (void)hipHostFree(a->h3);
@@ -517,8 +518,10 @@ static SapWS* sap_ws(sap_ctx* c) {
   ok = ok && hipMalloc((void**)&a->part, 3 * nsys * nchunk * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&a->dev3, 3 * nsys * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&a->coef, 6 * nsys * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&a->ck_res, 6 * nsys * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&a->ck_add, 6 * nsys * 8) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&a->h3, 3 * nsys * 8, 0) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&a->hcoef, 6 * nsys * 8, 0) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&a->hcoef, 12 * nsys * 8, 0) == hipSuccess;   // two coefficient sets
   if (!ok) {
     sap_ws_free(a);
     return nullptr;
@@ -589,6 +592,18 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
   bo.method = SAP_CG;
   long long block_iters = 0;
   std::vector<sap_solve_info> binfo((size_t)nrhs * (c->geom.L[0] / c->geom.l0));
+  // the preconditioner's fixed updates kr = in - M kx (0, 1, -1) and kx += ky (1, 1, 0),
+  // uploaded once so that applying K needs no host synchronisation
+  for (int sys = 0; sys < nh; ++sys) {
+    const double res_c[6] = {0, 0, 1, 0, -1, 0}, add_c[6] = {1, 0, 1, 0, 0, 0};
+    for (int e = 0; e < 6; ++e) {
+      a->hcoef[6 * sys + e] = res_c[e];
+      a->hcoef[6 * nh + 6 * sys + e] = add_c[e];
+    }
+  }
+  SAP_HIP_CHECK(c, hipMemcpyAsync(a->ck_res, a->hcoef, 6 * nh * 8, hipMemcpyHostToDevice, st));
+  SAP_HIP_CHECK(c, hipMemcpyAsync(a->ck_add, a->hcoef + 6 * nh, 6 * nh * 8, hipMemcpyHostToDevice, st));
+  SAP_HIP_CHECK(c, hipStreamSynchronize(st));
   // out = K in
   auto K = [&](double2* out, const double2* in) -> int {
     SAP_HIP_CHECK(c, hipMemsetAsync(a->kx, 0, fullb, st));
@@ -599,7 +614,7 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
         if (cyc > 0 || col > 0) {
           int rc = apply_op_any(c, a->mt, a->kx, nrhs, 0, 0, -1, SAP_F64, st);
           if (rc) return rc;
-          if ((rc = lin3(a->kr, in, a->mt, nullptr, zero, one, mone, false))) return rc;
+          blas_lin3<double>(G, nh, H(a->kr), H((double2*)in), H(a->mt), NONE, a->ck_res, nullptr, st);
           rhs = (const double*)a->kr;
         }
         if (o->sap_block_terms > 0) {
@@ -628,8 +643,8 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
           if (rc) return rc;
           for (auto& e : binfo) block_iters += e.iters;
         }
-        int rc;
-        if ((rc = lin3(a->kx, a->ky, nullptr, nullptr, one, one, zero, false))) return rc;
+        blas_lin3<double>(G, nh, H(a->kx), H(a->ky), NONE, NONE, a->ck_add, nullptr, st);
+        SAP_HIP_CHECK(c, hipGetLastError());
       }
     SAP_HIP_CHECK(c, hipMemcpyAsync(out, a->kx, fullb, hipMemcpyDeviceToDevice, st));
     return SAP_OK;
