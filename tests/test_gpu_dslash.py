@@ -215,3 +215,43 @@ def test_pack_unpack_roundtrip(gu):
     back = torch.zeros(p.size, dtype=torch.float64, device="cuda")
     ctx.unpack_momenta(back, fp)
     assert np.array_equal(back.cpu().numpy().reshape(p.shape), p)
+
+
+def test_many_rhs_every_mapping_and_invalid_arguments(gu):
+    """21 right-hand sides (odd, more groups than any workgroup or set holds) through every
+    hop mapping in FP32 and FP16, three rhs checked against the oracle on every site; and
+    the host-side argument checks: nrhs 0 or above max_rhs, an unknown precision, aliasing
+    input and output."""
+    import paper_0710_0066_amd as sap
+    L, l0, k, nrhs = (8, 4, 2, 6), 2, 0.15, 21
+    print("21 rhs, every mapping", flush=True)
+    U = synth.gauge_field(L, 0.5, 1051)
+    psi = synth.gaussian_spinor(L, 2051, nrhs=nrhs)
+    ctx = gu.make_ctx(L, l0, k, U, max_rhs=nrhs)
+    check = (0, 10, nrhs - 1)
+    ref = {r: dirac.hop(U, psi[r]) for r in check}
+    for prec, tol in [(sap.SAP_F32, F32_TOL), (sap.SAP_F16, 16 * 2.0 ** -12 / 0.16)]:
+        fin = gu.to_sap(ctx, psi, nrhs, prec)
+        fout = ctx.new_field(nrhs, prec)
+        for hop_map in range(sap.HOP_NMAP):
+            sap.sap_set_hop_map(ctx, 0, prec, nrhs, hop_map)
+            fout.fill_(5.0)
+            for parity in (0, 1):
+                sap.apply_Dslash_eo(ctx, fout, fin, nrhs, parity, prec)
+            got = gu.from_sap(ctx, fout, nrhs, psi.shape, prec)
+            for r in check:
+                scale = np.max(np.abs(psi[r] if prec == sap.SAP_F16 else ref[r]))
+                err = float(np.max(np.abs(got[r] - ref[r])) / scale)
+                assert err <= tol, (prec, hop_map, r, err)
+        sap.sap_set_hop_map(ctx, 0, prec, nrhs, -1)
+    f = ctx.new_field(1)
+    g = ctx.new_field(1)
+    for call in (lambda: sap.apply_M(ctx, f, g, 0, sap.SAP_F64),
+                 lambda: sap.apply_M(ctx, f, g, nrhs + 1, sap.SAP_F64),
+                 lambda: sap.apply_M(ctx, f, g, 1, 7),
+                 lambda: sap.apply_Dslash_eo(ctx, f, g, 1, 2, sap.SAP_F64),
+                 lambda: sap.solve_blocks(ctx, f, g, 0, 1, sap.SAP_ALL, sap.solve_opts()),
+                 lambda: sap.solve_full(ctx, f, f, 1, sap.solve_opts())):
+        with pytest.raises(sap.SapError) as e:
+            call()
+        assert e.value.code == sap.SAP_E_ARG
