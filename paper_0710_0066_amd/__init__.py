@@ -19,6 +19,12 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is missing: build it with `python paper_0710_0066_amd/build.py`")
 
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7) as the system
+# one this library links against, and the first copy loaded serves the whole process.
+# torch only works with its own copy (loading this library first leaves torch with "No HIP
+# GPUs are available"), so torch is imported before the library is loaded.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(_LIB_PATH)
 
 SAP_OK, SAP_E_ARG, SAP_E_NOMEM, SAP_E_HIP, SAP_E_NOCONV, SAP_E_NONFINITE, SAP_E_STATE = \
