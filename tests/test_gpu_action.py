@@ -38,7 +38,8 @@ def _rel(a, b):
 
 def test_eo_pf_terms_match_oracle(gu):
     """S1 = ||W3eo^-1 phi||^2 and S2 = ||phi + rho W2eo^-1 phi||^2: heat bath, action (equal
-    to ||P_e xi||^2 at the heat bath) and force, FP64 and FP32 inner solves."""
+    to ||P_e xi||^2 at the heat bath) and force, FP64, FP32 and FP16 inner solves (the
+    shifted even-odd solves of W3eo = W2eo + rho run on FP16 fields in the last case)."""
     import paper_0710_0066_amd as sap
     print("eo pseudo-fermion terms", flush=True)
     U = synth.gauge_field(L, 0.5, 101)
@@ -53,8 +54,10 @@ def test_eo_pf_terms_match_oracle(gu):
         S_ref = A.S1(phi_ref) if kind == 1 else A.S2(phi_ref)
         F_ref = A.F1(phi_ref) if kind == 1 else A.F2(phi_ref)
         assert abs(S_ref - float(np.sum(np.abs(A.e * xi) ** 2))) <= 1e-10 * S_ref
-        for inner, ftol in ((sap.SAP_F64, 1e-9), (sap.SAP_F32, 1e-7)):
+        for inner, ftol in ((sap.SAP_F64, 1e-9), (sap.SAP_F32, 1e-7), (sap.SAP_F16, 1e-7)):
             o = _opts(sap, tol=1e-13 if inner == sap.SAP_F64 else 1e-11, inner=inner)
+            if inner == sap.SAP_F16:
+                o.inner_tol = 2e-3
             F = ctx.new_momenta()
             S = sap.eo_pf_force(ctx, F, 1.0, fphi, kind, RHO, o)
             assert abs(S - S_ref) <= 1e-9 * S_ref, (kind, inner)
