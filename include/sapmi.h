@@ -201,7 +201,9 @@ size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs);
 size_t sap_momenta_bytes(const sap_ctx* ctx);
 
 /* Load the gauge field from the canonical layout (device, complex128) into the
- * context's FP64, FP32 and FP16 copies. */
+ * context's FP64, FP32 and FP16 copies. The links must be SU(3): the FP32 and FP16 copies
+ * keep the first two rows of each link and the kernels rebuild the third from unitarity
+ * and unit determinant (FP64 operators use the links as given). */
 int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream);
 /* Copy the context's FP64 gauge field back to the canonical layout. */
 int sap_get_gauge(sap_ctx* ctx, double* U, void* stream);

@@ -94,10 +94,10 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
     delete c;
     return sap_fail(nullptr, SAP_E_HIP, "hipGetDevice failed (no HIP device?)");
   }
-  const size_t nlink = (size_t)72 * c->Vhp;
+  const size_t nlink = (size_t)72 * c->Vhp, nlink2 = (size_t)48 * c->Vhp;   // 2-row copies: 6 of 9
   if (hipMalloc((void**)&c->U64, nlink * sizeof(double2)) != hipSuccess ||
-      hipMalloc((void**)&c->U32, nlink * sizeof(float2)) != hipSuccess ||
-      hipMalloc((void**)&c->U16, nlink * sizeof(__half2)) != hipSuccess) {
+      hipMalloc((void**)&c->U32, nlink2 * sizeof(float2)) != hipSuccess ||
+      hipMalloc((void**)&c->U16, nlink2 * sizeof(__half2)) != hipSuccess) {
     sap_destroy(c);
     return sap_fail(nullptr, SAP_E_NOMEM, "cannot allocate the gauge copies");
   }
@@ -127,7 +127,7 @@ int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream) {
   if (!ctx) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
   if (!U) return sap_fail(ctx, SAP_E_ARG, "U is NULL");
   hipStream_t s = (hipStream_t)stream;
-  launch_pack_gauge(ctx->g, ctx->U64, ctx->U32, (const double2*)U, s);
+  launch_pack_gauge(ctx->g, ctx->U64, nullptr, (const double2*)U, s);
   launch_gauge_to_f32(ctx->g, ctx->U32, ctx->U16, ctx->U64, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
   ctx->have_gauge = true;

@@ -42,6 +42,18 @@ template <class R> __device__ __forceinline__ cx<R> cjfma(cx<R> acc, cx<R> a, cx
   return acc;
 }
 
+// third row of an SU(3) matrix from its first two (m[0..5], row-major): the rows are
+// orthonormal with unit determinant, so row 3 = conj(row 1 x row 2)
+template <class R> __device__ __forceinline__ void third_row(cx<R> m[9]) {
+  const cx<R> a0 = m[0], a1 = m[1], a2 = m[2], b0 = m[3], b1 = m[4], b2 = m[5];
+  const cx<R> c0 = cmul(a1, b2) - cmul(a2, b1);
+  const cx<R> c1 = cmul(a2, b0) - cmul(a0, b2);
+  const cx<R> c2 = cmul(a0, b1) - cmul(a1, b0);
+  m[6] = {c0.r, -c0.i};
+  m[7] = {c1.r, -c1.i};
+  m[8] = {c2.r, -c2.i};
+}
+
 // FP16 storage tag: spinor components as half2 with one FP32 norm per site (the largest
 // component magnitude of the site), links as plain half2; arithmetic in FP32
 struct h16 {};

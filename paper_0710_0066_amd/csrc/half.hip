@@ -12,14 +12,17 @@
 
 namespace sap {
 
+// FP16 links keep the first two rows (see the layout of the reduced link copies); the
+// third is rebuilt in FP32 from unitarity and unit determinant
 __device__ __forceinline__ void load_link16(const __half2* U, long long Vhp, int mu, int par, long long j,
                                             cx<float> m[9]) {
-  const __half2* p = U + par * 36 * Vhp + tiled(j, 9 * mu, 36);
+  const __half2* p = U + par * 24 * Vhp + tiled(j, 6 * mu, 24);
 #pragma unroll
-  for (int e = 0; e < 9; ++e) {
+  for (int e = 0; e < 6; ++e) {
     const float2 v = __half22float2(p[e * TILE]);
     m[e] = {v.x, v.y};
   }
+  third_row<float>(m);
 }
 
 // all eight hops of output site j of parity p for the rhs r0 .. r0 + nr - 1 (nr <= NR):

@@ -18,7 +18,9 @@ namespace sap {
 // Full FP16 fields: rs = 26*Vhp, ps = 12*Vhp, no = 24*Vhp; single-parity: rs = 13*Vhp,
 // ps = 0, no = 12*Vhp (a half2 and a float are both 4 bytes).
 // Gauge field: link (parity p, site j, mu, entry e = 3*row + col) at
-//   p*36*Vhp + tiled(j, 9*mu + e, 36).
+//   p*36*Vhp + tiled(j, 9*mu + e, 36)   (FP64);
+// the FP32 and FP16 copies hold rows 0 and 1 only (e < 6), at  p*24*Vhp + tiled(j, 6*mu + e, 24),
+// and the kernels rebuild row 2 from unitarity and unit determinant.
 // Momenta / forces (float64): (p, j, mu, a) at  p*32*Vhp + tiled(j, 8*mu + a, 32).
 template <class R> struct Field {
   typename vec2<R>::type* ptr;
