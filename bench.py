@@ -363,6 +363,8 @@ def main():
     if args.only_dslash:       # one operator only, for profiler runs
         n_op = args.nrhs if args.op == "eo" else 1
         sap.sap_tune(ctx, n_op)
+        if args.op == "eo" and args.prec == "f32" and args.nrhs == nrhs and args.hop_map < 0:
+            sap.sap_set_hop_map(ctx, 0, sap.SAP_F32, nrhs, sap.HOP_MAP_MARCH2)   # as in the headline
         if args.hop_map >= 0:
             sap.sap_set_hop_map(ctx, int(args.op == "M"), PREC[args.prec], n_op, args.hop_map)
         fn = eo(args.prec, args.nrhs) if args.op == "eo" else full(args.prec)
@@ -375,6 +377,10 @@ def main():
 
     print("[bench] tuning the hop mapping", file=sys.stderr, flush=True)
     tuning = {"nrhs_%d" % n: sap.sap_tune(ctx, n) for n in (1, nrhs)}
+    # the headline launch uses the x0-marching mapping with 2 rhs per work-item, the
+    # tuner's choice on this workload; the runner-up mappings are within a few percent, so
+    # fixing it keeps the line, its profile and its counters on one kernel
+    sap.sap_set_hop_map(ctx, 0, sap.SAP_F32, nrhs, sap.HOP_MAP_MARCH2)
     ms = time_op(sap, torch, eo("f32", nrhs), args.steps, args.warmup)
     gbs = eo_bytes(V, "f32", nrhs) / (ms * 1e-3) / 1e9
     print(f"[bench] D_eo f32 {nrhs} rhs: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s", file=sys.stderr, flush=True)
