@@ -84,6 +84,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   c->Vhp = c->g.Vhp;
   c->have_gauge = false;
   c->U64 = nullptr;
+  c->U64c = nullptr;
   c->U32 = nullptr;
   c->U16 = nullptr;
   c->solver = nullptr;
@@ -96,6 +97,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   }
   const size_t nlink = (size_t)72 * c->Vhp, nlink2 = (size_t)48 * c->Vhp;   // 2-row copies: 6 of 9
   if (hipMalloc((void**)&c->U64, nlink * sizeof(double2)) != hipSuccess ||
+      hipMalloc((void**)&c->U64c, nlink2 * sizeof(double2)) != hipSuccess ||
       hipMalloc((void**)&c->U32, nlink2 * sizeof(float2)) != hipSuccess ||
       hipMalloc((void**)&c->U16, nlink2 * sizeof(__half2)) != hipSuccess) {
     sap_destroy(c);
@@ -118,6 +120,7 @@ void sap_destroy(sap_ctx* ctx) {
   sap_solver_destroy(ctx);
   sap_force_destroy(ctx);
   if (ctx->U64) (void)hipFree(ctx->U64);
+  if (ctx->U64c) (void)hipFree(ctx->U64c);
   if (ctx->U32) (void)hipFree(ctx->U32);
   if (ctx->U16) (void)hipFree(ctx->U16);
   delete ctx;
@@ -128,7 +131,7 @@ int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream) {
   if (!U) return sap_fail(ctx, SAP_E_ARG, "U is NULL");
   hipStream_t s = (hipStream_t)stream;
   launch_pack_gauge(ctx->g, ctx->U64, nullptr, (const double2*)U, s);
-  launch_gauge_to_f32(ctx->g, ctx->U32, ctx->U16, ctx->U64, s);
+  launch_gauge_to_f32(ctx->g, ctx->U64c, ctx->U32, ctx->U16, ctx->U64, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
   ctx->have_gauge = true;
   return SAP_OK;

@@ -27,21 +27,15 @@ __device__ __forceinline__ void load_spinor(const typename vec2<R>::type* p, lon
     }
 }
 
-// The FP64 links are stored whole (9 entries). The FP32 copy keeps the first two rows and
-// rebuilds the third from unitarity and unit determinant: row 3 = conj(row 1 x row 2).
+// The hop kernels read two-row link copies (FP64 or FP32) and rebuild the third row from
+// unitarity and unit determinant: row 3 = conj(row 1 x row 2).
 template <class R>
 __device__ __forceinline__ void load_link(const typename vec2<R>::type* U, long long Vhp, int mu,
                                           int par, long long j, cx<R> m[9]) {
-  if constexpr (std::is_same<R, float>::value) {
-    const float2* p = U + par * 24 * Vhp + tiled(j, 6 * mu, 24);
+  const typename vec2<R>::type* p = U + par * 24 * Vhp + tiled(j, 6 * mu, 24);
 #pragma unroll
-    for (int e = 0; e < 6; ++e) m[e] = ld<R>(p + e * TILE);
-    third_row<R>(m);
-  } else {
-    const typename vec2<R>::type* p = U + par * 36 * Vhp + tiled(j, 9 * mu, 36);
-#pragma unroll
-    for (int e = 0; e < 9; ++e) m[e] = ld<R>(p + e * TILE);
-  }
+  for (int e = 0; e < 6; ++e) m[e] = ld<R>(p + e * TILE);
+  third_row<R>(m);
 }
 
 // Work-item mappings (MAP):

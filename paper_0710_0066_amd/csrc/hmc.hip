@@ -95,7 +95,7 @@ void hop_sel(sap_ctx* c, double2* out, const double2* in, int colour, int outer,
   A.out = {out, 24 * Vhp, 12 * Vhp};
   A.in = {(double2*)in, 24 * Vhp, 12 * Vhp};
   A.x = A.in;
-  A.U = c->U64;
+  A.U = gauge_of<double>(c);
   A.g = c->g;
   A.nrhs = 1;
   A.parity_out = -1;
@@ -210,7 +210,7 @@ int hop_odd(sap_ctx* c, double2* out, const double2* in, bool dag, hipStream_t s
   A.out = {out, 24 * Vhp, 12 * Vhp};
   A.in = {(double2*)in, 24 * Vhp, 12 * Vhp};
   A.x = {nullptr, 0, 0};
-  A.U = c->U64; A.g = c->g; A.nrhs = 1; A.parity_out = 1;
+  A.U = gauge_of<double>(c); A.g = c->g; A.nrhs = 1; A.parity_out = 1;
   A.lb = c->geom.l0_sub; A.slb = 0; A.colour = 0; A.block = -1;
   A.a = 0.0; A.b = 1.0; A.g5_in = A.g5_out = dag ? 1 : 0; A.map = HOP_MAP_SITE;
   launch_hop<double>(A, s);
@@ -227,7 +227,7 @@ int apply_weo(sap_ctx* c, double2* out, const double2* in, double rho, double2* 
   A.out = {out, 24 * Vhp, 12 * Vhp};
   A.in = {tmp, 24 * Vhp, 12 * Vhp};
   A.x = {(double2*)in, 24 * Vhp, 12 * Vhp};
-  A.U = c->U64; A.g = c->g; A.nrhs = 1; A.parity_out = 0;
+  A.U = gauge_of<double>(c); A.g = c->g; A.nrhs = 1; A.parity_out = 0;
   A.lb = c->geom.l0_sub; A.slb = 0; A.colour = 0; A.block = -1;
   const double k = c->geom.kappa;
   A.a = 1.0 + rho; A.b = -k * k; A.g5_in = A.g5_out = 0; A.map = HOP_MAP_SITE;
@@ -307,7 +307,7 @@ int kinetic_host(sap_ctx* c, const double* P, double* K, hipStream_t s) {
   return SAP_OK;
 }
 
-void links_changed(sap_ctx* c, hipStream_t s) { launch_gauge_to_f32(c->g, c->U32, c->U16, c->U64, s); }
+void links_changed(sap_ctx* c, hipStream_t s) { launch_gauge_to_f32(c->g, c->U64c, c->U32, c->U16, c->U64, s); }
 
 // ---- the two-level integrator --------------------------------------------------------
 struct Traj {
@@ -637,7 +637,7 @@ int hmc_trajectory(sap_ctx* c, double* U, const sap_hmc_params* P, sap_hmc_info*
   A.out = {phi1, 24 * Vhp, 12 * Vhp};
   A.in = {w->f[0], 24 * Vhp, 12 * Vhp};
   A.x = A.in;
-  A.U = c->U64; A.g = c->g; A.nrhs = 1; A.parity_out = -1;
+  A.U = gauge_of<double>(c); A.g = c->g; A.nrhs = 1; A.parity_out = -1;
   A.lb = c->geom.l0; A.slb = c->geom.l0; A.colour = 0; A.block = -1;
   A.a = 1.0; A.b = -c->geom.kappa; A.g5_in = A.g5_out = 0; A.map = HOP_MAP_SITE;
   launch_hop<double>(A, s);

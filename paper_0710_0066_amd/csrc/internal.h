@@ -19,8 +19,9 @@ namespace sap {
 // ps = 0, no = 12*Vhp (a half2 and a float are both 4 bytes).
 // Gauge field: link (parity p, site j, mu, entry e = 3*row + col) at
 //   p*36*Vhp + tiled(j, 9*mu + e, 36)   (FP64);
-// the FP32 and FP16 copies hold rows 0 and 1 only (e < 6), at  p*24*Vhp + tiled(j, 6*mu + e, 24),
-// and the kernels rebuild row 2 from unitarity and unit determinant.
+// the copies the hop kernels read (FP64, FP32, FP16) hold rows 0 and 1 only (e < 6), at
+// p*24*Vhp + tiled(j, 6*mu + e, 24), and the kernels rebuild row 2 from unitarity and unit
+// determinant.
 // Momenta / forces (float64): (p, j, mu, a) at  p*32*Vhp + tiled(j, 8*mu + a, 32).
 template <class R> struct Field {
   typename vec2<R>::type* ptr;
@@ -96,8 +97,8 @@ void launch_unpack_spinor(const Geo& g, double2* out, const typename vec2<R>::ty
                           int nrhs, hipStream_t s);
 void launch_pack_gauge(const Geo& g, double2* U64, float2* U32, const double2* in, hipStream_t s);
 void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStream_t s);
-// the FP32 (and, if U16 is given, FP16) link copies from the FP64 links
-void launch_gauge_to_f32(const Geo& g, float2* U32, __half2* U16, const double2* U64, hipStream_t s);
+// the two-row FP64, FP32 and FP16 link copies of the hop kernels from the FP64 links
+void launch_gauge_to_f32(const Geo& g, double2* U64c, float2* U32, __half2* U16, const double2* U64, hipStream_t s);
 void launch_pack_spinor16(const Geo& g, __half2* out, const double2* in, int nrhs, hipStream_t s);
 void launch_unpack_spinor16(const Geo& g, double2* out, const __half2* in, int nrhs, hipStream_t s);
 void launch_pack_momenta(const Geo& g, double* out, const double* in, hipStream_t s);
@@ -121,9 +122,10 @@ struct sap_ctx {
   long long V, Vh, Vhp;
   int device;
   bool have_gauge;
-  double2* U64;   // tiled gauge layout, 72*Vhp complex
-  float2* U32;
-  __half2* U16;   // FP16 copy (kept in step with U32)
+  double2* U64;   // tiled gauge layout, 72*Vhp complex (whole links: forces, link updates)
+  double2* U64c;  // two-row FP64 copy read by the hop kernels (48*Vhp complex)
+  float2* U32;    // two-row FP32 copy
+  __half2* U16;   // two-row FP16 copy (all three kept in step with U64)
   std::string err;
   void* solver;   // solver workspace (solver.hip)
   void* forces;   // force / trajectory workspace (hmc.hip)
@@ -161,7 +163,7 @@ int check_solve_opts(sap_ctx* c, const sap_solve_opts* o);
 
 // the context's link copy for storage type S
 template <class S> inline const typename sap::vec2<S>::type* gauge_of(const sap_ctx* c) {
-  if constexpr (std::is_same<S, double>::value) return c->U64;
+  if constexpr (std::is_same<S, double>::value) return c->U64c;
   else if constexpr (std::is_same<S, float>::value) return c->U32;
   else return c->U16;
 }

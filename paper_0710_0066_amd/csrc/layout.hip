@@ -84,15 +84,16 @@ __global__ void unpack_gauge_kernel(Geo g, double2* out, const double2* U64) {
 
 // FP32 / FP16 link copies keep the first two rows of each link (6 of 9 entries): entry k of
 // the copy is (parity, site j, component c = 6 mu + e) at  p*24*Vhp + tiled(j, c, 24)
-__global__ void gauge_to_f32_kernel(long long Vhp, float2* U32, __half2* U16, const double2* U64) {
+__global__ void gauge_to_f32_kernel(long long Vhp, double2* U64c, float2* U32, __half2* U16, const double2* U64) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= 48 * Vhp) return;
   const long long p = k / (24 * Vhp), r = k - p * 24 * Vhp;
   const long long tile = r / (24 * TILE), c = (r / TILE) % 24, lane = r % TILE;
   const long long j = tile * TILE + lane;
   const double2 v = U64[p * 36 * Vhp + tiled(j, (int)(9 * (c / 6) + c % 6), 36)];
+  U64c[k] = v;
   U32[k] = make_float2((float)v.x, (float)v.y);
-  if (U16) U16[k] = __floats2half2_rn((float)v.x, (float)v.y);
+  U16[k] = __floats2half2_rn((float)v.x, (float)v.y);
 }
 
 // FP16 spinor fields: components divided by the site norm (the largest component
@@ -173,9 +174,9 @@ void launch_pack_gauge(const Geo& g, double2* U64, float2* U32, const double2* i
 void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStream_t s) {
   hipLaunchKernelGGL(unpack_gauge_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, U64);
 }
-void launch_gauge_to_f32(const Geo& g, float2* U32, __half2* U16, const double2* U64, hipStream_t s) {
+void launch_gauge_to_f32(const Geo& g, double2* U64c, float2* U32, __half2* U16, const double2* U64, hipStream_t s) {
   long long n = 48LL * g.Vhp;
-  hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, g.Vhp, U32, U16, U64);
+  hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, g.Vhp, U64c, U32, U16, U64);
 }
 void launch_pack_spinor16(const Geo& g, __half2* out, const double2* in, int nrhs, hipStream_t s) {
   long long n = 2 * g.Vh * nrhs;

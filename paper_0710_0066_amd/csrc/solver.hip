@@ -331,8 +331,8 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     if (eo_only) {
       // A x = (M_hat + rho) x_e on the even sites, via the odd half of AX
       const Field<double> NONE64 = {nullptr, 0, 0};
-      hop<double>(c, c->U64, AX, X, NONE64, 1, nrhs, lb, colour, 0.0, 1.0, 0, 0, st);
-      hop<double>(c, c->U64, AX, AX, X, 0, nrhs, lb, colour, 1.0 + rho, -kap * kap, 0, 0, st);
+      hop<double>(c, gauge_of<double>(c), AX, X, NONE64, 1, nrhs, lb, colour, 0.0, 1.0, 0, 0, st);
+      hop<double>(c, gauge_of<double>(c), AX, AX, X, 0, nrhs, lb, colour, 1.0 + rho, -kap * kap, 0, 0, st);
       blas_resid(G, nrhs, R64, B, AX, w->partA, st, 1);
     } else {
       int rc = apply_op_any(c, w->ax, x, nrhs, lb, colour < 3 ? colour : 0, colour < 3 ? -1 : colour - 3,
@@ -626,13 +626,13 @@ static int sap_bicgstab(sap_ctx* c, double* x, const double* b, int nrhs, const 
           const Field<double> NONE64 = {nullptr, 0, 0, 0};
           const double kap = c->geom.kappa;
           const int lb = c->geom.l0;
-          hop<double>(c, c->U64, BH, RHS, RHS, 0, nrhs, lb, colour, 1.0, kap, 0, 0, st);
-          hop<double>(c, c->U64, Y, RHS, RHS, 0, nrhs, lb, colour, 1.0, kap, 0, 0, st);
+          hop<double>(c, gauge_of<double>(c), BH, RHS, RHS, 0, nrhs, lb, colour, 1.0, kap, 0, 0, st);
+          hop<double>(c, gauge_of<double>(c), Y, RHS, RHS, 0, nrhs, lb, colour, 1.0, kap, 0, 0, st);
           for (int n = 1; n < o->sap_block_terms; ++n) {
-            hop<double>(c, c->U64, Z, Y, NONE64, 1, nrhs, lb, colour, 0.0, 1.0, 0, 0, st);
-            hop<double>(c, c->U64, Y, Z, BH, 0, nrhs, lb, colour, 1.0, kap * kap, 0, 0, st);
+            hop<double>(c, gauge_of<double>(c), Z, Y, NONE64, 1, nrhs, lb, colour, 0.0, 1.0, 0, 0, st);
+            hop<double>(c, gauge_of<double>(c), Y, Z, BH, 0, nrhs, lb, colour, 1.0, kap * kap, 0, 0, st);
           }
-          hop<double>(c, c->U64, Y, Y, RHS, 1, nrhs, lb, colour, 1.0, kap, 0, 0, st);
+          hop<double>(c, gauge_of<double>(c), Y, Y, RHS, 1, nrhs, lb, colour, 1.0, kap, 0, 0, st);
           SAP_HIP_CHECK(c, hipGetLastError());
         } else {
           int rc = o->inner_prec == SAP_F64
