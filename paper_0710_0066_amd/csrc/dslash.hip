@@ -459,8 +459,8 @@ __device__ __forceinline__ void hop_store(const HopArgs<R>& A, int p, long long 
   }
 }
 
-// all eight hops of output site j
-template <class R, int NR>
+// all eight hops of output site j (NT: non-temporal output stores)
+template <class R, int NR, bool NT = false>
 __device__ __forceinline__ void hop_site_rhs(const HopArgs<R>& A, int p, long long j, int r0, int nr) {
   const Site s = decode(A.g, j, p);
   const bool sel = hop_selected(A, s.x0);
@@ -478,7 +478,7 @@ __device__ __forceinline__ void hop_site_rhs(const HopArgs<R>& A, int p, long lo
       hop_dir<R, NR>(A, p, j, s, mu, 1, r0, nr, acc);
     }
   }
-  hop_store<R, NR, false>(A, p, j, r0, nr, sel, acc);
+  hop_store<R, NR, NT>(A, p, j, r0, nr, sel, acc);
 }
 
 // Register-blocked kernel, chunk order: a workgroup holds 256 consecutive sites of one
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(128) void hop_march_kernel(HopArgs<R> A, int nck) {
     s = lo + chunk * 128 + threadIdx.x;
   }
   if (s >= hi) return;
-  hop_site_rhs<R, NR>(A, p, (long long)x0 * A.g.V3h + s, r0, min(NR, A.nrhs - r0));
+  hop_site_rhs<R, NR, true>(A, p, (long long)x0 * A.g.V3h + s, r0, min(NR, A.nrhs - r0));
 }
 
 // x0-walking even-odd hop. A work-item owns the slice-local site s (j = x0*V3h + s) of the
