@@ -10,7 +10,7 @@ a few 2^-24 m). For the hop, each of the 8 terms of eq. 2 sees a projected half 
 of at most 2 max|psi| per component times a link whose entries carry 2^-12 errors, and
 a link times the projected input error; with kappa <= 0.16 and the output itself rounded
 once, the sum stays below 16 * 2^-12 of the largest input component (F16_TOL below).
-Solves are judged by the FP64 residual, as for FP32 inner solves."""
+Solves are checked by their FP64 residual, as for FP32 inner solves."""
 import numpy as np
 import pytest
 
