@@ -336,7 +336,7 @@ int gauge_force(sap_ctx* ctx, double* F, double coef, double beta, double* S_G_o
  * (FP64 exponential, reunitarised). */
 int sap_update_links(sap_ctx* ctx, const double* p, double dt, void* stream);
 
-/* x0 profile of a force (the analogue of Sec. 4's plot of the average force on the spatial
+/* x0 profile of a force (the analogue of Fig. 1 of Sec. 3, the average force on the spatial
  * links against x0). F (device): a force / momentum field in the sap momenta layout
  * (sap_momenta_bytes), e.g. the output of gauge_force, block_pf_force or
  * schwarz_boundary_force. prof (host, 2*L0 doubles) receives

@@ -137,7 +137,7 @@ def gauge_force(U, beta):
 
 
 def force_profile(F):
-    """x0 profile of a force field F[x0, x1, x2, x3, mu, a] (Sec. 4, the plot of the average
+    """x0 profile of a force field F[x0, x1, x2, x3, mu, a] (Sec. 3, Fig. 1: the plot of the average
     force on the spatial links against x0): row 0 = mean over the sites of each slice and
     over mu = 1, 2, 3 of |F(x, mu)|, row 1 = the same for mu = 0, where |F| is the
     Euclidean norm of the eight components F^a."""

@@ -6,7 +6,7 @@ The library's interchange format fixes the chiral basis written here in 2x2 bloc
     gamma_0 = [[0, -1], [-1, 0]],   gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
     gamma_5 = gamma_0 gamma_1 gamma_2 gamma_3 = diag(1, 1, -1, -1).
 
-Pins (tests/test_oracle_gamma.py): Clifford algebra {g_mu, g_nu} = 2 delta, hermiticity,
+Pins (tests/test_oracle_dirac.py::test_gamma_algebra): Clifford algebra {g_mu, g_nu} = 2 delta, hermiticity,
 gamma_5 = diag(1,1,-1,-1), gamma_5 anticommuting with every gamma_mu.
 """
 import numpy as np

@@ -136,7 +136,7 @@ def test_force_profile_closed_form():
 
 
 def test_schwarz_force_profile_decays_from_block_boundaries():
-    """Sec. 4 (plot of the average force on the spatial links against x0): the force of the
+    """Sec. 3, Fig. 1 (plot of the average force on the spatial links against x0): the force of the
     Schwarz term det^2(M W1^{-1}) is largest at the boundaries between the blocks and
     smallest in the middle of a block. Two blocks of l0 = L0/2 as in the paper's first
     decomposition, on a rough field at kappa = 0.13 (short correlation length, so the decay
@@ -154,3 +154,83 @@ def test_schwarz_force_profile_decays_from_block_boundaries():
         assert np.all(np.diff(down) < 0), sp
         assert np.all(np.diff(up[::-1][:l0 // 2]) < 0), sp
         assert min(sp[first], sp[last]) > 100 * min(sp[mid - 1], sp[mid]), sp
+
+
+# ---- pins of the gauge action and the mean plaquette (Sec. 1, Wilson plaquette action) ----
+
+def _random_su3(n, rng):
+    """n Haar-ish SU(3) matrices from the QR decomposition of complex Gaussian matrices,
+    phases fixed so that det = 1 (independent of the oracle and of synth)."""
+    Z = rng.standard_normal((n, 3, 3)) + 1j * rng.standard_normal((n, 3, 3))
+    Q, R = np.linalg.qr(Z)
+    d = np.diagonal(R, axis1=-2, axis2=-1)
+    Q = Q * (d / np.abs(d))[:, None, :]
+    det = np.linalg.det(Q)
+    return Q / (det ** (1.0 / 3.0))[:, None, None]
+
+
+def test_gauge_action_is_gauge_invariant():
+    """S_G[U^g] = S_G[U] with U_mu(x) -> g(x) U_mu(x) g(x + mu)^dagger for a random SU(3)
+    g per site: a plaquette with a misplaced dagger or a wrong shift is not invariant."""
+    L = (4, 4, 2, 6)
+    U = synth.gauge_field(L, 0.6, 51)
+    rng = np.random.default_rng(52)
+    g = _random_su3(int(np.prod(L)), rng).reshape(tuple(L) + (3, 3))
+    assert np.max(np.abs(g @ np.swapaxes(g.conj(), -1, -2) - np.eye(3))) < 1e-13
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        g_next = np.roll(g, -1, axis=mu)                   # g(x + mu), periodic links
+        Ug[..., mu, :, :] = g @ U[..., mu, :, :] @ np.swapaxes(g_next.conj(), -1, -2)
+    s0, s1 = forces.gauge_action(U, 5.6), forces.gauge_action(Ug, 5.6)
+    assert abs(s1 - s0) <= 1e-12 * abs(s0)
+    assert abs(forces.mean_plaquette(Ug) - forces.mean_plaquette(U)) <= 1e-13
+
+
+def test_unit_links_give_plaquette_one_and_action_minus_6_beta_V():
+    """U = 1: every Re Tr U_P = 3, so <P> = 1 and S_G = -(beta/3) * 6V * 3 = -6 beta V."""
+    L = (4, 2, 6, 2)
+    V = int(np.prod(L))
+    U = np.broadcast_to(np.eye(3, dtype=complex), tuple(L) + (4, 3, 3)).copy()
+    assert forces.mean_plaquette(U) == pytest.approx(1.0, abs=1e-15)
+    assert forces.gauge_action(U, 5.6) == pytest.approx(-6.0 * 5.6 * V, rel=1e-15)
+
+
+def test_constant_abelian_flux_closed_form():
+    """A constant U(1) flux through the (1, 2) planes embedded in SU(3):
+    U_2(x) = diag(e^{iBx1}, e^{-iBx1}, 1), every other link 1, B = 2 pi n / L1 (periodic).
+    Each (1, 2) plaquette is diag(e^{+-iB}, e^{-+iB}, 1), Re Tr = 1 + 2 cos B, and the
+    other five planes give 3, so <P> = (15 + 1 + 2 cos B) / 18 and
+    S_G = -(beta/3) V (16 + 2 cos B)."""
+    L = (2, 6, 4, 2)
+    V = int(np.prod(L))
+    U = np.broadcast_to(np.eye(3, dtype=complex), tuple(L) + (4, 3, 3)).copy()
+    B = 2.0 * np.pi * 1 / L[1]
+    x1 = np.arange(L[1])[None, :, None, None]
+    ph = np.exp(1j * B * x1) * np.ones(L)
+    U[..., 2, 0, 0] = ph
+    U[..., 2, 1, 1] = ph.conj()
+    assert forces.mean_plaquette(U) == pytest.approx((16.0 + 2.0 * np.cos(B)) / 18.0, abs=1e-14)
+    assert forces.gauge_action(U, 5.6) == pytest.approx(-5.6 / 3.0 * V * (16.0 + 2.0 * np.cos(B)), rel=1e-14)
+
+
+def test_synthetic_mean_plaquette_is_c_to_the_fourth():
+    """For independent links whose distribution is invariant under conjugation and
+    under H -> -H, E[U] = c 1 with c = E[(1/3) Re Tr exp(i eps H)], and the expected
+    mean plaquette is c^4 (each plaquette is a product of four independent links or their
+    adjoints). c is estimated from 200 000 independently drawn H (eigenvalues of H only,
+    no plaquette code); the oracle's <P> on an 8^4 field must lie within 5 standard
+    errors of c^4 (the standard error from the spread of the per-site plaquettes)."""
+    eps = 0.35
+    rng = np.random.default_rng(53)
+    A = rng.standard_normal((200000, 3, 3)) + 1j * rng.standard_normal((200000, 3, 3))
+    H = 0.5 * (A + np.swapaxes(A.conj(), -1, -2))
+    H = H - (np.trace(H, axis1=-2, axis2=-1).real / 3.0)[:, None, None] * np.eye(3)
+    c = float(np.mean(np.cos(eps * np.linalg.eigvalsh(H)).sum(axis=-1)) / 3.0)
+    L = (8, 8, 8, 8)
+    U = synth.gauge_field(L, eps, 54)
+    per_site = forces.plaquette_field(U) / 18.0            # six planes, (1/3) Re Tr each
+    P = forces.mean_plaquette(U)
+    assert P == pytest.approx(float(per_site.mean()), abs=1e-14)
+    se = float(per_site.std()) / np.sqrt(per_site.size)
+    assert abs(P - c ** 4) <= 5.0 * se, (P, c ** 4, se)
+    assert 0.50 < c ** 4 < 0.52                            # the 0.509 of the workload recipe
