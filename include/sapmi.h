@@ -346,6 +346,21 @@ int sap_update_links(sap_ctx* ctx, const double* p, double dt, void* stream);
  * basis. Fixed-order sums (deterministic); needs no gauge field; synchronises. */
 int sap_force_profile(sap_ctx* ctx, const double* F, double* prof, void* stream);
 
+/* Allocation-free variant of sap_force_profile, for callers that cannot allocate device
+ * memory (code under HIP graph capture, loops that must not allocate). The same profile
+ * as sap_force_profile, computed by the same kernels, but prof is a DEVICE array of 2*L0
+ * doubles (same order) written on the stream, and the call does not synchronise. The
+ * call allocates nothing: its partial sums live in one fixed array of
+ * sap_force_profile_noalloc_max() doubles (2 MiB) per GPU, which the GPU holds until the
+ * process ends. The lattice must need at most that many, 2*L0*ceil(L1*L2*L3/256)
+ * (SAP_E_ARG otherwise). Every call on a GPU uses that GPU's array: calls that overlap
+ * in time on one GPU (several streams, threads or contexts) race and give wrong profiles.
+ * Errors: SAP_E_ARG (NULL pointer, lattice too large), SAP_E_STATE (array address not
+ * resolved by sap_create on this device), SAP_E_HIP (launch failed). */
+int sap_force_profile_noalloc(sap_ctx* ctx, const double* F, double* prof, void* stream);
+/* Capacity, in doubles, of the fixed array of sap_force_profile_noalloc. */
+size_t sap_force_profile_noalloc_max(void);
+
 /* Translate the context's gauge field by n slices in x0: U'(x0, ...) = U(x0 + n, ...)
  * (Sec. 2: shift after each trajectory for ergodicity of the inactive links). */
 int sap_shift_gauge(sap_ctx* ctx, int n, void* stream);

@@ -122,6 +122,8 @@ _SIGS = {
     "sap_plaquette": ([_P, _P, _P], _I),
     "sap_shift_gauge": ([_P, _I, _P], _I),
     "sap_force_profile": ([_P, _P, _P, _P], _I),
+    "sap_force_profile_noalloc": ([_P, _P, _P, _P], _I),
+    "sap_force_profile_noalloc_max": ([], ctypes.c_size_t),
     "sap_tune": ([_P, _I, _P, _P], _I),
     "sap_set_hop_map": ([_P, _I, _I, _I, _I], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
@@ -275,6 +277,16 @@ def sap_force_profile(ctx, F):
     out = (ctypes.c_double * (2 * L0))()
     _check(ctx.ptr, _lib.sap_force_profile(ctx.ptr, _ptr(F), out, _stream()))
     return [list(out[:L0]), list(out[L0:])]
+
+
+def sap_force_profile_noalloc(ctx, F, prof):
+    """The x0 profile of F written to the device tensor prof (2*L0 float64) on the current
+    stream, without allocating and without synchronising (see sap_force_profile)."""
+    _check(ctx.ptr, _lib.sap_force_profile_noalloc(ctx.ptr, _ptr(F), _ptr(prof), _stream()))
+
+
+def sap_force_profile_noalloc_max() -> int:
+    return _lib.sap_force_profile_noalloc_max()
 
 
 def eo_pf_heat_bath(ctx, phi, xi, kind, rho, opts):

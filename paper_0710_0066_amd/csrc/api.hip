@@ -69,6 +69,7 @@ int sap_solver_create(sap_ctx* ctx);     // solver.hip
 }  // extern "C"
 int sap_force_create(sap_ctx* ctx);      // hmc.hip
 void sap_force_destroy(sap_ctx* ctx);    // hmc.hip
+int sap_noalloc_setup(sap_ctx* ctx);     // noalloc.hip
 extern "C" {
 
 int sap_create(const sap_geom* g, sap_ctx** out) {
@@ -105,6 +106,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   }
   int rc = sap_solver_create(c);
   if (rc == SAP_OK) rc = sap_force_create(c);
+  if (rc == SAP_OK) rc = sap_noalloc_setup(c);
   if (rc != SAP_OK) {
     std::string m = c->err;
     sap_destroy(c);
