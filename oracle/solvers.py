@@ -17,6 +17,9 @@ yet below tol).
 * ``geometric_series``: W x = b in the even-odd form, x_e = sum_n (k^2 D_eo D_oe)^n b_hat,
   stopped when the last term is below tol ||b|| (the residual of the partial sum is the
   next term).
+* ``geometric_series_eo``: the same series for the even-site system (M_hat + rho) x = b of
+  the mass-preconditioned action parts (Sec. 1, end: W3eo = W2eo + rho), whose terms carry
+  the factor 1 / (1 + rho) each.
 
 Leading batch axes are independent systems with their own scalars.
 """
@@ -232,5 +235,36 @@ def geometric_series(U, b, kappa, l0=None, tol=1e-12, maxiter=100000):
             break
     x = xe + o * (b + kappa * hop(U, xe, l0))
     res = np.sqrt(_norm2(b - apply_op(U, x, kappa, l0))) / np.where(bn == 0, 1.0, bn)
+    res = res.reshape(res.shape[:-6]) if res.ndim > 6 else float(res.reshape(()))
+    return x, n, res
+
+
+def geometric_series_eo(U, b, kappa, l0=None, rho=0.0, tol=1e-12, maxiter=100000, adjoint=False):
+    """(M_hat + rho) x = b for b on the even sites, M_hat = 1 - kappa^2 P_e D P_o D P_e the
+    even-odd operator of M (l0 None) or of W_l0 (Sec. 1; rho > 0 is W3eo = W2eo + rho of
+    the mass preconditioning), or its adjoint (the hops D^dagger). Since
+    M_hat + rho = (1 + rho) (1 - kappa^2 P_e D P_o D P_e / (1 + rho)), the series is
+        x = sum_{n >= 0} t_n,  t_0 = b / (1 + rho),
+        t_{n+1} = kappa^2 / (1 + rho) P_e D P_o D t_n,
+    and the residual of the sum t_0 .. t_N is (1 + rho) t_{N+1}: the sum stops at the first
+    term with ||(1 + rho) t_{N+1}|| <= tol ||b|| (per system). The series converges where
+    the spectral radius of kappa^2 D_eo D_oe is below 1 + rho. Returns (x, terms added,
+    true relative residual)."""
+    L = U.shape[:4]
+    e, o = parity_masks(L)
+    c = 1.0 + rho
+    D = lambda v: hop(U, v, l0, adjoint)
+    t = e * b / c
+    bn = np.sqrt(_norm2(b))
+    x = np.zeros_like(b)
+    n = 0
+    for _ in range(maxiter):
+        x = x + t
+        n += 1
+        t = kappa * kappa / c * (e * D(o * D(t)))
+        if np.all(c * np.sqrt(_norm2(t)) <= tol * bn) or not np.all(np.isfinite(t)):
+            break
+    r = e * b - (c * x - kappa * kappa * (e * D(o * D(x))))
+    res = np.sqrt(_norm2(r)) / np.where(bn == 0, 1.0, bn)
     res = res.reshape(res.shape[:-6]) if res.ndim > 6 else float(res.reshape(()))
     return x, n, res

@@ -5,6 +5,7 @@ oracle: Krylov finite termination, numpy's dense solve, the exact vanishing of t
 residual on the colour updated last, and the free-field spectrum, which fixes the
 convergence rate of the geometric series in closed form."""
 import numpy as np
+import pytest
 
 import synth
 from oracle import dirac, lattice, solvers
@@ -154,3 +155,54 @@ def test_sap_with_series_block_solves_is_linear_and_converges():
     x, its, res = solvers.solve_sap_bicgstab(U, u, k, l0, ncy=2, tol=1e-12, block_terms=6)
     assert res <= 1e-12
     assert np.linalg.norm(x - ref) / np.linalg.norm(ref) <= 1e-10
+
+
+def _dense_eo_shifted(U, k, l0, rho, adjoint):
+    """Dense (M_hat + rho) on the even sites, from the oracle's dense M_hat-free operators:
+    built column by column from the plain hop of eq. 2 on unit vectors (no series code)."""
+    L = U.shape[:4]
+    e, o = dirac.parity_masks(L)
+    n = int(np.prod(L)) * 12
+    ev = np.nonzero(np.broadcast_to(e, tuple(L) + (4, 3)).reshape(-1))[0]
+    cols = []
+    for i in ev:
+        v = np.zeros(n, dtype=complex)
+        v[i] = 1.0
+        v = v.reshape(tuple(L) + (4, 3))
+        w = dirac.apply_Mhat(U, v, k, l0, adjoint) + rho * v
+        cols.append(w.reshape(-1)[ev])
+    return np.array(cols).T, ev
+
+
+@pytest.mark.parametrize("l0,adjoint", [(None, False), (2, False), (2, True)])
+def test_shifted_geometric_series_matches_dense_solve(l0, adjoint):
+    """(M_hat + rho) x = b on the even sites (rho = 0.3, the W3eo = W2eo + rho of the mass
+    preconditioning, and rho = 0) against numpy's dense solve; a dropped 1/(1 + rho) in
+    t_0 or in the ratio of the terms fails it."""
+    L, k = (4, 2, 2, 4), 0.13
+    U = synth.gauge_field(L, 0.5, 31)
+    e, _ = dirac.parity_masks(L)
+    b = e * synth.gaussian_spinor(L, 32)
+    for rho in (0.3, 0.0):
+        A, ev = _dense_eo_shifted(U, k, l0, rho, adjoint)
+        ref = np.linalg.solve(A, b.reshape(-1)[ev])
+        x, n, res = solvers.geometric_series_eo(U, b, k, l0, rho, tol=1e-13, adjoint=adjoint)
+        assert res <= 1e-13 and n > 2
+        assert np.all(x.reshape(-1)[np.setdiff1d(np.arange(b.size), ev)] == 0)
+        assert np.linalg.norm(x.reshape(-1)[ev] - ref) <= 1e-11 * np.linalg.norm(ref), (rho, l0)
+
+
+def test_shifted_geometric_series_rate_is_free_radius_over_one_plus_rho():
+    """Free field: the residual falls per term by the spectral radius of the unshifted
+    series divided by 1 + rho (closed form of the free Wilson spectrum); at kappa = 0.14,
+    where the unshifted series diverges, rho = 0.2 makes it converge."""
+    L = (4, 4, 4, 4)
+    U = _free_field(L)
+    e, _ = dirac.parity_masks(L)
+    b = e * synth.gaussian_spinor(L, 33)
+    for k, rho in ((0.12, 0.1), (0.14, 0.2)):
+        rate = _free_spectral_radius(L, k) / (1.0 + rho)
+        assert rate < 1.0
+        r60 = solvers.geometric_series_eo(U, b, k, None, rho, tol=0.0, maxiter=60)[2]
+        r70 = solvers.geometric_series_eo(U, b, k, None, rho, tol=0.0, maxiter=70)[2]
+        assert abs(r70 / r60 - rate ** 10) <= 2e-3 * rate ** 10, (k, rho, r70 / r60, rate ** 10)
