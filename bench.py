@@ -31,6 +31,13 @@ WORKLOAD = "batched_24x24x24x48"
 HBM_PEAK_GBS = 8000.0
 REAL = {"f64": 8, "f32": 4, "f16": 2}
 FLOP_PER_SITE = 1320      # hop of eq. 2 per output site and rhs (secondary figure)
+# hop mappings of the timed 12-rhs even-odd launches (one kernel per line, profile and
+# counter set); the full-size parity test sets the same ones
+HEADLINE_MAPS = {"f32": "march2", "f64": "march1", "f16": "march2"}
+
+
+def hop_map_id(sap, name):
+    return sap.HOP_MAP_NAMES.index(name)
 
 
 def spinor_site_bytes(prec):
@@ -59,8 +66,9 @@ def parse():
                     help="operator timed by --only-dslash (profiler runs)")
     ap.add_argument("--prec", choices=["f64", "f32", "f16"], default="f32")
     ap.add_argument("--nrhs", type=int, default=12)
-    ap.add_argument("--hop-map", type=int, default=-1,
-                    help="with --only-dslash: force this hop mapping (HOP_MAP_*) instead of the tuned one")
+    ap.add_argument("--hop-map", default="",
+                    help="with --only-dslash: comma-separated hop mappings (names or HOP_MAP_* numbers) "
+                         "timed one after the other instead of the tuned one")
     ap.add_argument("--skip-solve", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--cpu-extended", action="store_true",
@@ -74,25 +82,59 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(U, psi, V, budget_s=20.0):
-    """The FP64 oracle's even-odd hop on the same lattice (one rhs, output parity 0),
-    timed on the host cores on a bounded number of applications."""
+def _oracle_hop_worker(task):
+    """One application of the FP64 oracle's even-odd hop (output parity 0) to one rhs, in a
+    worker process started fresh (spawn: nothing of the GPU process is inherited); the
+    fields are memory-mapped from the .npy files the parent wrote. Returns the CPU seconds."""
+    import numpy as np
     from oracle import dirac, lattice
+    udir, r = task
+    U = np.load(os.path.join(udir, "U.npy"), mmap_mode="r")
+    psi = np.load(os.path.join(udir, "psi.npy"), mmap_mode="r")[r]
     par = lattice.parity(U.shape[:4])
     m_in, m_out = lattice.site_mask(U.shape[:4], par == 1), lattice.site_mask(U.shape[:4], par == 0)
-    n, t_wall, t_cpu = 0, 0.0, 0.0
-    while t_wall < budget_s and n < 20:
-        c0, w0 = time.process_time(), time.perf_counter()
-        dirac.hop(U, psi * m_in) * m_out
-        t_cpu += time.process_time() - c0
-        t_wall += time.perf_counter() - w0
-        n += 1
-    per = t_wall / n
-    cores = max(1, round(t_cpu / t_wall))
-    return {"value": round(eo_bytes(V, "f64", 1) / per / 1e9, 3), "unit": "GB/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{n} applications of the even-odd hop (FP64 numpy oracle, 1 rhs) on 24^3x48, "
-                      f"{per:.2f} s each; GB/s over the same algorithmic bytes (768 B per site)"}
+    c0 = time.process_time()
+    dirac.hop(np.asarray(U), psi * m_in) * m_out
+    return time.process_time() - c0
+
+
+def _worker_ready(_):
+    import oracle.dirac  # noqa: F401  (imports done before the timed passes)
+    return os.getpid()
+
+
+def cpu_baseline(U, psi, V, rounds=2):
+    """The FP64 oracle's even-odd hop on the benchmark's own workload, the 12 rhs of
+    24^3x48, on the host cores: one worker process per rhs (the oracle as it stands, applied
+    to independent rhs in parallel), `rounds` passes over the 12 rhs. GB/s over the
+    algorithmic bytes of the FP64 12-rhs launch."""
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+    import numpy as np
+    nrhs = psi.shape[0]
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, min(nrhs, ncpu))
+    udir = tempfile.mkdtemp(prefix="sap_oracle_")
+    try:
+        np.save(os.path.join(udir, "U.npy"), U)
+        np.save(os.path.join(udir, "psi.npy"), psi)
+        with mp.get_context("spawn").Pool(workers) as pool:
+            pool.map(_worker_ready, range(workers))
+            w0 = time.perf_counter()
+            cpu = 0.0
+            for _ in range(rounds):
+                cpu += sum(pool.map(_oracle_hop_worker, [(udir, r) for r in range(nrhs)], chunksize=1))
+            wall = time.perf_counter() - w0
+    finally:
+        shutil.rmtree(udir, ignore_errors=True)
+    per = wall / rounds
+    return {"value": round(eo_bytes(V, "f64", nrhs) / per / 1e9, 3), "unit": "GB/s",
+            "cores": workers, "kind": "oracle",
+            "sample": f"{rounds} passes of the even-odd hop (FP64 numpy oracle) over the {nrhs} rhs of 24^3x48, "
+                      f"one worker process per rhs on {workers} of {ncpu} host CPUs: {per:.2f} s wall per "
+                      f"12-rhs pass ({cpu / rounds / nrhs:.2f} s CPU per rhs); GB/s over the FP64 12-rhs "
+                      f"launch's algorithmic bytes"}
 
 
 def cpu_extended():
@@ -141,22 +183,27 @@ def cpu_extended():
     return res
 
 
-def hbm_probe(torch, gib=2):
-    """Plain-kernel HBM ceilings on this GPU: a device copy and a read-only reduction
-    of 2 GiB (best of 5 each), for context next to the 8 TB/s peak."""
-    n = gib * (1 << 30) // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda")
+def hbm_probe(sap, torch, gib=2):
+    """Bandwidth a plain streaming kernel reaches on this GPU (the library's own probe:
+    16-byte accesses, grid-stride): copy, copy with non-temporal stores and read-only
+    reduction of 2 GiB (best of 5 each), for context next to the 8 TB/s peak."""
+    n = gib * (1 << 30)
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    best_c = best_r = 1e9
-    for _ in range(5):
-        e0.record(); b.copy_(a); e1.record(); torch.cuda.synchronize()
-        best_c = min(best_c, e0.elapsed_time(e1))
-        e0.record(); a.sum(); e1.record(); torch.cuda.synchronize()
-        best_r = min(best_r, e0.elapsed_time(e1))
+    res = {}
+    for name, mode, moved in (("copy_gbs", 0, 2 * n), ("copy_nt_gbs", 1, 2 * n), ("read_gbs", 2, n)):
+        best = 1e9
+        for _ in range(5):
+            e0.record()
+            sap.sap_stream_probe(b, a, n, mode)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        res[name] = round(moved / best / 1e6, 1)
     del a, b
-    return {"copy_gbs": round(2 * n * 8 / best_c / 1e6, 1), "read_gbs": round(n * 8 / best_r / 1e6, 1),
-            "bytes": n * 8}
+    res["bytes"] = n
+    return res
 
 
 KERNEL_SOURCES = ("dslash.hip", "half.hip", "site_io.h", "device_common.h", "internal.h")
@@ -362,25 +409,30 @@ def main():
 
     if args.only_dslash:       # one operator only, for profiler runs
         n_op = args.nrhs if args.op == "eo" else 1
-        sap.sap_tune(ctx, n_op)
-        if args.op == "eo" and args.prec == "f32" and args.nrhs == nrhs and args.hop_map < 0:
-            sap.sap_set_hop_map(ctx, 0, sap.SAP_F32, nrhs, sap.HOP_MAP_MARCH2)   # as in the headline
-        if args.hop_map >= 0:
-            sap.sap_set_hop_map(ctx, int(args.op == "M"), PREC[args.prec], n_op, args.hop_map)
+        maps = [m for m in args.hop_map.split(",") if m]
+        if not maps:
+            sap.sap_tune(ctx, n_op)
+            if args.op == "eo" and args.nrhs == nrhs and args.prec in HEADLINE_MAPS:
+                maps = [HEADLINE_MAPS[args.prec]]
         fn = eo(args.prec, args.nrhs) if args.op == "eo" else full(args.prec)
-        ms = time_op(sap, torch, fn, args.steps, args.warmup)
-        print(f"[bench] {args.op} {args.prec} nrhs={args.nrhs if args.op == 'eo' else 1}: "
-              f"{ms * 1e3:.1f} us/launch", file=sys.stderr, flush=True)
+        for m in maps or [None]:     # the given mappings only (no tuner launches in the profile)
+            if m is not None:
+                mid = int(m) if m.isdigit() else hop_map_id(sap, m)
+                sap.sap_set_hop_map(ctx, int(args.op == "M"), PREC[args.prec], n_op, mid)
+            ms = time_op(sap, torch, fn, args.steps, args.warmup)
+            print(f"[bench] {args.op} {args.prec} nrhs={args.nrhs if args.op == 'eo' else 1} map {m}: "
+                  f"{ms * 1e3:.1f} us/launch", file=sys.stderr, flush=True)
         if args.copy_calibration:
-            copy_calibration(torch)
+            copy_calibration(sap, torch)
         return
 
     print("[bench] tuning the hop mapping", file=sys.stderr, flush=True)
     tuning = {"nrhs_%d" % n: sap.sap_tune(ctx, n) for n in (1, nrhs)}
-    # the headline launch uses the x0-marching mapping with 2 rhs per work-item, the
-    # tuner's choice on this workload; the runner-up mappings are within a few percent, so
-    # fixing it keeps the line, its profile and its counters on one kernel
-    sap.sap_set_hop_map(ctx, 0, sap.SAP_F32, nrhs, sap.HOP_MAP_MARCH2)
+    # the 12-rhs launches use fixed mappings (HEADLINE_MAPS, the tuner's choices on this
+    # workload, whose runner-up mappings are within a few percent), so that the line, its
+    # profile and its counters describe one kernel
+    for prec, name in HEADLINE_MAPS.items():
+        sap.sap_set_hop_map(ctx, 0, PREC[prec], nrhs, hop_map_id(sap, name))
     ms = time_op(sap, torch, eo("f32", nrhs), args.steps, args.warmup)
     gbs = eo_bytes(V, "f32", nrhs) / (ms * 1e-3) / 1e9
     print(f"[bench] D_eo f32 {nrhs} rhs: {ms * 1e3:.1f} us/launch, {gbs:.0f} GB/s", file=sys.stderr, flush=True)
@@ -415,30 +467,31 @@ def main():
     result["hop_tuning_us"] = {n: {k: {m: round(v, 1) for m, v in d.items()} for k, d in t.items()}
                                for n, t in tuning.items()}
     fields.clear()
-    result["hbm_probe"] = hbm_probe(torch)
+    result["hbm_probe"] = hbm_probe(sap, torch)
     if not args.skip_solve:
         result["block_solve"] = block_solve_comparison(sap, torch, ctx, cfg, L)
     if not args.skip_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(U, psi[0], V)
+        result["cpu_baseline"] = cpu_baseline(U, psi, V)
         if args.cpu_extended:
             print("[bench] timing further oracle operations", file=sys.stderr, flush=True)
             result["cpu_extended"] = cpu_extended()
     print(json.dumps(result), flush=True)
 
 
-def copy_calibration(torch):
-    """Plain device copy of 1 GiB whose source was pushed out of the 256 MB MALL by a second
-    1 GiB fill: its counters read 1 GiB fetched and 1 GiB written."""
-    n = 1024 * 1024 * 1024 // 8
-    a = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
-    c = torch.full((n,), 2.0, dtype=torch.float64, device="cuda")
+def copy_calibration(sap, torch):
+    """One copy of 1 GiB by the library's stream probe (k_stream_copy) whose source was
+    pushed out of the 256 MB MALL by a second 1 GiB fill: its counters must read 1 GiB
+    fetched and 1 GiB written, which fixes the scale of FETCH_SIZE / WRITE_SIZE."""
+    n = 1024 * 1024 * 1024
+    a = torch.full((n // 4,), 1.0, dtype=torch.float32, device="cuda")
+    c = torch.full((n // 4,), 2.0, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
-    b.copy_(a)
+    sap.sap_stream_probe(b, a, n, 0)
     torch.cuda.synchronize()
     del a, b, c
-    print(f"[bench] copy calibration: one copy of {n * 8} bytes", file=sys.stderr, flush=True)
+    print(f"[bench] copy calibration: one stream-probe copy of {n} bytes", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

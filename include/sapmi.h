@@ -171,6 +171,14 @@ typedef struct {
   double u_metropolis;
   const double* step_scale; /* host [L0][4] or NULL, as in sap_hmc_params */
   int time_shift;
+  const sap_solve_opts* part_solve; /* host array of 8 entries, or NULL: the solves of S1..S4
+                          * inside the molecular dynamics (entries 0..3) and for their heat
+                          * baths and the actions in dH (entries 4..7); NULL gives force_solve /
+                          * action_solve to every part. Sec. 3's assignment is SAP_GEOM for S1,
+                          * S2 and S3 and SAP_SAP_BICGSTAB for S4. A part whose options name
+                          * SAP_SAP_BICGSTAB solves its full-lattice systems (M x = b) with it
+                          * and its block systems (the heat bath of S4) or even-site systems
+                          * with even-odd BiCGstab under the same tolerances. */
 } sap_hmc4_params;
 
 typedef struct {
@@ -183,7 +191,7 @@ typedef struct {
 
 /* ---- context ---------------------------------------------------------------- */
 
-/* Version of this ABI (major*100 + minor). */
+/* Version of this ABI (major*100 + minor): 101 (sap_hmc4_params.part_solve added). */
 int sap_version(void);
 
 /* Host-only geometry check (no HIP call): SAP_OK or SAP_E_ARG. */
@@ -201,9 +209,14 @@ size_t sap_field_bytes(const sap_ctx* ctx, sap_prec prec, int nrhs);
 size_t sap_momenta_bytes(const sap_ctx* ctx);
 
 /* Load the gauge field from the canonical layout (device, complex128) into the
- * context's FP64, FP32 and FP16 copies. The links must be SU(3): the FP32 and FP16 copies
- * keep the first two rows of each link and the kernels rebuild the third from unitarity
- * and unit determinant (FP64 operators use the links as given). */
+ * context's FP64 links and the FP64, FP32 and FP16 copies the hop kernels read. The links
+ * must be SU(3): the hop copies keep the first two rows of each link and the hop kernels
+ * of every precision rebuild the third from unitarity and unit determinant (the force,
+ * gauge-force and link-update kernels read the whole FP64 links). Checked on the device:
+ * if the largest entry modulus of U U^+ - 1 or |det U - 1| over all links exceeds 1e-10
+ * (or is not finite) the call returns SAP_E_ARG and the context holds no gauge field
+ * (later calls that need one return SAP_E_STATE) until a valid field is set.
+ * Synchronises. */
 int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream);
 /* Copy the context's FP64 gauge field back to the canonical layout. */
 int sap_get_gauge(sap_ctx* ctx, double* U, void* stream);
@@ -257,10 +270,15 @@ int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parit
  * projection in registers; the full operator runs them as march1 / march2), 16 band1
  * (even-odd hop: each XCD owns a band of x0 slices and each work-item steps through it at
  * a fixed spatial site, loading every input once and carrying the time hops in registers;
- * the full operator runs it as march1). FP16 storage has site and march1 / 2 / 4 only
- * (the other maps run as one of these). us_out (host, may be NULL): 102 floats,
- * microseconds per launch (-1: not applicable), ordered [full f64, full f32, even-odd
- * f64, even-odd f32, full f16, even-odd f16] x the 17 mappings. Uses the solver
+ * the full operator runs it as march1), 17 / 18 / 19 slab1 / slab1w / slab2 (even-odd hop:
+ * band order with a workgroup owning a spatial tile of every slice of the band, TA x1
+ * values by TB x2 values by all of x3, staged in LDS so that the spatial hops inside the
+ * tile read the LDS copy; 1 rhs per work-item with tiles of up to 40 KB / 80 KB of LDS
+ * (slab1 / slab1w) or 2 rhs per work-item (slab2); the full operator runs them as march1 /
+ * march1 / march2). FP16 storage has site and march1 / 2 / 4 only (the other maps run as
+ * one of these). us_out (host, may be NULL): 120 floats, microseconds per launch (-1: not
+ * applicable), ordered [full f64, full f32, even-odd f64, even-odd f32, full f16, even-odd
+ * f16] x the 20 mappings. Uses the solver
  * workspace; synchronises. Untuned calls use site for one rhs and lane4 (FP16: site) for
  * several. */
 int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
@@ -269,7 +287,8 @@ int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
  * 2 wave4, 3 stream (even-odd hop only, full = 0), 4..6 = 0..2 with rhs-slowest workgroup
  * order, 7 reg2, 8 reg4, 9 / 10 reg2 / reg4 group-slowest, 11 / 12 / 13 x0-marching with
  * 1 / 2 / 4 rhs per work-item, 14 / 15 x0-walking with 1 / 2 rhs (march1 / march2 for
- * the full operator), 16 x0-band (march1 for the full operator); -1 restores the
+ * the full operator), 16 x0-band (march1 for the full operator), 17 / 18 / 19 slab1 /
+ * slab1w / slab2 (march1 / march1 / march2 for the full operator); -1 restores the
  * default), for the full operator (full = 1) or the even-odd hop (full = 0) at precision
  * prec. */
 int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);
@@ -377,7 +396,10 @@ int sap_plaquette(sap_ctx* ctx, double* plaq_out, void* stream);
  * (= ||W2eo^-1 W3eo phi||^2). Fields are FP64 sap-layout spinors whose odd half is zero.
  * Heat bath: phi = W3eo P_e xi (kind 1) or W3eo^-1 W2eo P_e xi (kind 2), so that S equals
  * ||P_e xi||^2. Force: F += coef * dS/dw (F NULL: action only); *S_out (host, may be
- * NULL) receives S. Solves by opts on the even-odd system (not SAP_GEOM). Synchronise. */
+ * NULL) receives S. Solves by opts on the even-site systems: CG, BiCGstab, or (SAP_GEOM, the
+ * solver Sec. 3 uses for these parts) the geometric series
+ * x = sum_n (k^2 D_eo D_oe / (1 + rho))^n b / (1 + rho), which converges where the spectral
+ * radius of k^2 D_eo D_oe is below 1 + rho; SAP_SAP_BICGSTAB runs as BiCGstab. Synchronise. */
 int eo_pf_heat_bath(sap_ctx* ctx, double* phi, const double* xi, int kind, double rho,
                     const sap_solve_opts* opts, void* stream);
 int eo_pf_force(sap_ctx* ctx, double* F, double coef, const double* phi, int kind, double rho,
@@ -414,6 +436,18 @@ int hmc_trajectory(sap_ctx* ctx, double* U, const sap_hmc_params* p, sap_hmc_inf
  * the resulting one. Needs l0_sub > 0. info: host. */
 int hmc_trajectory_4pf(sap_ctx* ctx, double* U, const sap_hmc4_params* p, sap_hmc4_info* info,
                        void* stream);
+
+/* ---- benchmark aid ---------------------------------------------------------------- */
+
+/* Streaming probe of the bandwidth a plain kernel reaches on this GPU, to set the hop
+ * kernels against: mode 0 copies bytes from src to dst, mode 1 does the same with
+ * non-temporal stores, mode 2 reads src and writes one float partial sum per workgroup to
+ * dst (sap_stream_probe_blocks() floats). 16-byte accesses in a grid-stride loop of
+ * sap_stream_probe_blocks() workgroups. bytes must be a positive multiple of 16 and both
+ * pointers 16-byte aligned device pointers (SAP_E_ARG otherwise); queued on the stream,
+ * no synchronisation. Needs no context. */
+int sap_stream_probe(void* dst, const void* src, size_t bytes, int mode, void* stream);
+int sap_stream_probe_blocks(void);
 
 #ifdef __cplusplus
 }

@@ -73,7 +73,8 @@ class sap_hmc4_params(ctypes.Structure):
                 ("force_solve", sap_solve_opts), ("action_solve", sap_solve_opts),
                 ("p0", ctypes.c_void_p), ("xi1", ctypes.c_void_p), ("xi2", ctypes.c_void_p),
                 ("g3", ctypes.c_void_p), ("g4", ctypes.c_void_p), ("u_metropolis", ctypes.c_double),
-                ("step_scale", ctypes.c_void_p), ("time_shift", ctypes.c_int)]
+                ("step_scale", ctypes.c_void_p), ("time_shift", ctypes.c_int),
+                ("part_solve", ctypes.POINTER(sap_solve_opts))]
 
 
 class sap_hmc4_info(ctypes.Structure):
@@ -124,6 +125,8 @@ _SIGS = {
     "sap_force_profile": ([_P, _P, _P, _P], _I),
     "sap_force_profile_noalloc": ([_P, _P, _P, _P], _I),
     "sap_force_profile_noalloc_max": ([], ctypes.c_size_t),
+    "sap_stream_probe": ([_P, _P, ctypes.c_size_t, _I, _P], _I),
+    "sap_stream_probe_blocks": ([], _I),
     "sap_tune": ([_P, _I, _P, _P], _I),
     "sap_set_hop_map": ([_P, _I, _I, _I, _I], _I),
     "hmc_trajectory": ([_P, _P, ctypes.POINTER(sap_hmc_params), ctypes.POINTER(sap_hmc_info), _P], _I),
@@ -148,8 +151,44 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+def _buf(ctx, t, nbytes, what, optional=False):
+    """Device pointer of t after checking it: the library reads and writes through raw
+    pointers, so the tensor must be a contiguous floating-point or complex tensor on the
+    context's device holding at least nbytes (an undersized buffer would become an
+    out-of-bounds device access). None gives NULL when optional, else SapError."""
+    if t is None:
+        if optional:
+            return None
+        raise SapError(SAP_E_ARG, f"{what} is None")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise SapError(SAP_E_ARG, f"{what}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.device.type != "cuda" or (ctx is not None and t.device.index != ctx.device):
+        raise SapError(SAP_E_ARG, f"{what}: must live on the context's device cuda:{ctx.device if ctx else '?'}, "
+                                  f"not {t.device}")
+    if not (t.is_floating_point() or t.is_complex()):
+        raise SapError(SAP_E_ARG, f"{what}: dtype {t.dtype} is not a floating-point or complex type")
+    if not t.is_contiguous():
+        raise SapError(SAP_E_ARG, f"{what}: must be contiguous")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise SapError(SAP_E_ARG, f"{what}: {have} bytes, the call needs {nbytes}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _field(ctx, t, nrhs, prec, what, optional=False):
+    """A library-layout spinor field of nrhs right-hand sides at precision prec."""
+    if not (isinstance(nrhs, int) and nrhs >= 1):
+        raise SapError(SAP_E_ARG, f"nrhs must be a positive int, got {nrhs!r}")
+    if prec not in (SAP_F64, SAP_F32, SAP_F16):
+        raise SapError(SAP_E_ARG, f"unknown precision {prec!r}")
+    return _buf(ctx, t, _lib.sap_field_bytes(ctx.ptr, prec, nrhs), what, optional)
+
+
+def _mom(ctx, t, what, optional=False):
+    """A library-layout momentum / force field."""
+    return _buf(ctx, t, _lib.sap_momenta_bytes(ctx.ptr), what, optional)
 
 
 def _check(ctx_ptr, rc, info=None):
@@ -178,67 +217,74 @@ def solve_opts(tol=1e-10, max_iter=100000, inner_prec=SAP_F32, inner_tol=1e-5, m
 # ---- C entry points with their own names -------------------------------------------
 
 def apply_M(ctx, out, inp, nrhs, prec):
-    _check(ctx.ptr, _lib.apply_M(ctx.ptr, _ptr(out), _ptr(inp), nrhs, prec, _stream()))
+    po, pi = _field(ctx, out, nrhs, prec, "out"), _field(ctx, inp, nrhs, prec, "in")
+    _check(ctx.ptr, _lib.apply_M(ctx.ptr, po, pi, nrhs, prec, _stream()))
 
 
 def apply_W1_block(ctx, out, inp, nrhs, level=1, block=-1, color=SAP_ALL, prec=SAP_F64):
-    _check(ctx.ptr, _lib.apply_W1_block(ctx.ptr, _ptr(out), _ptr(inp), nrhs, level, block, color,
-                                        prec, _stream()))
+    po, pi = _field(ctx, out, nrhs, prec, "out"), _field(ctx, inp, nrhs, prec, "in")
+    _check(ctx.ptr, _lib.apply_W1_block(ctx.ptr, po, pi, nrhs, level, block, color, prec, _stream()))
 
 
 def apply_Dslash_eo(ctx, out, inp, nrhs, parity, prec):
-    _check(ctx.ptr, _lib.apply_Dslash_eo(ctx.ptr, _ptr(out), _ptr(inp), nrhs, parity, prec, _stream()))
+    po, pi = _field(ctx, out, nrhs, prec, "out"), _field(ctx, inp, nrhs, prec, "in")
+    _check(ctx.ptr, _lib.apply_Dslash_eo(ctx.ptr, po, pi, nrhs, parity, prec, _stream()))
 
 
 def solve_full(ctx, x, b, nrhs, opts):
+    px, pb = _field(ctx, x, nrhs, SAP_F64, "x"), _field(ctx, b, nrhs, SAP_F64, "b")
     info = (sap_solve_info * nrhs)()
-    rc = _lib.solve_full(ctx.ptr, _ptr(x), _ptr(b), nrhs, ctypes.byref(opts), info, _stream())
+    rc = _lib.solve_full(ctx.ptr, px, pb, nrhs, ctypes.byref(opts), info, _stream())
     _check(ctx.ptr, rc, info)
     return list(info)
 
 
 def solve_blocks(ctx, x, b, nrhs, level, color, opts, block=-1):
+    if level not in (1, 2) or (level == 2 and not ctx.l0_sub):
+        raise SapError(SAP_E_ARG, "level must be 1, or 2 with l0_sub set")
+    px, pb = _field(ctx, x, nrhs, SAP_F64, "x"), _field(ctx, b, nrhs, SAP_F64, "b")
     nb = ctx.nblocks(level)
     info = (sap_solve_info * (nb * nrhs))()
-    rc = _lib.solve_blocks(ctx.ptr, _ptr(x), _ptr(b), nrhs, level, color, block, ctypes.byref(opts),
-                           info, _stream())
+    rc = _lib.solve_blocks(ctx.ptr, px, pb, nrhs, level, color, block, ctypes.byref(opts), info, _stream())
     _check(ctx.ptr, rc, info)
     return list(info)
 
 
 def block_pf_force(ctx, F, coef, phi, opts):
     S = ctypes.c_double(0.0)
-    _check(ctx.ptr, _lib.block_pf_force(ctx.ptr, _ptr(F), coef, _ptr(phi), ctypes.byref(opts),
-                                        ctypes.byref(S), _stream()))
+    pF, pp = _mom(ctx, F, "F"), _field(ctx, phi, 1, SAP_F64, "phi")
+    _check(ctx.ptr, _lib.block_pf_force(ctx.ptr, pF, coef, pp, ctypes.byref(opts), ctypes.byref(S), _stream()))
     return S.value
 
 
 def schwarz_boundary_force(ctx, F, coef, chi, opts):
     S = ctypes.c_double(0.0)
-    _check(ctx.ptr, _lib.schwarz_boundary_force(ctx.ptr, _ptr(F), coef, _ptr(chi),
-                                                ctypes.byref(opts), ctypes.byref(S), _stream()))
+    pF, pc = _mom(ctx, F, "F"), _field(ctx, chi, 1, SAP_F64, "chi")
+    _check(ctx.ptr, _lib.schwarz_boundary_force(ctx.ptr, pF, coef, pc, ctypes.byref(opts), ctypes.byref(S),
+                                                _stream()))
     return S.value
 
 
 def gauge_force(ctx, F, coef, beta):
     S = ctypes.c_double(0.0)
-    _check(ctx.ptr, _lib.gauge_force(ctx.ptr, _ptr(F), coef, beta, ctypes.byref(S), _stream()))
+    _check(ctx.ptr, _lib.gauge_force(ctx.ptr, _mom(ctx, F, "F"), coef, beta, ctypes.byref(S), _stream()))
     return S.value
 
 
 def schwarz_heat_bath(ctx, chi, g, opts):
-    _check(ctx.ptr, _lib.schwarz_heat_bath(ctx.ptr, _ptr(chi), _ptr(g), ctypes.byref(opts), _stream()))
+    pc, pg = _field(ctx, chi, 1, SAP_F64, "chi"), _field(ctx, g, 1, SAP_F64, "g")
+    _check(ctx.ptr, _lib.schwarz_heat_bath(ctx.ptr, pc, pg, ctypes.byref(opts), _stream()))
 
 
 def schwarz_action(ctx, chi, opts):
     S = ctypes.c_double(0.0)
-    _check(ctx.ptr, _lib.schwarz_action(ctx.ptr, _ptr(chi), ctypes.byref(opts), ctypes.byref(S),
-                                        _stream()))
+    _check(ctx.ptr, _lib.schwarz_action(ctx.ptr, _field(ctx, chi, 1, SAP_F64, "chi"), ctypes.byref(opts),
+                                        ctypes.byref(S), _stream()))
     return S.value
 
 
 def sap_update_links(ctx, p, dt):
-    _check(ctx.ptr, _lib.sap_update_links(ctx.ptr, _ptr(p), dt, _stream()))
+    _check(ctx.ptr, _lib.sap_update_links(ctx.ptr, _mom(ctx, p, "p"), dt, _stream()))
 
 
 def sap_plaquette(ctx):
@@ -252,9 +298,7 @@ def sap_tune(ctx, nrhs):
     us = (ctypes.c_float * (6 * HOP_NMAP))()
     _check(ctx.ptr, _lib.sap_tune(ctx.ptr, nrhs, us, _stream()))
     names = ["full_f64", "full_f32", "eo_f64", "eo_f32", "full_f16", "eo_f16"]
-    maps = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4",
-            "reg2_sweep", "reg4_sweep", "march1", "march2", "march4", "walk1", "walk2", "band1"]
-    return {n: {m: us[HOP_NMAP * i + k] for k, m in enumerate(maps) if us[HOP_NMAP * i + k] >= 0}
+    return {n: {m: us[HOP_NMAP * i + k] for k, m in enumerate(HOP_MAP_NAMES) if us[HOP_NMAP * i + k] >= 0}
             for i, n in enumerate(names)}
 
 
@@ -263,7 +307,11 @@ HOP_MAP_REG2, HOP_MAP_REG4, HOP_MAP_REG2_SWEEP, HOP_MAP_REG4_SWEEP = 7, 8, 9, 10
 HOP_MAP_MARCH1, HOP_MAP_MARCH2, HOP_MAP_MARCH4 = 11, 12, 13
 HOP_MAP_WALK1, HOP_MAP_WALK2 = 14, 15
 HOP_MAP_BAND1 = 16
-HOP_NMAP = 17
+HOP_MAP_SLAB1, HOP_MAP_SLAB1W, HOP_MAP_SLAB2 = 17, 18, 19
+HOP_NMAP = 20
+HOP_MAP_NAMES = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4",
+                 "reg2_sweep", "reg4_sweep", "march1", "march2", "march4", "walk1", "walk2", "band1",
+                 "slab1", "slab1w", "slab2"]
 
 
 def sap_set_hop_map(ctx, full, prec, nrhs, hop_map):
@@ -275,14 +323,15 @@ def sap_force_profile(ctx, F):
     [mean |F| over the spatial links of each slice, mean |F| over its time links]."""
     L0 = ctx.L[0]
     out = (ctypes.c_double * (2 * L0))()
-    _check(ctx.ptr, _lib.sap_force_profile(ctx.ptr, _ptr(F), out, _stream()))
+    _check(ctx.ptr, _lib.sap_force_profile(ctx.ptr, _mom(ctx, F, "F"), out, _stream()))
     return [list(out[:L0]), list(out[L0:])]
 
 
 def sap_force_profile_noalloc(ctx, F, prof):
     """The x0 profile of F written to the device tensor prof (2*L0 float64) on the current
     stream, without allocating and without synchronising (see sap_force_profile)."""
-    _check(ctx.ptr, _lib.sap_force_profile_noalloc(ctx.ptr, _ptr(F), _ptr(prof), _stream()))
+    pF, pq = _mom(ctx, F, "F"), _buf(ctx, prof, 2 * ctx.L[0] * 8, "prof")
+    _check(ctx.ptr, _lib.sap_force_profile_noalloc(ctx.ptr, pF, pq, _stream()))
 
 
 def sap_force_profile_noalloc_max() -> int:
@@ -290,38 +339,49 @@ def sap_force_profile_noalloc_max() -> int:
 
 
 def eo_pf_heat_bath(ctx, phi, xi, kind, rho, opts):
-    _check(ctx.ptr, _lib.eo_pf_heat_bath(ctx.ptr, _ptr(phi), _ptr(xi), kind, rho, ctypes.byref(opts), _stream()))
+    pp, px = _field(ctx, phi, 1, SAP_F64, "phi"), _field(ctx, xi, 1, SAP_F64, "xi")
+    _check(ctx.ptr, _lib.eo_pf_heat_bath(ctx.ptr, pp, px, kind, rho, ctypes.byref(opts), _stream()))
 
 
 def eo_pf_force(ctx, F, coef, phi, kind, rho, opts):
     """F += coef * dS/dw of S1 (kind 1) or S2 (kind 2); F None: action only. Returns S."""
     S = ctypes.c_double(0.0)
-    _check(ctx.ptr, _lib.eo_pf_force(ctx.ptr, _ptr(F) if F is not None else None, coef, _ptr(phi), kind, rho,
-                                     ctypes.byref(opts), ctypes.byref(S), _stream()))
+    pF, pp = _mom(ctx, F, "F", optional=True), _field(ctx, phi, 1, SAP_F64, "phi")
+    _check(ctx.ptr, _lib.eo_pf_force(ctx.ptr, pF, coef, pp, kind, rho, ctypes.byref(opts), ctypes.byref(S),
+                                     _stream()))
     return S.value
 
 
 def schwarz2_heat_bath(ctx, chi, g, opts):
-    _check(ctx.ptr, _lib.schwarz2_heat_bath(ctx.ptr, _ptr(chi), _ptr(g), ctypes.byref(opts), _stream()))
+    pc, pg = _field(ctx, chi, 1, SAP_F64, "chi"), _field(ctx, g, 1, SAP_F64, "g")
+    _check(ctx.ptr, _lib.schwarz2_heat_bath(ctx.ptr, pc, pg, ctypes.byref(opts), _stream()))
 
 
 def schwarz2_force(ctx, F, coef, chi, opts):
     """F += coef * dS/dw of the level-2 Schwarz term (S3); F None: action only. Returns S."""
     S = ctypes.c_double(0.0)
-    _check(ctx.ptr, _lib.schwarz2_force(ctx.ptr, _ptr(F) if F is not None else None, coef, _ptr(chi),
-                                        ctypes.byref(opts), ctypes.byref(S), _stream()))
+    pF, pc = _mom(ctx, F, "F", optional=True), _field(ctx, chi, 1, SAP_F64, "chi")
+    _check(ctx.ptr, _lib.schwarz2_force(ctx.ptr, pF, coef, pc, ctypes.byref(opts), ctypes.byref(S), _stream()))
     return S.value
 
 
 def hmc4_params(beta, tau, rho, n, p0, xi1, xi2, g3, g4, u_metropolis, force_solve, action_solve,
-                scheme=(1, 1, 0, 0, 0), lam=1.0 / 6.0, step_scale=None, time_shift=0):
+                scheme=(1, 1, 0, 0, 0), lam=1.0 / 6.0, step_scale=None, time_shift=0, part_solve=None):
+    """sap_hmc4_params from torch tensors. part_solve: None, or 8 sap_solve_opts (the force
+    solves of S1..S4, then their heat-bath and action solves), kept alive on the result."""
     P = sap_hmc4_params()
+    if part_solve is not None:
+        if len(part_solve) != 8:
+            raise SapError(SAP_E_ARG, "part_solve needs 8 entries (force S1..S4, action S1..S4)")
+        P._parts = (sap_solve_opts * 8)(*part_solve)
+        P.part_solve = ctypes.cast(P._parts, ctypes.POINTER(sap_solve_opts))
     P.beta, P.tau, P.lambda_, P.rho = beta, tau, lam, rho
     P.n = (ctypes.c_int * 5)(*n)
     P.scheme = (ctypes.c_int * 5)(*scheme)
     P.force_solve, P.action_solve = force_solve, action_solve
     P.p0, P.xi1, P.xi2 = p0.data_ptr(), xi1.data_ptr(), xi2.data_ptr()
     P.g3, P.g4 = g3.data_ptr(), g4.data_ptr()
+    P._tensors = {"p0": p0, "xi1": xi1, "xi2": xi2, "g3": g3, "g4": g4}
     P.u_metropolis = u_metropolis
     if step_scale is not None:
         import numpy as np
@@ -331,9 +391,26 @@ def hmc4_params(beta, tau, rho, n, p0, xi1, xi2, g3, g4, u_metropolis, force_sol
     return P
 
 
+def _check_hmc_buffers(ctx, U, params):
+    """The trajectory reads and writes the canonical gauge field U, reads the momenta (sap
+    layout) and the canonical noise spinors whose pointers the params hold."""
+    pU = _buf(ctx, U, ctx.V * 36 * 16, "U")
+    ten = getattr(params, "_tensors", None)
+    if ten is None:
+        raise SapError(SAP_E_ARG, "params must come from hmc_params / hmc4_params (they keep the tensors)")
+    _mom(ctx, ten["p0"], "p0")
+    for k, v in ten.items():
+        if k != "p0":
+            _buf(ctx, v, ctx.V * 12 * 16, k)
+    if getattr(params, "_scale", None) is not None and params._scale.size < 4 * ctx.L[0]:
+        raise SapError(SAP_E_ARG, f"step_scale must hold {4 * ctx.L[0]} values ([L0][4])")
+    return pU
+
+
 def hmc_trajectory_4pf(ctx, U, params):
+    pU = _check_hmc_buffers(ctx, U, params)
     info = sap_hmc4_info()
-    _check(ctx.ptr, _lib.hmc_trajectory_4pf(ctx.ptr, _ptr(U), ctypes.byref(params), ctypes.byref(info), _stream()))
+    _check(ctx.ptr, _lib.hmc_trajectory_4pf(ctx.ptr, pU, ctypes.byref(params), ctypes.byref(info), _stream()))
     return info
 
 
@@ -348,6 +425,7 @@ def hmc_params(beta, tau, n_outer, n_inner, p0, xi1, xi2, u_metropolis, force_so
     prm = sap_hmc_params(beta, tau, lam, n_outer, n_inner, scheme_outer, scheme_inner, force_solve,
                          action_solve, p0.data_ptr(), xi1.data_ptr(), xi2.data_ptr(), u_metropolis,
                          None, time_shift)
+    prm._tensors = {"p0": p0, "xi1": xi1, "xi2": xi2}
     if step_scale is not None:
         import numpy as np
         prm._scale = np.ascontiguousarray(step_scale, dtype=np.float64)
@@ -356,10 +434,20 @@ def hmc_params(beta, tau, n_outer, n_inner, p0, xi1, xi2, u_metropolis, force_so
 
 
 def hmc_trajectory(ctx, U, params):
+    pU = _check_hmc_buffers(ctx, U, params)
     info = sap_hmc_info()
-    _check(ctx.ptr, _lib.hmc_trajectory(ctx.ptr, _ptr(U), ctypes.byref(params), ctypes.byref(info),
-                                        _stream()))
+    _check(ctx.ptr, _lib.hmc_trajectory(ctx.ptr, pU, ctypes.byref(params), ctypes.byref(info), _stream()))
     return info
+
+
+def sap_stream_probe(dst, src, nbytes, mode):
+    """Plain streaming kernel over device tensors (mode 0 copy, 1 copy with non-temporal
+    stores, 2 read with one float partial per workgroup written to dst)."""
+    need = nbytes if mode < 2 else 4 * _lib.sap_stream_probe_blocks()
+    pd, ps = _buf(None, dst, need, "dst"), _buf(None, src, nbytes, "src")
+    rc = _lib.sap_stream_probe(pd, ps, nbytes, mode, _stream())
+    if rc != SAP_OK:
+        raise SapError(rc, "sap_stream_probe failed")
 
 
 # ---- context ------------------------------------------------------------------------
@@ -378,6 +466,8 @@ class Context:
         rc = _lib.sap_create(ctypes.byref(g), ctypes.byref(p))
         _check(None, rc)
         self.ptr = p
+        import torch
+        self.device = torch.cuda.current_device()     # sap_create bound the context to it
 
     def close(self):
         if getattr(self, "ptr", None):
@@ -408,20 +498,27 @@ class Context:
         return torch.zeros(_lib.sap_momenta_bytes(self.ptr) // 8, dtype=torch.float64, device="cuda")
 
     def set_gauge(self, U):
-        """U: canonical complex128 gauge field on the device (any shape with V*4*9 entries)."""
-        _check(self.ptr, _lib.sap_set_gauge(self.ptr, _ptr(U), _stream()))
+        """U: canonical complex128 gauge field on the device (any shape with V*4*9 entries);
+        the links must be SU(3) (checked by the library)."""
+        _check(self.ptr, _lib.sap_set_gauge(self.ptr, _buf(self, U, self.V * 36 * 16, "U"), _stream()))
 
     def get_gauge(self, U):
-        _check(self.ptr, _lib.sap_get_gauge(self.ptr, _ptr(U), _stream()))
+        _check(self.ptr, _lib.sap_get_gauge(self.ptr, _buf(self, U, self.V * 36 * 16, "U"), _stream()))
 
     def pack_spinor(self, out, psi, nrhs, prec=SAP_F64):
-        _check(self.ptr, _lib.sap_pack_spinor(self.ptr, _ptr(out), _ptr(psi), nrhs, prec, _stream()))
+        po = _field(self, out, nrhs, prec, "out")
+        _check(self.ptr, _lib.sap_pack_spinor(self.ptr, po, _buf(self, psi, nrhs * self.V * 12 * 16, "psi"),
+                                              nrhs, prec, _stream()))
 
     def unpack_spinor(self, out, f, nrhs, prec=SAP_F64):
-        _check(self.ptr, _lib.sap_unpack_spinor(self.ptr, _ptr(out), _ptr(f), nrhs, prec, _stream()))
+        pf = _field(self, f, nrhs, prec, "f")
+        _check(self.ptr, _lib.sap_unpack_spinor(self.ptr, _buf(self, out, nrhs * self.V * 12 * 16, "out"), pf,
+                                                nrhs, prec, _stream()))
 
     def pack_momenta(self, out, p):
-        _check(self.ptr, _lib.sap_pack_momenta(self.ptr, _ptr(out), _ptr(p), _stream()))
+        _check(self.ptr, _lib.sap_pack_momenta(self.ptr, _mom(self, out, "out"),
+                                               _buf(self, p, self.V * 32 * 8, "p"), _stream()))
 
     def unpack_momenta(self, out, f):
-        _check(self.ptr, _lib.sap_unpack_momenta(self.ptr, _ptr(out), _ptr(f), _stream()))
+        _check(self.ptr, _lib.sap_unpack_momenta(self.ptr, _buf(self, out, self.V * 32 * 8, "out"),
+                                                 _mom(self, f, "f"), _stream()))

@@ -39,7 +39,7 @@ static std::string geom_problem(const sap_geom* g) {
 
 extern "C" {
 
-int sap_version(void) { return 100; }
+int sap_version(void) { return 101; }
 
 int sap_check_geom(const sap_geom* g) {
   std::string p = geom_problem(g);
@@ -70,6 +70,7 @@ int sap_solver_create(sap_ctx* ctx);     // solver.hip
 int sap_force_create(sap_ctx* ctx);      // hmc.hip
 void sap_force_destroy(sap_ctx* ctx);    // hmc.hip
 int sap_noalloc_setup(sap_ctx* ctx);     // noalloc.hip
+int su3_deviation_host(sap_ctx* c, double* dev, hipStream_t s);   // hmc.hip
 extern "C" {
 
 int sap_create(const sap_geom* g, sap_ctx** out) {
@@ -132,9 +133,21 @@ int sap_set_gauge(sap_ctx* ctx, const double* U, void* stream) {
   if (!ctx) return sap_fail(nullptr, SAP_E_ARG, "ctx is NULL");
   if (!U) return sap_fail(ctx, SAP_E_ARG, "U is NULL");
   hipStream_t s = (hipStream_t)stream;
+  ctx->have_gauge = false;
   launch_pack_gauge(ctx->g, ctx->U64, nullptr, (const double2*)U, s);
   launch_gauge_to_f32(ctx->g, ctx->U64c, ctx->U32, ctx->U16, ctx->U64, s);
   SAP_HIP_CHECK(ctx, hipGetLastError());
+  // the hop kernels rebuild the third row of every link from the first two, which holds
+  // for SU(3) only: refuse anything else
+  double dev = 0.0;
+  int rc = su3_deviation_host(ctx, &dev, s);
+  if (rc) return rc;
+  if (!(dev <= SAP_SU3_TOL)) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "links are not SU(3): max |U U^+ - 1|, |det U - 1| = %.3e > %.0e", dev,
+                  SAP_SU3_TOL);
+    return sap_fail(ctx, SAP_E_ARG, msg);
+  }
   ctx->have_gauge = true;
   return SAP_OK;
 }

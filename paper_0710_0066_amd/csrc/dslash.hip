@@ -821,6 +821,212 @@ __global__ __launch_bounds__(128) void hop_band_kernel(HopArgs<R> A, int nck) {
   }
 }
 
+// x0-band even-odd hop with the slice tile staged in LDS ("slab"). XCD k (workgroup id % 8)
+// owns the output slices [L0 k / 8, L0 (k + 1) / 8), as in the band order. A workgroup owns
+// a spatial tile of the slice, TA x1 values x TB x2 values x every x3 (S = TA TB L3h sites of
+// one parity), for one group of NR rhs, and walks the band: work-item t owns slice-local
+// site s(t) of the output parity and of the input parity alike (a step in x0 keeps s). At
+// step x0 it loads its input (x0 + 1, s) once: that input gives the forward time hop of
+// output (x0, s) and is written to the LDS copy of slice x0 + 1; the six spatial hops of
+// output (x0, s) read the slice-x0 copy for neighbours inside the tile (each input site of
+// the tile serves up to six outputs there) and memory only for the halo, which belongs to
+// the neighbouring tiles of the same band step; the backward time hop
+// U_0(x0 - 1, s)^+ (1 + g0) in(x0 - 1, s) is formed one step earlier from the LDS copy and
+// carried in registers. The LDS holds two slice copies (one barrier per step). Workgroups of
+// one XCD are ordered tile-major with the rhs groups of a tile adjacent, so the groups of a
+// tile read each link at about the same time (L2 hits after the first). Tiles tile the
+// slice exactly (TA | L1, TB | L2); work-items t >= S only join the barriers.
+template <class R, int NR>
+__global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
+  typedef typename vec2<R>::type V2;
+  extern __shared__ char smem_raw[];
+  V2* lds = (V2*)smem_raw;                      // [2 copies][NR][12 components][S]
+  const Geo& g = A.g;
+  const int L3h = g.L3h;
+  const int S = TA * TB * L3h;
+  const int nt2 = g.L2 / TB, ntile = (g.L1 / TA) * nt2;
+  const int ngroups = (A.nrhs + NR - 1) / NR;
+  const int xcd = blockIdx.x & 7;
+  const int l = blockIdx.x >> 3;
+  const int tile = l / ngroups;
+  const int r0 = (l - tile * ngroups) * NR;
+  const int x0a = (int)((long long)g.L0 * xcd / 8), x0b = (int)((long long)g.L0 * (xcd + 1) / 8);
+  if (tile >= ntile || x0a >= x0b) return;      // whole workgroup, before any barrier
+  const int nr = min(NR, A.nrhs - r0);
+  const int x1a = (tile / nt2) * TA, x2a = (tile % nt2) * TB;
+  const int t = threadIdx.x;
+  const bool act = t < S;
+  const int lx3 = act ? t % L3h : 0;
+  const int lx2 = act ? (t / L3h) % TB : 0;
+  const int lx1 = act ? t / (L3h * TB) : 0;
+  const int s = ((x1a + lx1) * g.L2 + (x2a + lx2)) * L3h + lx3;
+  const int p = A.parity_out, q = 1 - p;
+  const V2* inb = A.in.ptr + q * A.in.ps;
+  const bool g5i = A.g5_in != 0;
+  const int lb = A.lb;
+  const long long V3h = g.V3h;
+  auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
+  auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
+  auto wrap = [&](int x) { return x < 0 ? x + g.L0 : (x >= g.L0 ? x - g.L0 : x); };
+  auto slot = [&](int cp, int r, int c, int k) { return lds + ((cp * NR + r) * 12 + c) * S + k; };
+  auto put = [&](int cp, int r, const cx<R> sp[4][3]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) st<R>(slot(cp, r, a * 3 + c, t), sp[a][c]);
+  };
+  auto get = [&](int cp, int r, int k, cx<R> sp[4][3]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sp[a][c] = ld<R>(slot(cp, r, a * 3 + c, k));
+  };
+
+  // U_0(x0 - 1, s)^+ (1 + g0) in(x0 - 1, s) for the backward time hop of the current output
+  cx<R> carry[NR][2][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) carry[r][h][c] = {R(0), R(0)};
+  if (act) {
+    const bool need_c = hop_selected(A, x0a) && bwd_on(x0a);
+    cx<R> m[9];
+    if (need_c) load_link<R>(A.U, g.Vhp, 0, q, (long long)wrap(x0a - 1) * V3h + s, m);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r < nr) {
+        cx<R> sp[4][3];
+        load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)x0a * V3h + s, g5i, sp);
+        put(0, r, sp);
+        if (need_c) {
+          cx<R> h[2][3];
+          load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)wrap(x0a - 1) * V3h + s, g5i, sp);
+          project<R>(0, true, sp, h);
+          su3_dag_mul<R>(m, h[0], carry[r][0]);
+          su3_dag_mul<R>(m, h[1], carry[r][1]);
+          if (x0a == 0)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) carry[r][k][c] = -carry[r][k][c];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  for (int x0 = x0a; x0 < x0b; ++x0) {
+    const int cp = (x0 - x0a) & 1;
+    if (act) {
+      const long long j = (long long)x0 * V3h + s;
+      const Site st_ = decode(g, j, p);
+      const bool sel = hop_selected(A, x0);
+      cx<R> acc[NR][4][3];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r][a][c] = {R(0), R(0)};
+      // input (x0 + 1, s): forward time hop now, LDS copy for the next step
+      const bool use_f = sel && fwd_on(x0);
+      const bool stage = x0 + 1 < x0b;
+      if (use_f || stage) {
+        cx<R> m[9];
+        if (use_f) load_link<R>(A.U, g.Vhp, 0, p, j, m);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            cx<R> sp[4][3];
+            load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)wrap(x0 + 1) * V3h + s, g5i, sp);
+            if (stage) put(cp ^ 1, r, sp);
+            if (use_f) {
+              cx<R> h[2][3], uh[2][3];
+              project<R>(0, false, sp, h);
+              su3_mul<R>(m, h[0], uh[0]);
+              su3_mul<R>(m, h[1], uh[1]);
+              if (x0 == g.L0 - 1)
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                  for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+              accum_recon<R>(0, false, uh, acc[r]);
+            }
+          }
+        }
+      }
+      if (sel) {
+        if (bwd_on(x0))
+#pragma unroll
+          for (int r = 0; r < NR; ++r) accum_recon<R>(0, true, carry[r], acc[r]);
+        // spatial hops: tile neighbours from the LDS copy of slice x0, the halo from memory
+#pragma unroll
+        for (int mu = 1; mu < 4; ++mu) {
+#pragma unroll
+          for (int dir = 0; dir < 2; ++dir) {
+            const long long jn = nbr(g, st_, j, mu, dir == 0 ? +1 : -1);
+            int k = -1;     // LDS slot of the neighbour, -1: outside the tile
+            if (mu == 3) {
+              k = t - lx3 + (int)(jn - (j - st_.x3h));
+            } else if (mu == 2) {
+              int y = st_.x2 + (dir == 0 ? 1 : -1);
+              y = y < 0 ? y + g.L2 : (y >= g.L2 ? y - g.L2 : y);
+              const int ly = y - x2a;
+              if (ly >= 0 && ly < TB) k = t + (ly - lx2) * L3h;
+            } else {
+              int y = st_.x1 + (dir == 0 ? 1 : -1);
+              y = y < 0 ? y + g.L1 : (y >= g.L1 ? y - g.L1 : y);
+              const int ly = y - x1a;
+              if (ly >= 0 && ly < TA) k = t + (ly - lx1) * L3h * TB;
+            }
+            cx<R> m[9];
+            if (dir == 0) load_link<R>(A.U, g.Vhp, mu, p, j, m);
+            else load_link<R>(A.U, g.Vhp, mu, q, jn, m);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+              if (r < nr) {
+                cx<R> sp[4][3], h[2][3], uh[2][3];
+                // the LDS read and the memory load must not share one pointer (a select
+                // between LDS and global addresses): read a valid slot, then overwrite
+                get(cp, r, k >= 0 ? k : t, sp);
+                if (k < 0) load_spinor<R>(inb + (r0 + r) * A.in.rs, jn, g5i, sp);
+                project<R>(mu, dir == 1, sp, h);
+                if (dir == 0) {
+                  su3_mul<R>(m, h[0], uh[0]);
+                  su3_mul<R>(m, h[1], uh[1]);
+                } else {
+                  su3_dag_mul<R>(m, h[0], uh[0]);
+                  su3_dag_mul<R>(m, h[1], uh[1]);
+                }
+                accum_recon<R>(mu, dir == 1, uh, acc[r]);
+              }
+            }
+          }
+        }
+      }
+      hop_store<R, NR, true>(A, p, j, r0, nr, sel, acc);
+      // the backward time hop of output (x0 + 1, s) from input (x0, s) (LDS copy)
+      if (x0 + 1 < x0b && hop_selected(A, x0 + 1) && bwd_on(x0 + 1)) {
+        cx<R> m[9];
+        load_link<R>(A.U, g.Vhp, 0, q, j, m);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            cx<R> sp[4][3], h[2][3];
+            get(cp, r, t, sp);
+            project<R>(0, true, sp, h);
+            su3_dag_mul<R>(m, h[0], carry[r][0]);
+            su3_dag_mul<R>(m, h[1], carry[r][1]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 static inline long long round8(long long n) { return (n + 7) / 8 * 8; }
 
 template <class R, int NR, bool SWEEP> static void launch_reg(const HopArgs<R>& A, hipStream_t st) {
@@ -861,6 +1067,42 @@ template <class R, int NR> static void launch_band(const HopArgs<R>& A, hipStrea
   hipLaunchKernelGGL((hop_band_kernel<R, NR>), grid, blk, 0, st, A, nck);
 }
 
+// Tile of the slab kernel: TA | L1 x1 values by TB | L2 x2 values (every x3), with at most
+// smax sites (TA TB L3h), chosen to minimise the halo per tile site 2 (1/TA + 1/TB), then to
+// maximise the tile.
+static void slab_tile(const Geo& g, int smax, int& TA, int& TB) {
+  TA = TB = 1;
+  double best = 1e30;
+  for (int a = 1; a <= g.L1; ++a) {
+    if (g.L1 % a) continue;
+    for (int b = 1; b <= g.L2; ++b) {
+      if (g.L2 % b || a * b * g.L3h > smax) continue;
+      const double halo = 2.0 / a + 2.0 / b;
+      if (halo < best - 1e-12 || (halo < best + 1e-12 && a * b > TA * TB)) {
+        best = halo;
+        TA = a;
+        TB = b;
+      }
+    }
+  }
+}
+
+// LDS budget per workgroup of the slab kernel (two slice copies of the tile for NR rhs)
+template <class R, int NR> static void launch_slab(const HopArgs<R>& A, hipStream_t st, int lds_budget) {
+  typedef typename vec2<R>::type V2;
+  const int per_site = 2 * NR * 12 * (int)sizeof(V2);
+  const int smax = min(512, max(A.g.L3h, lds_budget / per_site));
+  int TA, TB;
+  slab_tile(A.g, smax, TA, TB);
+  const int S = TA * TB * A.g.L3h;
+  const int ntile = (A.g.L1 / TA) * (A.g.L2 / TB);
+  const long long groups = (A.nrhs + NR - 1) / NR;
+  const int threads = (S + 63) / 64 * 64;
+  const size_t lds = (size_t)S * per_site;
+  hipLaunchKernelGGL((hop_slab_kernel<R, NR>), dim3((unsigned)(8LL * ntile * groups)), dim3(threads), lds, st,
+                     A, TA, TB);
+}
+
 template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {
   typedef typename vec2<R>::type V2;
   constexpr int S = sizeof(R) == 8 ? 128 : 256;     // 48 KB of LDS either way
@@ -893,6 +1135,18 @@ template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t st) {
     case HOP_MAP_BAND1:
       if (full) launch_march<R, 1>(A, st);
       else launch_band<R, 1>(A, st);
+      return;
+    case HOP_MAP_SLAB1:
+      if (full) launch_march<R, 1>(A, st);
+      else launch_slab<R, 1>(A, st, 40 * 1024);
+      return;
+    case HOP_MAP_SLAB1W:
+      if (full) launch_march<R, 1>(A, st);
+      else launch_slab<R, 1>(A, st, 80 * 1024);
+      return;
+    case HOP_MAP_SLAB2:
+      if (full) launch_march<R, 2>(A, st);
+      else launch_slab<R, 2>(A, st, 80 * 1024);
       return;
     default: break;
   }

@@ -14,6 +14,8 @@ void launch_gauge_force(const Geo& g, double* F, double c, const double2* U, hip
 void launch_shift_links(const Geo& g, double2* out, const double2* in, int n, hipStream_t s);
 // out[0] = sum_x sum_{mu>nu} Re tr U_P (part: ceil(Vh/128) doubles of scratch)
 void launch_plaq_sum(const Geo& g, const double2* U, double* part, double* out, hipStream_t s);
+// out[0] = max over the links of max(max_e |(U U^+ - 1)_e|, |det U - 1|) (NaN if any is NaN)
+void launch_su3_dev(const Geo& g, const double2* U, double* part, double* out, hipStream_t s);
 void launch_kinetic(const Geo& g, const double* P, double* part, double* out, hipStream_t s);
 void launch_norm2_full(const Geo& g, const double2* f, double* part, double* out, hipStream_t s);
 void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s,

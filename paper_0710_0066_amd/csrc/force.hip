@@ -234,6 +234,47 @@ __global__ __launch_bounds__(256) void k_plaq(Geo g, const double2* U, double* p
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// Per-workgroup maximum over the links of the largest deviation from SU(3): the largest
+// entry modulus of U U^+ - 1 and |det U - 1|. A NaN entry gives a NaN maximum (kept by
+// the comparisons below), so a non-finite field fails the check as well.
+__device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+__global__ __launch_bounds__(256) void k_su3_dev(Geo g, const double2* U, double* part) {
+  __shared__ double sh[4];
+  const int p = threadIdx.x >> 7;
+  const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
+  double dev = 0.0;
+  if (j < g.Vh) {
+    for (int mu = 0; mu < 4; ++mu) {
+      const M3 u = load_U(U, g.Vhp, p, j, mu);
+      const M3 uu = mmul_nd(u, u);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        const double re = uu.m[e].r - ((e % 4 == 0) ? 1.0 : 0.0);
+        dev = nanmax(dev, sqrt(re * re + uu.m[e].i * uu.m[e].i));
+      }
+      // det = row 0 . (row 1 x row 2)
+      const C c0 = cmul(u.m[4], u.m[8]) - cmul(u.m[5], u.m[7]);
+      const C c1 = cmul(u.m[5], u.m[6]) - cmul(u.m[3], u.m[8]);
+      const C c2 = cmul(u.m[3], u.m[7]) - cmul(u.m[4], u.m[6]);
+      const C det = cmul(u.m[0], c0) + cmul(u.m[1], c1) + cmul(u.m[2], c2);
+      dev = nanmax(dev, sqrt((det.r - 1.0) * (det.r - 1.0) + det.i * det.i));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dev = nanmax(dev, __shfl_down(dev, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = nanmax(nanmax(sh[0], sh[1]), nanmax(sh[2], sh[3]));
+}
+
+__global__ void k_max_parts(int n, const double* part, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < n; ++i) m = nanmax(m, part[i]);
+    out[0] = m;
+  }
+}
+
 // Per-workgroup partial of 1/2 sum p^2 over valid sites
 __global__ __launch_bounds__(256) void k_kinetic(Geo g, const double* P, double* part) {
   const int p = threadIdx.x >> 7;
@@ -499,6 +540,10 @@ void launch_shift_links(const Geo& g, double2* out, const double2* in, int n, hi
 void launch_plaq_sum(const Geo& g, const double2* U, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_plaq, dim3(site_blocks(g)), dim3(256), 0, s, g, U, part);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, (int)site_blocks(g), part, out);
+}
+void launch_su3_dev(const Geo& g, const double2* U, double* part, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_su3_dev, dim3(site_blocks(g)), dim3(256), 0, s, g, U, part);
+  hipLaunchKernelGGL(k_max_parts, dim3(1), dim3(64), 0, s, (int)site_blocks(g), part, out);
 }
 void launch_kinetic(const Geo& g, const double* P, double* part, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_kinetic, dim3(site_blocks(g)), dim3(256), 0, s, g, P, part);

@@ -110,8 +110,19 @@ void hop_sel(sap_ctx* c, double2* out, const double2* in, int colour, int outer,
   launch_hop<double>(A, s);
 }
 
+// options for a solve of a block (lb > 0) or even-site system: SAP_SAP_BICGSTAB, which
+// solves M x = b only, becomes even-odd BiCGstab with the same tolerances
+const sap_solve_opts* sub_opts(const sap_solve_opts* o, sap_solve_opts* tmp) {
+  if (o->method != SAP_SAP_BICGSTAB) return o;
+  *tmp = *o;
+  tmp->method = SAP_BICGSTAB;
+  return tmp;
+}
+
 int solve1(sap_ctx* c, double2* x, const double2* b, int lb, int colour, const sap_solve_opts* o,
            hipStream_t s) {
+  sap_solve_opts tmp;
+  if (lb) o = sub_opts(o, &tmp);
   sap_solve_info inf[64];
   const int nsys = lb ? c->geom.L[0] / lb : 1;
   sap_solve_info* ip = nsys <= 64 ? inf : nullptr;
@@ -237,6 +248,8 @@ int apply_weo(sap_ctx* c, double2* out, const double2* in, double rho, double2* 
 }
 
 int solve_eo1(sap_ctx* c, double2* x, const double2* b, double rho, const sap_solve_opts* o, hipStream_t s) {
+  sap_solve_opts tmp;
+  o = sub_opts(o, &tmp);
   sap_solve_info inf[64];
   const int nsys = c->geom.L[0] / c->geom.l0_sub;
   sap_solve_info* ip = nsys <= 64 ? inf : nullptr;
@@ -378,6 +391,15 @@ int hamiltonian(Traj& T, double* K, double* SG, double* SW, double* SR) {
 }
 
 // ---- the five-level integrator of the four-part action (Sec. 2) ---------------------
+// solver options of part j = 1..4 inside the molecular dynamics and for its heat bath and
+// action (part_solve, else the common force_solve / action_solve)
+const sap_solve_opts* force_opts4(const sap_hmc4_params* P, int j) {
+  return P->part_solve ? &P->part_solve[j - 1] : &P->force_solve;
+}
+const sap_solve_opts* action_opts4(const sap_hmc4_params* P, int j) {
+  return P->part_solve ? &P->part_solve[3 + j] : &P->action_solve;
+}
+
 struct Traj4 {
   sap_ctx* c;
   const sap_hmc4_params* P;
@@ -390,7 +412,7 @@ struct Traj4 {
 int kick4(Traj4& T, int j, double dt) {
   sap_ctx* c = T.c;
   double* mom = fws(c)->mom;
-  const sap_solve_opts* o = &T.P->force_solve;
+  const sap_solve_opts* o = j ? force_opts4(T.P, j) : nullptr;
   switch (j) {
     case 0:
       launch_gauge_force(c->g, mom, -dt * T.P->beta / 6.0, c->U64, T.s, T.sx);
@@ -435,16 +457,28 @@ int step4(Traj4& T, int j, double dt) {
 int hamiltonian4(Traj4& T, double* K, double S[5]) {
   int rc;
   sap_ctx* c = T.c;
-  const sap_solve_opts* o = &T.P->action_solve;
+  const sap_hmc4_params* P = T.P;
   if ((rc = kinetic_host(c, fws(c)->mom, K, T.s))) return rc;
-  if ((rc = gauge_action_host(c, T.P->beta, &S[0], T.s))) return rc;
-  if ((rc = eo_pf_terms(c, nullptr, 0.0, T.phi1, 1, T.P->rho, o, &S[1], T.s))) return rc;
-  if ((rc = eo_pf_terms(c, nullptr, 0.0, T.phi2, 2, T.P->rho, o, &S[2], T.s))) return rc;
-  if ((rc = schwarz_terms(c, nullptr, 0.0, T.chi3, o, &S[3], T.s, nullptr, c->geom.l0))) return rc;
-  return schwarz_terms(c, nullptr, 0.0, T.chi4, o, &S[4], T.s, nullptr, 0);
+  if ((rc = gauge_action_host(c, P->beta, &S[0], T.s))) return rc;
+  if ((rc = eo_pf_terms(c, nullptr, 0.0, T.phi1, 1, P->rho, action_opts4(P, 1), &S[1], T.s))) return rc;
+  if ((rc = eo_pf_terms(c, nullptr, 0.0, T.phi2, 2, P->rho, action_opts4(P, 2), &S[2], T.s))) return rc;
+  if ((rc = schwarz_terms(c, nullptr, 0.0, T.chi3, action_opts4(P, 3), &S[3], T.s, nullptr, c->geom.l0)))
+    return rc;
+  return schwarz_terms(c, nullptr, 0.0, T.chi4, action_opts4(P, 4), &S[4], T.s, nullptr, 0);
 }
 
 }  // namespace
+
+// Largest deviation of the context's FP64 links from SU(3) (host output; synchronises).
+int su3_deviation_host(sap_ctx* c, double* dev, hipStream_t s) {
+  ForceWS* w = fws(c);
+  launch_su3_dev(c->g, c->U64, w->part, w->scal, s);
+  SAP_HIP_CHECK(c, hipMemcpyAsync(w->h_scal, w->scal, 8, hipMemcpyDeviceToHost, s));
+  SAP_HIP_CHECK(c, hipStreamSynchronize(s));
+  *dev = w->h_scal[0];
+  return SAP_OK;
+}
+
 
 extern "C" {
 
@@ -687,6 +721,9 @@ int hmc_trajectory_4pf(sap_ctx* c, double* U, const sap_hmc4_params* P, sap_hmc4
     return sap_fail(c, SAP_E_ARG, "tau must be > 0, beta and lambda finite, rho finite and >= 0");
   int rc;
   if ((rc = check_opts(c, &P->force_solve)) || (rc = check_opts(c, &P->action_solve))) return rc;
+  if (P->part_solve)
+    for (int k = 0; k < 8; ++k)
+      if ((rc = check_opts(c, &P->part_solve[k]))) return rc;
   if (P->step_scale)
     for (int i = 0; i < 4 * c->geom.L[0]; ++i)
       if (!(P->step_scale[i] >= 0.0 && std::isfinite(P->step_scale[i])))
@@ -702,16 +739,17 @@ int hmc_trajectory_4pf(sap_ctx* c, double* U, const sap_hmc4_params* P, sap_hmc4
   // heat baths (noise staged in f[11]): phi1 = W3eo P_e xi1, phi2 = W3eo^-1 W2eo P_e xi2,
   // chi3 = R_hat_2 Pi_2 g3, chi4 = R_hat Pi g4
   double2 *phi1 = w->f[7], *chi4 = w->f[8], *phi2 = w->f[9], *chi3 = w->f[10], *stage = w->f[11];
-  const sap_solve_opts* ao = &P->action_solve;
   if ((rc = sap_pack_spinor(c, stage, P->xi1, 1, SAP_F64, stream)) ||
-      (rc = eo_heat_bath(c, phi1, stage, 1, P->rho, ao, s)))
+      (rc = eo_heat_bath(c, phi1, stage, 1, P->rho, action_opts4(P, 1), s)))
     goto fail;
   if ((rc = sap_pack_spinor(c, stage, P->xi2, 1, SAP_F64, stream)) ||
-      (rc = eo_heat_bath(c, phi2, stage, 2, P->rho, ao, s)))
+      (rc = eo_heat_bath(c, phi2, stage, 2, P->rho, action_opts4(P, 2), s)))
     goto fail;
-  if ((rc = sap_pack_spinor(c, stage, P->g3, 1, SAP_F64, stream)) || (rc = heat_bath(c, chi3, stage, ao, s, c->geom.l0)))
+  if ((rc = sap_pack_spinor(c, stage, P->g3, 1, SAP_F64, stream)) ||
+      (rc = heat_bath(c, chi3, stage, action_opts4(P, 3), s, c->geom.l0)))
     goto fail;
-  if ((rc = sap_pack_spinor(c, stage, P->g4, 1, SAP_F64, stream)) || (rc = heat_bath(c, chi4, stage, ao, s, 0)))
+  if ((rc = sap_pack_spinor(c, stage, P->g4, 1, SAP_F64, stream)) ||
+      (rc = heat_bath(c, chi4, stage, action_opts4(P, 4), s, 0)))
     goto fail;
   {
     Traj4 T = {c, P, phi1, phi2, chi3, chi4, s, P->step_scale ? w->sx : nullptr};

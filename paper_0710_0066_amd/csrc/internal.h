@@ -82,7 +82,10 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
        HOP_MAP_WALK2 = 15,  //   registers, 1 / 2 rhs per work-item
        HOP_MAP_BAND1 = 16,  // even-odd hop only: each XCD owns a band of x0 slices, time
                             //   hops carried in registers, 1 rhs per work-item
-       HOP_NMAP = 17 };
+       HOP_MAP_SLAB1 = 17,  // even-odd hop only: band order, a workgroup owns a spatial tile
+       HOP_MAP_SLAB1W = 18, //   of the slice staged in LDS and walks the band; 1 rhs per
+       HOP_MAP_SLAB2 = 19,  //   work-item (SLAB1W: tiles up to twice as large), or 2
+       HOP_NMAP = 20 };
 constexpr int HOP_WALK_T = 8;   // slices per walk
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
@@ -129,10 +132,13 @@ struct sap_ctx {
   std::string err;
   void* solver;   // solver workspace (solver.hip)
   void* forces;   // force / trajectory workspace (hmc.hip)
-  void* sapws;    // Schwarz-preconditioned BiCGstab workspace (solver.hip), allocated on first use
+  void* sapws;    // Schwarz-preconditioned BiCGstab workspace (solver.hip), allocated by sap_create
   // tuned hop mapping per [full operator?][precision (sap_prec)][nrhs] (-1: not tuned)
   signed char hop_map[2][3][65];
 };
+
+// largest deviation from SU(3) (|U U^+ - 1| entries, |det U - 1|) sap_set_gauge accepts
+constexpr double SAP_SU3_TOL = 1e-10;
 
 // precision code (sap_prec) of a storage type
 template <class S> constexpr int prec_of() {

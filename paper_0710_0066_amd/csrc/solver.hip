@@ -9,7 +9,9 @@
 //    into its input and output;
 //  * BiCGstab (van der Vorst) on M_hat directly, with complex per-system scalars;
 //  * the geometric series x_e = sum_n (k^2 D_eo D_oe)^n b_hat (Sec. 3 uses it for the block
-//    terms), whose residual after n terms is the next term.
+//    terms), whose residual after n terms is the next term; for the shifted even-site
+//    system (M_hat + rho) x_e = b_e of the mass-preconditioned parts every term carries a
+//    factor 1 / (1 + rho) and the residual after n terms is (1 + rho) times the next term.
 // Per-system scalars stay on the device; converged systems are frozen while the others
 // continue; the host reads one counter every few iterations.
 // Outer loop: FP64 defect correction r = b - A x (A applied in FP64), inner solve in
@@ -49,6 +51,8 @@ struct SolverWS {
 constexpr int ITERS_PER_GRAPH = 8;
 
 static SolverWS* ws_of(sap_ctx* c) { return (SolverWS*)c->solver; }
+struct SapWS;
+static SapWS* sap_ws(sap_ctx* c);   // Schwarz-preconditioned BiCGstab workspace (below)
 
 extern "C" int sap_solver_create(sap_ctx* c) {
   SolverWS* w = new SolverWS();   // value-initialised: every pointer starts null
@@ -84,6 +88,8 @@ extern "C" int sap_solver_create(sap_ctx* c) {
   if (!ok) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the solver workspace");
   if (hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess)
     return sap_fail(c, SAP_E_HIP, "cannot create the capture stream");
+  // the Schwarz-preconditioned BiCGstab workspace too, so that no solve allocates fields
+  if (!sap_ws(c)) return sap_fail(c, SAP_E_NOMEM, "cannot allocate the Schwarz-preconditioned BiCGstab workspace");
   return SAP_OK;
 }
 
@@ -164,8 +170,11 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
   const Ar aI = (Ar)(1.0 + rho);               // unit term of M_hat + rho
   const size_t fullb = (size_t)24 * Vhp * nrhs * sizeof(double2);
   const size_t fullR = full_bytes<R>(Vhp, nrhs), halfR = half_bytes<R>(Vhp, nrhs);
-  if (o->method == SAP_GEOM && (eo_only || rho != 0.0))
-    return sap_fail(c, SAP_E_ARG, "the geometric series is available for the unshifted W x = b only");
+  if (rho != 0.0 && !eo_only) return sap_fail(c, SAP_E_ARG, "a shift needs the even-site system");
+  // geometric series: terms t_0 = b_hat / (1 + rho), t_{n+1} = k^2 / (1 + rho) D_eo D_oe t_n,
+  // residual (1 + rho) t_{n+1}: the series works on t, so b_hat and the target are scaled
+  const bool geom = o->method == SAP_GEOM;
+  const double shift_inv = 1.0 / (1.0 + rho);
 
   Field<double> X = {(double2*)x, 24 * Vhp, 12 * Vhp}, B = {(double2*)b, 24 * Vhp, 12 * Vhp};
   Field<double> R64 = {w->r64, 24 * Vhp, 12 * Vhp}, AX = {w->ax, 24 * Vhp, 12 * Vhp};
@@ -218,14 +227,16 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     ++outer;
     // inner right-hand side at the inner precision
     blas_convert<R, double>(G, nrhs, RIN, R64, 2, st);
-    // b_hat_e = r_e + k D_eo r_o  (into S)
-    hop<R>(c, U, S, RIN, RIN, 0, nrhs, lb, colour, Ar(1), kR, 0, 0, st);
+    // b_hat_e = r_e + k D_eo r_o  (into S; times 1 / (1 + rho) for the series)
+    hop<R>(c, U, S, RIN, RIN, 0, nrhs, lb, colour, geom ? (Ar)shift_inv : Ar(1),
+           geom ? (Ar)(kap * shift_inv) : kR, 0, 0, st);
     SAP_HIP_CHECK(c, hipMemsetAsync(w->e, 0, fullR, st));
     blas_norm2<R>(G, nrhs, S, 1, w->partB, st);
     // stop the inner solve at ||s|| <= max(inner_tol ||b_hat||, 0.3 tol ||b||): the outer
     // residual after x += e equals the inner one up to rounding
     hipLaunchKernelGGL(k_targets, dim3(1), dim3(256), 0, st, nsys, w->partB, G.nchunk, w->bnorm2,
-                       inner_tol * inner_tol, 0.09 * tol * tol, w->target2);
+                       inner_tol * inner_tol, 0.09 * tol * tol * (geom ? shift_inv * shift_inv : 1.0),
+                       w->target2);
     SAP_HIP_CHECK(c, hipMemsetAsync(w->flags, 0, 16, st));
     const size_t halfb = halfR;
     if (method == SAP_CG) {
@@ -283,7 +294,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
           Field<R> from = h == 0 ? S : HX, to = h == 0 ? HX : S;
           blas_geom_add<R>(G, nrhs, Ee, from, w->active, q);
           hop<R>(c, U, T, from, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 0, 0, q);
-          hop<R>(c, U, to, T, NONE, 0, nrhs, lb, colour, Ar(0), (Ar)(kap * kap), 0, 0, q);
+          hop<R>(c, U, to, T, NONE, 0, nrhs, lb, colour, Ar(0), (Ar)(kap * kap * shift_inv), 0, 0, q);
           blas_norm2<R>(G, nrhs, to, 1, w->partA, q);
           fin_geom(SC, nsys, G.nchunk, w->partA, w->selected, w->target2, 0, q);
         }
@@ -386,7 +397,7 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
   for (int m = 0; m < HOP_NMAP; ++m) {
     const bool one_rhs_alias = m == HOP_MAP_LANE4 || m == HOP_MAP_WAVE4 ||
                                (m >= HOP_SWEEP && m != HOP_MAP_MARCH1 && m != HOP_MAP_WALK1 &&
-                                m != HOP_MAP_BAND1);
+                                m != HOP_MAP_BAND1 && m != HOP_MAP_SLAB1 && m != HOP_MAP_SLAB1W);
     const bool half_only = m == HOP_MAP_STREAM || m >= HOP_MAP_WALK1;
     // FP16 storage has the site and marching kernels only
     const bool f16_alias = f16 && m != HOP_MAP_SITE && m != HOP_MAP_MARCH1 && m != HOP_MAP_MARCH2 &&
@@ -503,6 +514,7 @@ extern "C" void sap_sapws_destroy(sap_ctx* c) {
   c->sapws = nullptr;
 }
 
+// allocated by sap_create (sap_solver_create); later calls return it
 static SapWS* sap_ws(sap_ctx* c) {
   if (c->sapws) return (SapWS*)c->sapws;
   SapWS* a = new SapWS();

@@ -159,3 +159,71 @@ def test_hmc_4pf_16x16x16x32(gu):
     assert abs(info.S0[3] - n2(schwarz.Pi(g3, Lat, l02, l01))) <= 1e-8 * info.S0[3]
     assert abs(info.S0[4] - n2(schwarz.Pi(g4, Lat, l01))) <= 1e-8 * info.S0[4]
     assert np.isfinite(info.dH) and info.accepted == (0.5 < np.exp(-info.dH))
+
+
+def test_eo_pf_terms_with_geometric_series_match_oracle(gu):
+    """S1 and S2 with the solver Sec. 3 uses for them, the geometric series of the
+    even-site systems (W3eo = W2eo + rho: every term carries 1 / (1 + rho)), in FP64 and
+    with FP32 inner terms: heat bath, action and force against the oracle's CGLS-based
+    values (the solutions are unique, so only the solver tolerance separates them)."""
+    import paper_0710_0066_amd as sap
+    print("eo pseudo-fermion terms, geometric series", flush=True)
+    U = synth.gauge_field(L, 0.5, 141)
+    A = action.FourPart(U, K, L01, L02, RHO, tol=1e-13)
+    ctx = gu.make_ctx(L, L01, K, U, L02)
+    for kind in (1, 2):
+        xi = synth.noise_spinor(L, 142 + kind)
+        phi_ref = A.heat_bath1(A.e * xi) if kind == 1 else A.heat_bath2(A.e * xi)
+        S_ref = A.S1(phi_ref) if kind == 1 else A.S2(phi_ref)
+        F_ref = A.F1(phi_ref) if kind == 1 else A.F2(phi_ref)
+        for inner, tol, ftol in ((sap.SAP_F64, 1e-13, 1e-9), (sap.SAP_F32, 1e-11, 1e-7)):
+            o = _opts(sap, tol=tol, inner=inner)
+            o.method = sap.SAP_GEOM
+            fphi = ctx.new_field(1)
+            sap.eo_pf_heat_bath(ctx, fphi, gu.to_sap(ctx, xi, 1), kind, RHO, o)
+            assert _rel(gu.from_sap(ctx, fphi, 1, xi.shape), phi_ref) <= 1e-9, (kind, inner)
+            F = ctx.new_momenta()
+            S = sap.eo_pf_force(ctx, F, 1.0, fphi, kind, RHO, o)
+            assert abs(S - S_ref) <= 1e-9 * S_ref, (kind, inner, S, S_ref)
+            assert _rel(_mom_from_sap(ctx, F, L), F_ref) <= ftol, (kind, inner)
+
+
+def test_hmc_4pf_trajectory_with_the_papers_solvers_matches_oracle(gu):
+    """The five-level trajectory with Sec. 3's solver assignment through part_solve: the
+    geometric series for S1, S2 and S3 (even-site series with the 1 / (1 + rho) factor for
+    S1 and S2; level-1 and level-2 block series for S3) and BiCGstab on M right-preconditioned
+    by a Schwarz cycle with 8-term series block solves for S4 (its heat bath runs even-odd
+    BiCGstab on the blocks), against the oracle's trajectory with CGLS solves: same dH and
+    links to the solver tolerance."""
+    import paper_0710_0066_amd as sap
+    Lat, k, beta, tau, n = (8, 2, 2, 4), 0.13, 5.6, 0.3, (2, 2, 1, 1, 2)
+    print("four-part hmc, paper's solvers, vs oracle", flush=True)
+    U = synth.gauge_field(Lat, 0.4, 151)
+    p0, xi1, xi2, g3, g4 = _inputs(Lat, 152)
+    A = action.FourPart(U, k, L01, L02, RHO, tol=1e-13)
+    fields = (A.heat_bath1(A.e * xi1), A.heat_bath2(A.e * xi2), A.heat_bath3(g3), A.heat_bath4(g4))
+    make = lambda V: action.FourPart(V, k, L01, L02, RHO, tol=1e-13)
+    lev = action.five_level(fields, k, beta, L01, L02, RHO, n, make)
+    U_ref, acc_ref, dH_ref, H0_ref, H1_ref = hmc.trajectory(lev, U, p0, tau, u_metropolis=0.0)
+    ctx = gu.make_ctx(Lat, L01, k, U, L02)
+    fU = gu.dev(U).clone()
+    fp = ctx.new_momenta()
+    ctx.pack_momenta(fp, gu.dev(p0))
+    geom = _opts(sap)
+    geom.method = sap.SAP_GEOM
+    sapb = _opts(sap)
+    sapb.method, sapb.sap_ncy, sapb.sap_block_terms, sapb.max_iter = sap.SAP_SAP_BICGSTAB, 1, 8, 2000
+    parts = [geom, geom, geom, sapb] * 2
+    o = _opts(sap)
+    prm = sap.hmc4_params(beta, tau, RHO, n, fp, gu.dev(xi1), gu.dev(xi2), gu.dev(g3), gu.dev(g4), 0.0, o, o,
+                          part_solve=parts)
+    info = sap.hmc_trajectory_4pf(ctx, fU, prm)
+    print(f"  dH gpu {info.dH:.12e} oracle {dH_ref:.12e} iters {info.solver_iters}", flush=True)
+    assert info.accepted == 1 and acc_ref
+    assert abs(info.H0 - H0_ref) <= 1e-9 * abs(H0_ref)
+    assert abs(info.dH - dH_ref) <= 1e-7 * max(1.0, abs(dH_ref))
+    assert np.max(np.abs(fU.cpu().numpy().reshape(U.shape) - U_ref)) <= 1e-9
+    with pytest.raises(sap.SapError) as e:
+        sap.hmc4_params(beta, tau, RHO, n, fp, gu.dev(xi1), gu.dev(xi2), gu.dev(g3), gu.dev(g4), 0.0, o, o,
+                        part_solve=parts[:4])
+    assert e.value.code == sap.SAP_E_ARG

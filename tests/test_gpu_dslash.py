@@ -94,16 +94,19 @@ def test_apply_Dslash_eo_matches_oracle(gu, L, l0, l0_sub, k, nrhs):
             assert gu.rel_err(got * m_out, ref) <= tol, (parity, prec)
 
 
-@pytest.mark.parametrize("hop_map", list(range(17)))
-@pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15)])
+@pytest.mark.parametrize("hop_map", list(range(20)))
+@pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15),
+                                          ((16, 10, 10, 12), 4, 2, 0.14)])
 def test_every_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
     """Each work-item mapping of the hop kernel (site, lane4, wave4, their rhs-slowest
     orders, register-blocked 2 / 4 rhs, x0-marching per XCD and, for the even-odd hop, the
     x0-streaming kernel with LDS staging, the x0-walking kernels with time neighbours
-    carried in registers and the x0-band kernel with one band of slices per XCD) gives
-    the oracle's D_eo, M and W, with
-    1 and 5 right-hand sides, including the gamma_5-folded and block-restricted forms the
-    solvers use (through solve_blocks)."""
+    carried in registers, the x0-band kernel with one band of slices per XCD and the slab
+    kernels with LDS-staged spatial tiles) gives the oracle's D_eo, M and W, with 1 and 5
+    right-hand sides, including the gamma_5-folded and block-restricted forms the solvers
+    use (through solve_blocks). On the 16 x 10^2 x 12 lattice the slab tiles (5 x 5 x 12
+    sites in FP32, 2 x 5 x 12 in FP64) leave halos in both x1 and x2 and every XCD walks a
+    band of two slices."""
     import paper_0710_0066_amd as sap
     print(f"hop map {hop_map} L={L}", flush=True)
     U = synth.gauge_field(L, 0.5, 1021)
@@ -165,36 +168,43 @@ def test_apply_M_and_W_full_size(gu, name):
 
 def test_benchmark_launch_24x24x24x48_12rhs(gu):
     """The benchmark's own launches: the even-odd hop on all 12 right-hand sides of the
-    24^3x48 workload after sap_tune, in FP64, FP32 and FP16 storage, both output parities.
-    Right-hand sides 0, 5 and 11 (the first, a middle and the last rhs group of every
-    mapping) are compared with the oracle's hop on every site; for the others, the rhs
-    must differ from each other as their sources do (no group reads another's input)."""
+    24^3x48 workload with the mappings bench.py times (bench.HEADLINE_MAPS) in FP64, FP32 and
+    FP16 storage, both output parities, every rhs compared with the oracle's hop on every
+    site; then the tuner's choices, three rhs checked."""
     import paper_0710_0066_amd as sap
+    from bench import HEADLINE_MAPS, hop_map_id
     cfg = synth.CONFIGS["batched_24x24x24x48"]
     L, k, l0, nrhs = cfg["L"], cfg["kappa"], cfg["l0"], cfg["nrhs"]
-    print("benchmark launch 24^3x48, 12 rhs", flush=True)
+    print(f"benchmark launch 24^3x48, 12 rhs, maps {HEADLINE_MAPS}", flush=True)
     U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
     psi = synth.gaussian_spinor(L, cfg["seed_src"], nrhs=nrhs)
     ctx = gu.make_ctx(L, l0, k, U, cfg["l0_sub"], max_rhs=nrhs)
+    ref = [dirac.hop(U, psi[r]) for r in range(nrhs)]
+    f16_tol = 16 * 2.0 ** -12 / 0.16
+    precs = {"f64": (sap.SAP_F64, F64_TOL), "f32": (sap.SAP_F32, F32_TOL), "f16": (sap.SAP_F16, f16_tol)}
+
+    def run(prec, tol, rhs):
+        fin = gu.to_sap(ctx, psi, nrhs, prec)
+        fout = ctx.new_field(nrhs, prec)
+        fout.fill_(3.0)
+        for parity in (0, 1):
+            sap.apply_Dslash_eo(ctx, fout, fin, nrhs, parity, prec)
+        got = gu.from_sap(ctx, fout, nrhs, psi.shape, prec)
+        for r in rhs:
+            scale = np.max(np.abs(psi[r] if prec == sap.SAP_F16 else ref[r]))
+            err = float(np.max(np.abs(got[r] - ref[r])) / scale)
+            assert err <= tol, (prec, r, err)
+
+    for name, (prec, tol) in precs.items():
+        print(f"  {name} map {HEADLINE_MAPS[name]}", flush=True)
+        sap.sap_set_hop_map(ctx, 0, prec, nrhs, hop_map_id(sap, HEADLINE_MAPS[name]))
+        run(prec, tol, range(nrhs))
     tuned = sap.sap_tune(ctx, nrhs)
     print(f"  tuned even-odd maps: f32 {min(tuned['eo_f32'], key=tuned['eo_f32'].get)}, "
           f"f64 {min(tuned['eo_f64'], key=tuned['eo_f64'].get)}, f16 {min(tuned['eo_f16'], key=tuned['eo_f16'].get)}",
           flush=True)
-    check = (0, 5, nrhs - 1)
-    ref = {r: dirac.hop(U, psi[r]) for r in check}
-    par = lattice.parity(L)
-    f16_tol = 16 * 2.0 ** -12 / 0.16
-    for prec, tol in [(sap.SAP_F64, F64_TOL), (sap.SAP_F32, F32_TOL), (sap.SAP_F16, f16_tol)]:
-        fin = gu.to_sap(ctx, psi, nrhs, prec)
-        fout = ctx.new_field(nrhs, prec)
-        for parity in (0, 1):
-            sap.apply_Dslash_eo(ctx, fout, fin, nrhs, parity, prec)
-        got = gu.from_sap(ctx, fout, nrhs, psi.shape, prec)
-        for r in check:
-            err = float(np.max(np.abs(got[r] - ref[r])) / np.max(np.abs(psi[r] if prec == sap.SAP_F16 else ref[r])))
-            assert err <= tol, (prec, r, err)
-        assert all(not np.allclose(got[r], got[r + 1]) for r in range(nrhs - 1))
-        del fin, fout, got
+    for name, (prec, tol) in precs.items():
+        run(prec, tol, (0, 5, nrhs - 1))
 
 
 def test_pack_unpack_roundtrip(gu):

@@ -349,3 +349,32 @@ def test_sap_series_block_solves_match_dense_solution(gu, L, l0, k, terms):
     x_or, _, res_or = solvers.solve_sap_bicgstab(U, b[0], k, l0, ncy=2, tol=1e-11, block_terms=terms)
     assert res_or <= 1e-11
     assert np.linalg.norm(x[0] - x_or) / np.linalg.norm(x_or) <= np.linalg.cond(A) * 2e-10
+
+
+def test_full_lattice_bicgstab_beyond_convergence_stops_cleanly(gu):
+    """At the workload's kappa = 0.1575 the synthetic 16^3x32 links are beyond the
+    mean-field critical point, where plain and Schwarz-preconditioned BiCGstab do not
+    converge on the full lattice: both must stop at their caps with SAP_E_NOCONV (not a
+    non-finite value), report a finite residual above tol, and leave the context usable
+    (a CG solve afterwards reaches 1e-10)."""
+    import paper_0710_0066_amd as sap
+    cfg = synth.CONFIGS["plain_16x16x16x32"]
+    L = cfg["L"]
+    print("full-lattice BiCGstab at kappa = 0.1575: clean stop", flush=True)
+    U = synth.gauge_field(L, cfg["eps"], cfg["seed_gauge"])
+    b = synth.gaussian_spinor(L, cfg["seed_src"])
+    ctx = gu.make_ctx(L, cfg["l0"], cfg["kappa"], U, cfg["l0_sub"], max_rhs=1)
+    fb = gu.to_sap(ctx, b, 1)
+    fx = ctx.new_field(1)
+    for o in (sap.solve_opts(tol=1e-10, max_iter=400, inner_prec=sap.SAP_F32, inner_tol=1e-5, max_outer=3,
+                             method=sap.SAP_BICGSTAB),
+              sap.solve_opts(tol=1e-10, max_iter=30, inner_prec=sap.SAP_F32, max_outer=2,
+                             method=sap.SAP_SAP_BICGSTAB, sap_ncy=1, sap_block_terms=8)):
+        with pytest.raises(sap.SapError) as e:
+            sap.solve_full(ctx, fx, fb, 1, o)
+        assert e.value.code == sap.SAP_E_NOCONV, str(e.value)
+        res = e.value.info[0].true_rel_res
+        print(f"  method {o.method}: {e.value}; residual {res:.3e}", flush=True)
+        assert np.isfinite(res) and res > 1e-10
+    info = sap.solve_full(ctx, fx, fb, 1, _mopts(sap, "cg", sap.SAP_F32))
+    assert info[0].true_rel_res <= 1e-10
