@@ -25,8 +25,10 @@
  *   tiled structure of arrays. Within a parity, site j = i / 2; sites are grouped in
  *   tiles of 64 (j / 64), Vhp = V/2 rounded up to a multiple of 64.
  *   spinor  complex number (rhs, parity, c = 3*spin + colour, j) at index
- *           ((rhs*2 + parity)*12*Vhp) + ((j/64)*12 + c)*64 + j%64
- *           (complex128 for SAP_F64, complex64 for SAP_F32).
+ *           ((rhs*2 + parity)*12*Vhp) + ((j/64)*12 + c)*64 + j%64   (SAP_F64, complex128)
+ *           ((rhs*2 + parity)*12*Vhp) + ((j/64)*12 + c - c%2)*64 + 2*(j%64) + c%2
+ *                                                                   (SAP_F32, complex64:
+ *           the components 2k and 2k + 1 of a site are adjacent, one 16-byte word).
  *           SAP_F16: the same component order with a half-precision complex (two FP16)
  *           per entry and rhs blocks of 26*Vhp entries: parity 0 and 1 components
  *           (24*Vhp), then one FP32 norm per (parity, j) at float index

@@ -5,6 +5,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace sap {
 
@@ -87,6 +88,69 @@ template <class R> __device__ __forceinline__ void st(typename vec2<R>::type* p,
 constexpr int TILE = 64;
 __device__ __host__ __forceinline__ long long tiled(long long j, int c, int NC) {
   return ((j >> 6) * NC + c) * TILE + (j & (TILE - 1));
+}
+
+// Spinor sites in storage R. FP64 fields keep the tiled layout above (12 components of 16
+// bytes). FP32 fields store the 12 complex components of a site in 6 pairs (2k, 2k + 1),
+// each pair one 16-byte word, in the same tiled scheme with 6 components: pair k of site j
+// is float4 number tiled(j, k, 6) of the (rhs, parity) block, i.e. complex number
+// ((j / 64) * 12 + 2k) * 64 + 2 (j % 64) + (c % 2) for component c = 2k + c % 2. A work-item
+// then moves a site with 6 loads or stores instead of 12.
+template <class R> __device__ __host__ __forceinline__ long long sidx(long long j, int c) {
+  if constexpr (std::is_same<R, float>::value) return ((j >> 6) * 12 + (c & ~1)) * TILE + 2 * (j & (TILE - 1)) + (c & 1);
+  else return tiled(j, c, 12);
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// the 12 components of site j of one (rhs, parity) block of a spinor field
+template <class R>
+__device__ __forceinline__ void ld_site(const typename vec2<R>::type* blk, long long j, cx<R> v[12]) {
+  if constexpr (std::is_same<R, float>::value) {
+    const f4v* q = (const f4v*)blk + tiled(j, 0, 6);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const f4v w = q[k * TILE];
+      v[2 * k] = {w.x, w.y};
+      v[2 * k + 1] = {w.z, w.w};
+    }
+  } else {
+    const typename vec2<R>::type* q = blk + tiled(j, 0, 12);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const typename vec2<R>::type w = q[c * TILE];
+      v[c] = {w.x, w.y};
+    }
+  }
+}
+
+// store the 12 components of site j (NT: non-temporal stores)
+template <class R, bool NT = false>
+__device__ __forceinline__ void st_site(typename vec2<R>::type* blk, long long j, const cx<R> v[12]) {
+  if constexpr (std::is_same<R, float>::value) {
+    f4v* q = (f4v*)blk + tiled(j, 0, 6);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const f4v w = {v[2 * k].r, v[2 * k].i, v[2 * k + 1].r, v[2 * k + 1].i};
+      if (NT) __builtin_nontemporal_store(w, q + k * TILE);
+      else q[k * TILE] = w;
+    }
+  } else {
+    typename vec2<R>::type* q = blk + tiled(j, 0, 12);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      if (NT) {
+        __builtin_nontemporal_store(v[c].r, &q[c * TILE].x);
+        __builtin_nontemporal_store(v[c].i, &q[c * TILE].y);
+      } else {
+        typename vec2<R>::type w;
+        w.x = v[c].r;
+        w.y = v[c].i;
+        q[c * TILE] = w;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------

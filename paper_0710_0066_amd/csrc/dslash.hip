@@ -17,25 +17,68 @@ namespace sap {
 template <class R>
 __device__ __forceinline__ void load_spinor(const typename vec2<R>::type* p, long long j, bool g5,
                                             cx<R> s[4][3]) {
-  const typename vec2<R>::type* q = p + tiled(j, 0, 12);
+  cx<R> v[12];
+  ld_site<R>(p, j, v);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[sp][c] = (g5 && sp >= 2) ? -v[sp * 3 + c] : v[sp * 3 + c];
+}
+
+// out site j of the (rhs, parity) block ob: a x + b (gamma_5 if g5o) acc, or zero when the
+// site is not selected; xb: the same block of x, or null (NT: non-temporal stores)
+template <class R, bool NT>
+__device__ __forceinline__ void store_out(typename vec2<R>::type* ob, const typename vec2<R>::type* xb, long long j,
+                                          bool sel, bool g5o, R a, R b, const cx<R> acc[4][3]) {
+  cx<R> v[12], xv[12];
+  if (sel && xb) ld_site<R>(xb, j, xv);
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cx<R> v = ld<R>(q + (sp * 3 + c) * TILE);
-      s[sp][c] = (g5 && sp >= 2) ? -v : v;
+      const int k = sp * 3 + c;
+      cx<R> h = acc[sp][c];
+      if (g5o && sp >= 2) h = -h;
+      cx<R> r = {b * h.r, b * h.i};
+      if (xb) {
+        r.r += a * xv[k].r;
+        r.i += a * xv[k].i;
+      }
+      v[k] = sel ? r : cx<R>{R(0), R(0)};
     }
+  st_site<R, NT>(ob, j, v);
 }
 
 // The hop kernels read two-row link copies (FP64 or FP32) and rebuild the third row from
-// unitarity and unit determinant: row 3 = conj(row 1 x row 2).
+// unitarity and unit determinant: row 3 = conj(row 1 x row 2). o24 is the offset of the
+// site's tile row, tiled(j, 0, 24) with the lane j % 64. FP64 entries are 16 bytes each
+// (entry e of link mu at o24 + (6 mu + e) * 64). The FP32 copy holds the six entries of a
+// link as three pairs, each pair one 16-byte word per lane: pair k = (2k, 2k + 1) of link mu
+// at float2 offset  tile * 24 * 64 + (6 mu + 2k) * 64 + 2 lane  (+1 for the odd entry),
+// so that a link takes three 16-byte loads.
+template <class R>
+__device__ __forceinline__ void load_link_at(const typename vec2<R>::type* U, long long Vhp, int mu, int par,
+                                             long long o24, cx<R> m[9]) {
+  if constexpr (std::is_same<R, float>::value) {
+    const long long lane = o24 & (TILE - 1);
+    const float4* p = (const float4*)(U + par * 24 * Vhp + (o24 - lane) + 6 * mu * TILE) + lane;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 v = p[k * TILE];
+      m[2 * k] = {v.x, v.y};
+      m[2 * k + 1] = {v.z, v.w};
+    }
+  } else {
+    const typename vec2<R>::type* p = U + par * 24 * Vhp + o24 + 6 * mu * TILE;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) m[e] = ld<R>(p + e * TILE);
+  }
+  third_row<R>(m);
+}
 template <class R>
 __device__ __forceinline__ void load_link(const typename vec2<R>::type* U, long long Vhp, int mu,
                                           int par, long long j, cx<R> m[9]) {
-  const typename vec2<R>::type* p = U + par * 24 * Vhp + tiled(j, 6 * mu, 24);
-#pragma unroll
-  for (int e = 0; e < 6; ++e) m[e] = ld<R>(p + e * TILE);
-  third_row<R>(m);
+  load_link_at<R>(U, Vhp, mu, par, tiled(j, 0, 24), m);
 }
 
 // Work-item mappings (MAP):
@@ -99,16 +142,16 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A, long long nchunk
   const long long Vhp = g.Vhp;
   const Site s = decode(g, j, p);
 
-  V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
+  V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps;
+  const V2* xo = A.x.ptr ? A.x.ptr + rhs * A.x.rs + p * A.x.ps : nullptr;
   if (A.slb) {
     const int blk = s.x0 / A.slb;
     bool sel;
     if (A.block >= 0) sel = (blk == A.block);
     else sel = (A.colour == 0) || ((A.colour == 1) == ((blk & 1) == 1));
     if (!sel) {
-      cx<R> z = {R(0), R(0)};
-#pragma unroll
-      for (int c = 0; c < 12; ++c) st<R>(o + c * TILE, z);
+      const cx<R> z[4][3] = {};
+      store_out<R, false>(o, nullptr, j, false, false, R(0), R(0), z);
       return;
     }
   }
@@ -162,28 +205,7 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs<R> A, long long nchunk
     }
   }
 
-  if (A.g5_out) {
-#pragma unroll
-    for (int sp = 2; sp < 4; ++sp)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[sp][c] = -acc[sp][c];
-  }
-  if (A.x.ptr) {
-    const V2* xp = A.x.ptr + rhs * A.x.rs + p * A.x.ps + tiled(j, 0, 12);
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        cx<R> xv = ld<R>(xp + (sp * 3 + c) * TILE);
-        cx<R> r = {A.a * xv.r + A.b * acc[sp][c].r, A.a * xv.i + A.b * acc[sp][c].i};
-        st<R>(o + (sp * 3 + c) * TILE, r);
-      }
-  } else {
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) st<R>(o + (sp * 3 + c) * TILE, A.b * acc[sp][c]);
-  }
+  store_out<R, false>(o, xo, j, true, A.g5_out != 0, A.a, A.b, acc);
 }
 
 // x0-streaming even-odd hop (output parity p, input parity q = 1 - p). A workgroup owns
@@ -260,7 +282,7 @@ __global__ __launch_bounds__(S) void hop_stream_kernel(HopArgs<R> A, int T, int 
     if (active) {
       const long long j = slice_j(x0);
       const Site st_ = decode(g, j, p);
-      V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
+      V2* o = A.out.ptr + rhs * A.out.rs + p * A.out.ps;
       bool sel = true;
       if (A.slb) {
         const int blk = x0 / A.slb;
@@ -282,9 +304,8 @@ __global__ __launch_bounds__(S) void hop_stream_kernel(HopArgs<R> A, int T, int 
 #pragma unroll
         for (int c = 0; c < 3; ++c) { nx[2][c] = -nx[2][c]; nx[3][c] = -nx[3][c]; }
       if (!sel) {
-        cx<R> z = {R(0), R(0)};
-#pragma unroll
-        for (int c = 0; c < 12; ++c) st<R>(o + c * TILE, z);
+        const cx<R> z[4][3] = {};
+        store_out<R, false>(o, nullptr, j, false, false, R(0), R(0), z);
       } else {
         cx<R> acc[4][3];
 #pragma unroll
@@ -341,28 +362,8 @@ __global__ __launch_bounds__(S) void hop_stream_kernel(HopArgs<R> A, int T, int 
               for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
           accum_recon<R>(0, true, uh, acc);
         }
-        if (A.g5_out) {
-#pragma unroll
-          for (int a = 2; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[a][c] = -acc[a][c];
-        }
-        if (A.x.ptr) {
-          const V2* xp = A.x.ptr + rhs * A.x.rs + p * A.x.ps + tiled(j, 0, 12);
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              cx<R> xv = ld<R>(xp + (a * 3 + c) * TILE);
-              cx<R> r = {A.a * xv.r + A.b * acc[a][c].r, A.a * xv.i + A.b * acc[a][c].i};
-              st<R>(o + (a * 3 + c) * TILE, r);
-            }
-        } else {
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) st<R>(o + (a * 3 + c) * TILE, A.b * acc[a][c]);
-        }
+        const V2* xo = A.x.ptr ? A.x.ptr + rhs * A.x.rs + p * A.x.ps : nullptr;
+        store_out<R, false>(o, xo, j, true, A.g5_out != 0, A.a, A.b, acc);
       }
       // the input of this step's forward hop is the backward input two steps later
       project<R>(0, true, nx, carry[(x0 + 1) & 1]);
@@ -436,26 +437,9 @@ __device__ __forceinline__ void hop_store(const HopArgs<R>& A, int p, long long 
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     if (r >= nr) continue;
-    V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps + tiled(j, 0, 12);
-    const V2* xp = A.x.ptr ? A.x.ptr + (r0 + r) * A.x.rs + p * A.x.ps + tiled(j, 0, 12) : nullptr;
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        cx<R> v = {R(0), R(0)};
-        if (sel) {
-          cx<R> h = acc[r][a][c];
-          if (A.g5_out && a >= 2) h = -h;
-          v = A.b * h;
-          if (xp) {
-            const cx<R> xv = ld<R>(xp + (a * 3 + c) * TILE);
-            v.r += A.a * xv.r;
-            v.i += A.a * xv.i;
-          }
-        }
-        if (NT) st_nt<R>(o + (a * 3 + c) * TILE, v);
-        else st<R>(o + (a * 3 + c) * TILE, v);
-      }
+    V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps;
+    const V2* xo = A.x.ptr ? A.x.ptr + (r0 + r) * A.x.rs + p * A.x.ps : nullptr;
+    store_out<R, NT>(o, xo, j, sel, A.g5_out != 0, A.a, A.b, acc[r]);
   }
 }
 
@@ -836,11 +820,25 @@ __global__ __launch_bounds__(128) void hop_band_kernel(HopArgs<R> A, int nck) {
 // one XCD are ordered tile-major with the rhs groups of a tile adjacent, so the groups of a
 // tile read each link at about the same time (L2 hits after the first). Tiles tile the
 // slice exactly (TA | L1, TB | L2); work-items t >= S only join the barriers.
-template <class R, int NR>
+//
+// The walk keeps the work-item's geometry fixed: the x1 / x2 neighbours and their LDS slots
+// are worked out once, the x3 neighbour follows from the x3 bit, which flips with x0, and
+// with V3h a multiple of 64 (LIN) every address advances by a constant per slice. Time
+// flips, block drops and selections depend on x0 only (uniform over the workgroup). The
+// LDS is read through volatile address-space-3 pointers, so that the compiler cannot merge
+// the LDS read of a tile neighbour with the memory load of a halo neighbour into one load
+// through a generic (flat) address.
+template <class T> using lds_ptr = __attribute__((address_space(3))) T*;
+
+template <class R, int NR, bool LIN, bool G5I, bool G5O>
 __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
   typedef typename vec2<R>::type V2;
   extern __shared__ char smem_raw[];
-  V2* lds = (V2*)smem_raw;                      // [2 copies][NR][12 components][S]
+  // LDS: [2 copies][NR][NU 16-byte units][S]; a unit is a pair of FP32 components or one
+  // FP64 component
+  typedef typename std::conditional<std::is_same<R, float>::value, f4v, d2v>::type UNIT;
+  constexpr int NU = std::is_same<R, float>::value ? 6 : 12;
+  const lds_ptr<UNIT> lds = (lds_ptr<UNIT>)smem_raw;
   const Geo& g = A.g;
   const int L3h = g.L3h;
   const int S = TA * TB * L3h;
@@ -859,28 +857,90 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
   const int lx3 = act ? t % L3h : 0;
   const int lx2 = act ? (t / L3h) % TB : 0;
   const int lx1 = act ? t / (L3h * TB) : 0;
-  const int s = ((x1a + lx1) * g.L2 + (x2a + lx2)) * L3h + lx3;
+  const int x1 = x1a + lx1, x2 = x2a + lx2;
+  const int s = (x1 * g.L2 + x2) * L3h + lx3;
   const int p = A.parity_out, q = 1 - p;
-  const V2* inb = A.in.ptr + q * A.in.ps;
-  const bool g5i = A.g5_in != 0;
+  const long long V3h = g.V3h, Vhp = g.Vhp;
   const int lb = A.lb;
-  const long long V3h = g.V3h;
+  const int b_even = (p + x1 + x2) & 1;           // x3 bit of the site at even x0
+
+  // x1 / x2 neighbours (index d: 0 x1+, 1 x1-, 2 x2+, 3 x2-): slice-local index offset and
+  // LDS slot (-1: in a neighbouring tile)
+  int dsn[4], kn[4];
+  {
+    const int y1f = x1 + 1 == g.L1 ? 0 : x1 + 1, y1b = x1 == 0 ? g.L1 - 1 : x1 - 1;
+    const int y2f = x2 + 1 == g.L2 ? 0 : x2 + 1, y2b = x2 == 0 ? g.L2 - 1 : x2 - 1;
+    const int st1 = g.L2 * L3h;
+    dsn[0] = (y1f - x1) * st1;
+    dsn[1] = (y1b - x1) * st1;
+    dsn[2] = (y2f - x2) * L3h;
+    dsn[3] = (y2b - x2) * L3h;
+    kn[0] = (y1f - x1a >= 0 && y1f - x1a < TA) ? t + (y1f - x1) * L3h * TB : -1;
+    kn[1] = (y1b - x1a >= 0 && y1b - x1a < TA) ? t + (y1b - x1) * L3h * TB : -1;
+    kn[2] = (y2f - x2a >= 0 && y2f - x2a < TB) ? t + (y2f - x2) * L3h : -1;
+    kn[3] = (y2b - x2a >= 0 && y2b - x2a < TB) ? t + (y2b - x2) * L3h : -1;
+  }
+  // offset (complex numbers) of component 0 of slice-local site sl in slice x0 of a field
+  // with NC components per site
+  auto off = [&](int x0, int sl, int NC) -> long long {
+    if constexpr (LIN) return (long long)x0 * V3h * NC + tiled(sl, 0, NC);
+    else return tiled((long long)x0 * V3h + sl, 0, NC);
+  };
+  // site (x0, sl) in the FP32 pair layout or the FP64 tiled layout (sidx)
+  auto soff = [&](int x0, int sl) -> long long {
+    if constexpr (LIN) return (long long)x0 * V3h * 12 + sidx<R>(sl, 0);
+    else return sidx<R>((long long)x0 * V3h + sl, 0);
+  };
+  const V2* inb = A.in.ptr + q * A.in.ps;
+  auto load_sp = [&](int r, long long o, cx<R> sp[4][3]) {
+    const V2* b = inb + (r0 + r) * A.in.rs + o;
+    cx<R> v[12];
+    if constexpr (std::is_same<R, float>::value) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const f4v w = *(const f4v*)(b + 2 * k * TILE);
+        v[2 * k] = {w.x, w.y};
+        v[2 * k + 1] = {w.z, w.w};
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = ld<R>(b + c * TILE);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sp[a][c] = (G5I && a >= 2) ? -v[a * 3 + c] : v[a * 3 + c];
+  };
+  auto link = [&](int mu, int par, long long o24, cx<R> m[9]) { load_link_at<R>(A.U, Vhp, mu, par, o24, m); };
+  auto slot = [&](int cp, int r, int u, int k) { return lds + ((cp * NR + r) * NU + u) * S + k; };
+  auto put = [&](int cp, int r, const cx<R> sp[4][3]) {
+    const cx<R>* v = &sp[0][0];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      if constexpr (std::is_same<R, float>::value)
+        *slot(cp, r, u, t) = f4v{v[2 * u].r, v[2 * u].i, v[2 * u + 1].r, v[2 * u + 1].i};
+      else
+        *slot(cp, r, u, t) = d2v{v[u].r, v[u].i};
+    }
+  };
+  // volatile: the LDS reads stay LDS reads (ds_read), never merged with the memory load
+  // that may overwrite them into one load through a generic address
+  auto get = [&](int cp, int r, int k, cx<R> sp[4][3]) {
+    cx<R>* v = &sp[0][0];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const volatile __attribute__((address_space(3))) UNIT* q = slot(cp, r, u, k);
+      const UNIT w = *q;
+      if constexpr (std::is_same<R, float>::value) {
+        v[2 * u] = {w.x, w.y};
+        v[2 * u + 1] = {w.z, w.w};
+      } else {
+        v[u] = {w.x, w.y};
+      }
+    }
+  };
   auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
   auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
-  auto wrap = [&](int x) { return x < 0 ? x + g.L0 : (x >= g.L0 ? x - g.L0 : x); };
-  auto slot = [&](int cp, int r, int c, int k) { return lds + ((cp * NR + r) * 12 + c) * S + k; };
-  auto put = [&](int cp, int r, const cx<R> sp[4][3]) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) st<R>(slot(cp, r, a * 3 + c, t), sp[a][c]);
-  };
-  auto get = [&](int cp, int r, int k, cx<R> sp[4][3]) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) sp[a][c] = ld<R>(slot(cp, r, a * 3 + c, k));
-  };
 
   // U_0(x0 - 1, s)^+ (1 + g0) in(x0 - 1, s) for the backward time hop of the current output
   cx<R> carry[NR][2][3];
@@ -892,17 +952,18 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
       for (int c = 0; c < 3; ++c) carry[r][h][c] = {R(0), R(0)};
   if (act) {
     const bool need_c = hop_selected(A, x0a) && bwd_on(x0a);
+    const int xp = x0a == 0 ? g.L0 - 1 : x0a - 1;
     cx<R> m[9];
-    if (need_c) load_link<R>(A.U, g.Vhp, 0, q, (long long)wrap(x0a - 1) * V3h + s, m);
+    if (need_c) link(0, q, off(xp, s, 24), m);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       if (r < nr) {
         cx<R> sp[4][3];
-        load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)x0a * V3h + s, g5i, sp);
+        load_sp(r, soff(x0a, s), sp);
         put(0, r, sp);
         if (need_c) {
           cx<R> h[2][3];
-          load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)wrap(x0a - 1) * V3h + s, g5i, sp);
+          load_sp(r, soff(xp, s), sp);
           project<R>(0, true, sp, h);
           su3_dag_mul<R>(m, h[0], carry[r][0]);
           su3_dag_mul<R>(m, h[1], carry[r][1]);
@@ -919,10 +980,12 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
 
   for (int x0 = x0a; x0 < x0b; ++x0) {
     const int cp = (x0 - x0a) & 1;
+    const bool sel = hop_selected(A, x0);
+    const bool use_f = sel && fwd_on(x0), use_b = sel && bwd_on(x0);
+    const bool stage = x0 + 1 < x0b;
+    const bool carry_next = stage && hop_selected(A, x0 + 1) && bwd_on(x0 + 1);
     if (act) {
-      const long long j = (long long)x0 * V3h + s;
-      const Site st_ = decode(g, j, p);
-      const bool sel = hop_selected(A, x0);
+      const long long o24 = off(x0, s, 24);
       cx<R> acc[NR][4][3];
 #pragma unroll
       for (int r = 0; r < NR; ++r)
@@ -931,16 +994,15 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
 #pragma unroll
           for (int c = 0; c < 3; ++c) acc[r][a][c] = {R(0), R(0)};
       // input (x0 + 1, s): forward time hop now, LDS copy for the next step
-      const bool use_f = sel && fwd_on(x0);
-      const bool stage = x0 + 1 < x0b;
       if (use_f || stage) {
+        const int xn = x0 + 1 == g.L0 ? 0 : x0 + 1;
         cx<R> m[9];
-        if (use_f) load_link<R>(A.U, g.Vhp, 0, p, j, m);
+        if (use_f) link(0, p, o24, m);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r < nr) {
             cx<R> sp[4][3];
-            load_spinor<R>(inb + (r0 + r) * A.in.rs, (long long)wrap(x0 + 1) * V3h + s, g5i, sp);
+            load_sp(r, soff(xn, s), sp);
             if (stage) put(cp ^ 1, r, sp);
             if (use_f) {
               cx<R> h[2][3], uh[2][3];
@@ -957,41 +1019,37 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
           }
         }
       }
-      if (sel) {
-        if (bwd_on(x0))
+      if (use_b)
 #pragma unroll
-          for (int r = 0; r < NR; ++r) accum_recon<R>(0, true, carry[r], acc[r]);
-        // spatial hops: tile neighbours from the LDS copy of slice x0, the halo from memory
+        for (int r = 0; r < NR; ++r) accum_recon<R>(0, true, carry[r], acc[r]);
+      if (sel) {
+        // x3 neighbours from the x3 bit of this slice (always in the tile)
+        const int b = b_even ^ (x0 & 1);
+        const int h3f = b ? (lx3 + 1 == L3h ? 0 : lx3 + 1) : lx3;
+        const int h3b = b ? lx3 : (lx3 == 0 ? L3h - 1 : lx3 - 1);
 #pragma unroll
         for (int mu = 1; mu < 4; ++mu) {
 #pragma unroll
           for (int dir = 0; dir < 2; ++dir) {
-            const long long jn = nbr(g, st_, j, mu, dir == 0 ? +1 : -1);
-            int k = -1;     // LDS slot of the neighbour, -1: outside the tile
+            int sn, k;
             if (mu == 3) {
-              k = t - lx3 + (int)(jn - (j - st_.x3h));
-            } else if (mu == 2) {
-              int y = st_.x2 + (dir == 0 ? 1 : -1);
-              y = y < 0 ? y + g.L2 : (y >= g.L2 ? y - g.L2 : y);
-              const int ly = y - x2a;
-              if (ly >= 0 && ly < TB) k = t + (ly - lx2) * L3h;
+              const int h = dir == 0 ? h3f : h3b;
+              sn = s - lx3 + h;
+              k = t - lx3 + h;
             } else {
-              int y = st_.x1 + (dir == 0 ? 1 : -1);
-              y = y < 0 ? y + g.L1 : (y >= g.L1 ? y - g.L1 : y);
-              const int ly = y - x1a;
-              if (ly >= 0 && ly < TA) k = t + (ly - lx1) * L3h * TB;
+              const int d = (mu == 1 ? 0 : 2) + dir;
+              sn = s + dsn[d];
+              k = kn[d];
             }
             cx<R> m[9];
-            if (dir == 0) load_link<R>(A.U, g.Vhp, mu, p, j, m);
-            else load_link<R>(A.U, g.Vhp, mu, q, jn, m);
+            if (dir == 0) link(mu, p, o24, m);
+            else link(mu, q, off(x0, sn, 24), m);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
               if (r < nr) {
                 cx<R> sp[4][3], h[2][3], uh[2][3];
-                // the LDS read and the memory load must not share one pointer (a select
-                // between LDS and global addresses): read a valid slot, then overwrite
                 get(cp, r, k >= 0 ? k : t, sp);
-                if (k < 0) load_spinor<R>(inb + (r0 + r) * A.in.rs, jn, g5i, sp);
+                if (k < 0) load_sp(r, soff(x0, sn), sp);
                 project<R>(mu, dir == 1, sp, h);
                 if (dir == 0) {
                   su3_mul<R>(m, h[0], uh[0]);
@@ -1006,11 +1064,18 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
           }
         }
       }
-      hop_store<R, NR, true>(A, p, j, r0, nr, sel, acc);
+      // out = a x + b (g5) acc, zero on unselected slices, non-temporal
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (r >= nr) continue;
+        V2* o = A.out.ptr + (r0 + r) * A.out.rs + p * A.out.ps;
+        const V2* xo = A.x.ptr ? A.x.ptr + (r0 + r) * A.x.rs + p * A.x.ps : nullptr;
+        store_out<R, true>(o, xo, (long long)x0 * V3h + s, sel, G5O, A.a, A.b, acc[r]);
+      }
       // the backward time hop of output (x0 + 1, s) from input (x0, s) (LDS copy)
-      if (x0 + 1 < x0b && hop_selected(A, x0 + 1) && bwd_on(x0 + 1)) {
+      if (carry_next) {
         cx<R> m[9];
-        load_link<R>(A.U, g.Vhp, 0, q, j, m);
+        link(0, q, o24, m);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r < nr) {
@@ -1097,10 +1162,21 @@ template <class R, int NR> static void launch_slab(const HopArgs<R>& A, hipStrea
   const int S = TA * TB * A.g.L3h;
   const int ntile = (A.g.L1 / TA) * (A.g.L2 / TB);
   const long long groups = (A.nrhs + NR - 1) / NR;
-  const int threads = (S + 63) / 64 * 64;
+  const dim3 grid((unsigned)(8LL * ntile * groups)), blk((S + 63) / 64 * 64);
   const size_t lds = (size_t)S * per_site;
-  hipLaunchKernelGGL((hop_slab_kernel<R, NR>), dim3((unsigned)(8LL * ntile * groups)), dim3(threads), lds, st,
-                     A, TA, TB);
+  const bool lin = A.g.V3h % TILE == 0;
+#define SAP_SLAB(LIN, G5I, G5O) hipLaunchKernelGGL((hop_slab_kernel<R, NR, LIN, G5I, G5O>), grid, blk, lds, st, A, TA, TB)
+#define SAP_SLAB_G5(LIN)                                      \
+  do {                                                        \
+    if (A.g5_in && A.g5_out) SAP_SLAB(LIN, true, true);       \
+    else if (A.g5_in) SAP_SLAB(LIN, true, false);             \
+    else if (A.g5_out) SAP_SLAB(LIN, false, true);            \
+    else SAP_SLAB(LIN, false, false);                         \
+  } while (0)
+  if (lin) SAP_SLAB_G5(true);
+  else SAP_SLAB_G5(false);
+#undef SAP_SLAB_G5
+#undef SAP_SLAB
 }
 
 template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {

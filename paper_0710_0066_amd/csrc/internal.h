@@ -11,7 +11,8 @@
 namespace sap {
 
 // A spinor field in the library layout: element (rhs, parity, component c, site j) of
-// complex type at  ptr + rhs*rs + parity*ps + tiled(j, c, 12)  (in complex numbers).
+// complex type at  ptr + rhs*rs + parity*ps + sidx<R>(j, c)  (in complex numbers;
+// tiled(j, c, 12) for FP64 and FP16, pairs of components per 16-byte word for FP32).
 // Full fields: rs = 24*Vhp, ps = 12*Vhp. Single-parity fields: rs = 12*Vhp, ps = 0.
 // FP16 (h16) fields also hold one FP32 norm per site: the components are stored divided
 // by it, and the norms of (rhs, parity) start at  (float*)(ptr + rhs*rs + no) + parity*Vhp.
@@ -20,8 +21,9 @@ namespace sap {
 // Gauge field: link (parity p, site j, mu, entry e = 3*row + col) at
 //   p*36*Vhp + tiled(j, 9*mu + e, 36)   (FP64);
 // the copies the hop kernels read (FP64, FP32, FP16) hold rows 0 and 1 only (e < 6), at
-// p*24*Vhp + tiled(j, 6*mu + e, 24), and the kernels rebuild row 2 from unitarity and unit
-// determinant.
+// p*24*Vhp + tiled(j, 6*mu + e, 24) (FP32: the entries of a tile row stored in pairs, one
+// 16-byte word per lane, see gauge_to_f32_kernel), and the kernels rebuild row 2 from
+// unitarity and unit determinant.
 // Momenta / forces (float64): (p, j, mu, a) at  p*32*Vhp + tiled(j, 8*mu + a, 32).
 template <class R> struct Field {
   typename vec2<R>::type* ptr;

@@ -33,7 +33,7 @@ __global__ void pack_spinor_kernel(Geo g, typename vec2<R>::type* out, const dou
     double2 v = src[k];
     typename vec2<R>::type w;
     w.x = (R)v.x; w.y = (R)v.y;
-    o[tiled(j, k, 12)] = w;
+    o[sidx<R>(j, k)] = w;
   }
 }
 
@@ -49,7 +49,7 @@ __global__ void unpack_spinor_kernel(Geo g, double2* out, const typename vec2<R>
   const typename vec2<R>::type* src = in + (rhs * 2 + p) * 12 * g.Vhp;
   double2* o = out + (rhs * V + i) * 12;
   for (int k = 0; k < 12; ++k) {
-    typename vec2<R>::type v = src[tiled(j, k, 12)];
+    typename vec2<R>::type v = src[sidx<R>(j, k)];
     o[k] = make_double2((double)v.x, (double)v.y);
   }
 }
@@ -82,8 +82,12 @@ __global__ void unpack_gauge_kernel(Geo g, double2* out, const double2* U64) {
       out[(i * 4 + mu) * 9 + e] = U64[p * 36 * g.Vhp + tiled(j, 9 * mu + e, 36)];
 }
 
-// FP32 / FP16 link copies keep the first two rows of each link (6 of 9 entries): entry k of
-// the copy is (parity, site j, component c = 6 mu + e) at  p*24*Vhp + tiled(j, c, 24)
+// FP64 / FP32 / FP16 link copies keep the first two rows of each link (6 of 9 entries):
+// entry (parity p, site j, component c = 6 mu + e) of the FP64 and FP16 copies is at
+// p*24*Vhp + tiled(j, c, 24). The FP32 copy stores the entries of a tile row in pairs
+// (2k, 2k + 1) of one link, one 16-byte word per lane:
+//   p*24*Vhp + (j / 64)*24*64 + (c - c % 2)*64 + 2*(j % 64) + c % 2,
+// so that a link is three 16-byte loads per work-item.
 __global__ void gauge_to_f32_kernel(long long Vhp, double2* U64c, float2* U32, __half2* U16, const double2* U64) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= 48 * Vhp) return;
@@ -92,7 +96,7 @@ __global__ void gauge_to_f32_kernel(long long Vhp, double2* U64c, float2* U32, _
   const long long j = tile * TILE + lane;
   const double2 v = U64[p * 36 * Vhp + tiled(j, (int)(9 * (c / 6) + c % 6), 36)];
   U64c[k] = v;
-  U32[k] = make_float2((float)v.x, (float)v.y);
+  U32[p * 24 * Vhp + tile * 24 * TILE + (c - (c & 1)) * TILE + 2 * lane + (c & 1)] = make_float2((float)v.x, (float)v.y);
   U16[k] = __floats2half2_rn((float)v.x, (float)v.y);
 }
 

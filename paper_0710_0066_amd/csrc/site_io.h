@@ -2,8 +2,10 @@
 // yields the 12 components of one site at the arithmetic precision; a writer takes them
 // one by one. For FP16 storage (h16) the components of a site are stored divided by the
 // site norm (their largest magnitude, FP32): the reader scales by it, and the writer
-// buffers the site and stores it, with its new norm, at close(). For double and float a
-// writer stores each component at once, so those kernels keep their plain access pattern.
+// buffers the site and stores it, with its new norm, at close(). FP32 sites are stored as
+// 6 pairs of components, one 16-byte word each (sidx): the reader loads a pair per two
+// components (the compiler keeps one load for both), and the writer buffers the site and
+// stores the 6 pairs at close(). For double a writer stores each component at once.
 #pragma once
 #include <type_traits>
 #include "internal.h"
@@ -11,6 +13,7 @@
 namespace sap {
 
 template <class R> constexpr bool is_h16 = std::is_same<R, h16>::value;
+template <class R> constexpr bool is_f32 = std::is_same<R, float>::value;
 template <class R> using arith_t = typename arith<R>::type;
 
 // norms of block (rhs, parity p) of an FP16 field
@@ -20,13 +23,14 @@ __device__ __forceinline__ float* norm_ptr16(const Field<h16>& f, int rhs, int p
 
 template <class R> struct SiteR {
   const typename vec2<R>::type* b;   // component 0 of the site; component c at b + c*TILE
+                                     // (FP32: pair k = components 2k, 2k + 1 at b + 2k*TILE)
   float m;                           // h16: site norm
 };
 
 template <class R>
 __device__ __forceinline__ SiteR<R> site_r(const Field<R>& f, int rhs, int p, long long j, long long Vhp) {
   SiteR<R> s;
-  s.b = f.ptr + rhs * f.rs + p * f.ps + tiled(j, 0, 12);
+  s.b = f.ptr + rhs * f.rs + p * f.ps + sidx<R>(j, 0);
   if constexpr (is_h16<R>) s.m = norm_ptr16(f, rhs, p, Vhp)[j];
   else s.m = 1.0f;
   return s;
@@ -36,6 +40,9 @@ template <class R> __device__ __forceinline__ cx<arith_t<R>> get(const SiteR<R>&
   if constexpr (is_h16<R>) {
     const float2 v = __half22float2(s.b[c * TILE]);
     return {v.x * s.m, v.y * s.m};
+  } else if constexpr (is_f32<R>) {
+    const f4v w = *(const f4v*)(s.b + (c & ~1) * TILE);
+    return (c & 1) ? cx<float>{w.z, w.w} : cx<float>{w.x, w.y};
   } else {
     return ld<R>(s.b + c * TILE);
   }
@@ -44,20 +51,20 @@ template <class R> __device__ __forceinline__ cx<arith_t<R>> get(const SiteR<R>&
 template <class R> struct SiteW {
   typename vec2<R>::type* b;
   float* n;                              // h16: where the site norm goes
-  cx<float> v[is_h16<R> ? 12 : 1];       // h16: the buffered site
+  cx<float> v[(is_h16<R> || is_f32<R>) ? 12 : 1];   // h16, FP32: the buffered site
 };
 
 template <class R>
 __device__ __forceinline__ SiteW<R> site_w(const Field<R>& f, int rhs, int p, long long j, long long Vhp) {
   SiteW<R> w;
-  w.b = f.ptr + rhs * f.rs + p * f.ps + tiled(j, 0, 12);
+  w.b = f.ptr + rhs * f.rs + p * f.ps + sidx<R>(j, 0);
   if constexpr (is_h16<R>) w.n = norm_ptr16(f, rhs, p, Vhp) + j;
   else w.n = nullptr;
   return w;
 }
 
 template <class R> __device__ __forceinline__ void put(SiteW<R>& w, int c, cx<arith_t<R>> a) {
-  if constexpr (is_h16<R>) w.v[c] = a;
+  if constexpr (is_h16<R> || is_f32<R>) w.v[c] = a;
   else st<R>(w.b + c * TILE, a);
 }
 
@@ -70,6 +77,10 @@ template <class R> __device__ __forceinline__ void close(SiteW<R>& w) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) w.b[c * TILE] = __floats2half2_rn(w.v[c].r * inv, w.v[c].i * inv);
     *w.n = m;
+  } else if constexpr (is_f32<R>) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      *(f4v*)(w.b + 2 * k * TILE) = f4v{w.v[2 * k].r, w.v[2 * k].i, w.v[2 * k + 1].r, w.v[2 * k + 1].i};
   }
 }
 
