@@ -80,6 +80,25 @@ __device__ __forceinline__ void load_link(const typename vec2<R>::type* U, long 
                                           int par, long long j, cx<R> m[9]) {
   load_link_at<R>(U, Vhp, mu, par, tiled(j, 0, 24), m);
 }
+// the two stored rows only (entries 0..5), for kernels that load a link ahead of its use
+template <class R>
+__device__ __forceinline__ void load_link_raw(const typename vec2<R>::type* U, long long Vhp, int mu, int par,
+                                              long long o24, cx<R> m[6]) {
+  if constexpr (std::is_same<R, float>::value) {
+    const long long lane = o24 & (TILE - 1);
+    const float4* p = (const float4*)(U + par * 24 * Vhp + (o24 - lane) + 6 * mu * TILE) + lane;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float4 v = p[k * TILE];
+      m[2 * k] = {v.x, v.y};
+      m[2 * k + 1] = {v.z, v.w};
+    }
+  } else {
+    const typename vec2<R>::type* p = U + par * 24 * Vhp + o24 + 6 * mu * TILE;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) m[e] = ld<R>(p + e * TILE);
+  }
+}
 
 // Work-item mappings (MAP):
 //  SITE  one work-item per (site, rhs); a workgroup holds 256 sites of one parity (half
@@ -827,11 +846,16 @@ __global__ __launch_bounds__(128) void hop_band_kernel(HopArgs<R> A, int nck) {
 // flips, block drops and selections depend on x0 only (uniform over the workgroup). The
 // LDS is read through volatile address-space-3 pointers, so that the compiler cannot merge
 // the LDS read of a tile neighbour with the memory load of a halo neighbour into one load
-// through a generic (flat) address.
+// through a generic (flat) address. The link of the next spatial hop is loaded while the
+// current one is computed (after the current hop's halo spinor, since loads complete in
+// issue order). The FP32 one-rhs kernel is held to three waves per SIMD (at most 168
+// registers), the occupancy the pipelined loop is measured fastest at.
 template <class T> using lds_ptr = __attribute__((address_space(3))) T*;
 
 template <class R, int NR, bool LIN, bool G5I, bool G5O>
-__global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu((std::is_same<R, float>::value && NR == 1) ? 3 : 2)))
+void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
   typedef typename vec2<R>::type V2;
   extern __shared__ char smem_raw[];
   // LDS: [2 copies][NR][NU 16-byte units][S]; a unit is a pair of FP32 components or one
@@ -1022,44 +1046,103 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
       if (use_b)
 #pragma unroll
         for (int r = 0; r < NR; ++r) accum_recon<R>(0, true, carry[r], acc[r]);
-      if (sel) {
-        // x3 neighbours from the x3 bit of this slice (always in the tile)
-        const int b = b_even ^ (x0 & 1);
-        const int h3f = b ? (lx3 + 1 == L3h ? 0 : lx3 + 1) : lx3;
-        const int h3b = b ? lx3 : (lx3 == 0 ? L3h - 1 : lx3 - 1);
+      // spatial hop i = 2 (mu - 1) + dir: neighbour site sn and its LDS slot k (-1: halo);
+      // x3 neighbours follow from the x3 bit of this slice and are always in the tile
+      const int b = b_even ^ (x0 & 1);
+      const int h3f = b ? (lx3 + 1 == L3h ? 0 : lx3 + 1) : lx3;
+      const int h3b = b ? lx3 : (lx3 == 0 ? L3h - 1 : lx3 - 1);
+      auto nbr_of = [&](int i, int& sn, int& k) {
+        if (i >= 4) {
+          const int h = i == 4 ? h3f : h3b;
+          sn = s - lx3 + h;
+          k = t - lx3 + h;
+        } else {
+          sn = s + dsn[i];
+          k = kn[i];
+        }
+      };
+      // one spatial hop: spinors sp (one per rhs) through link m (all three rows)
+      auto hop_acc = [&](int i, const cx<R> m[9], cx<R> sp[NR][4][3]) {
+        const int mu = 1 + i / 2, dir = i & 1;
 #pragma unroll
-        for (int mu = 1; mu < 4; ++mu) {
-#pragma unroll
-          for (int dir = 0; dir < 2; ++dir) {
-            int sn, k;
-            if (mu == 3) {
-              const int h = dir == 0 ? h3f : h3b;
-              sn = s - lx3 + h;
-              k = t - lx3 + h;
+        for (int r = 0; r < NR; ++r) {
+          if (r < nr) {
+            cx<R> h[2][3], uh[2][3];
+            project<R>(mu, dir == 1, sp[r], h);
+            if (dir == 0) {
+              su3_mul<R>(m, h[0], uh[0]);
+              su3_mul<R>(m, h[1], uh[1]);
             } else {
-              const int d = (mu == 1 ? 0 : 2) + dir;
-              sn = s + dsn[d];
-              k = kn[d];
+              su3_dag_mul<R>(m, h[0], uh[0]);
+              su3_dag_mul<R>(m, h[1], uh[1]);
             }
-            cx<R> m[9];
-            if (dir == 0) link(mu, p, o24, m);
-            else link(mu, q, off(x0, sn, 24), m);
+            accum_recon<R>(mu, dir == 1, uh, acc[r]);
+          }
+        }
+      };
+      // FP32: the link of the next hop is loaded before the current hop's arithmetic, so
+      // that its latency overlaps with it; its two stored rows wait in nxt (FP64 has no
+      // registers to spare for that and loads each link just before its hop)
+      constexpr bool PIPE = std::is_same<R, float>::value;
+      // raw two-row link of hop i (i = 6: U_0(x0, s) of the input parity for the carry)
+      auto link_raw = [&](int i, cx<R> raw[6]) {
+        int sn, k;
+        nbr_of(i, sn, k);
+        const int mu = i < 6 ? 1 + i / 2 : 0;
+        const int par = i == 6 || (i & 1) ? q : p;
+        load_link_raw<R>(A.U, Vhp, mu, par, i < 6 && (i & 1) ? off(x0, sn, 24) : o24, raw);
+      };
+      cx<R> nxt[PIPE ? 6 : 1];
+      if constexpr (PIPE) {
+        if (sel) link_raw(0, nxt);
+        else if (carry_next) link_raw(6, nxt);
+        if (sel) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) {
+            int sn, k;
+            nbr_of(i, sn, k);
+            cx<R> m[9], sp[NR][4][3];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+            // the halo spinor is requested before the next link, so that waiting for it
+            // leaves the link's loads in flight (loads complete in issue order)
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
               if (r < nr) {
-                cx<R> sp[4][3], h[2][3], uh[2][3];
-                get(cp, r, k >= 0 ? k : t, sp);
-                if (k < 0) load_sp(r, soff(x0, sn), sp);
-                project<R>(mu, dir == 1, sp, h);
-                if (dir == 0) {
-                  su3_mul<R>(m, h[0], uh[0]);
-                  su3_mul<R>(m, h[1], uh[1]);
-                } else {
-                  su3_dag_mul<R>(m, h[0], uh[0]);
-                  su3_dag_mul<R>(m, h[1], uh[1]);
-                }
-                accum_recon<R>(mu, dir == 1, uh, acc[r]);
+                get(cp, r, k >= 0 ? k : t, sp[r]);
+                if (k < 0) load_sp(r, soff(x0, sn), sp[r]);
               }
+            }
+            if (i < 5) link_raw(i + 1, nxt);
+            else if (carry_next) link_raw(6, nxt);
+            third_row<R>(m);
+            hop_acc(i, m, sp);
+          }
+        }
+      } else if (sel) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          const int mu = 1 + i / 2, dir = i & 1;
+          int sn, k;
+          nbr_of(i, sn, k);
+          cx<R> m[9];
+          if (dir == 0) link(mu, p, o24, m);
+          else link(mu, q, off(x0, sn, 24), m);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            if (r < nr) {
+              cx<R> sp[4][3], h[2][3], uh[2][3];
+              get(cp, r, k >= 0 ? k : t, sp);
+              if (k < 0) load_sp(r, soff(x0, sn), sp);
+              project<R>(mu, dir == 1, sp, h);
+              if (dir == 0) {
+                su3_mul<R>(m, h[0], uh[0]);
+                su3_mul<R>(m, h[1], uh[1]);
+              } else {
+                su3_dag_mul<R>(m, h[0], uh[0]);
+                su3_dag_mul<R>(m, h[1], uh[1]);
+              }
+              accum_recon<R>(mu, dir == 1, uh, acc[r]);
             }
           }
         }
@@ -1072,10 +1155,17 @@ __global__ __launch_bounds__(512) void hop_slab_kernel(HopArgs<R> A, int TA, int
         const V2* xo = A.x.ptr ? A.x.ptr + (r0 + r) * A.x.rs + p * A.x.ps : nullptr;
         store_out<R, true>(o, xo, (long long)x0 * V3h + s, sel, G5O, A.a, A.b, acc[r]);
       }
-      // the backward time hop of output (x0 + 1, s) from input (x0, s) (LDS copy)
+      // the backward time hop of output (x0 + 1, s) from input (x0, s) (LDS copy); its link
+      // is already in nxt
       if (carry_next) {
         cx<R> m[9];
-        link(0, q, o24, m);
+        if constexpr (PIPE) {
+#pragma unroll
+          for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+          third_row<R>(m);
+        } else {
+          link(0, q, o24, m);
+        }
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r < nr) {
