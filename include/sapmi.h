@@ -193,7 +193,8 @@ typedef struct {
 
 /* ---- context ---------------------------------------------------------------- */
 
-/* Version of this ABI (major*100 + minor): 101 (sap_hmc4_params.part_solve added). */
+/* Version of this ABI (major*100 + minor): 102 (hop mapping 20 added; sap_tune writes 126
+ * floats). */
 int sap_version(void);
 
 /* Host-only geometry check (no HIP call): SAP_OK or SAP_E_ARG. */
@@ -277,10 +278,13 @@ int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parit
  * values by TB x2 values by all of x3, staged in LDS so that the spatial hops inside the
  * tile read the LDS copy; 1 rhs per work-item with tiles of up to 40 KB / 80 KB of LDS
  * (slab1 / slab1w) or 2 rhs per work-item (slab2); the full operator runs them as march1 /
- * march1 / march2). FP16 storage has site and march1 / 2 / 4 only (the other maps run as
- * one of these). us_out (host, may be NULL): 120 floats, microseconds per launch (-1: not
- * applicable), ordered [full f64, full f32, even-odd f64, even-odd f32, full f16, even-odd
- * f16] x the 20 mappings. Uses the solver
+ * march1 / march2), 20 slabd (even-odd FP32 hop: the slab order with each slice of the
+ * tile and its x1 / x2 halo staged in LDS by direct memory-to-LDS loads, so that every
+ * spatial neighbour is read from LDS; FP64 runs it as slab1, the full operator as march1).
+ * FP16 storage has site and march1 / 2 / 4 only (the other maps run as one of these).
+ * us_out (host, may be NULL): 126 floats, microseconds per launch (-1: not applicable),
+ * ordered [full f64, full f32, even-odd f64, even-odd f32, full f16, even-odd f16] x the
+ * 21 mappings. Uses the solver
  * workspace; synchronises. Untuned calls use site for one rhs and lane4 (FP16: site) for
  * several. */
 int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
@@ -290,7 +294,8 @@ int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
  * order, 7 reg2, 8 reg4, 9 / 10 reg2 / reg4 group-slowest, 11 / 12 / 13 x0-marching with
  * 1 / 2 / 4 rhs per work-item, 14 / 15 x0-walking with 1 / 2 rhs (march1 / march2 for
  * the full operator), 16 x0-band (march1 for the full operator), 17 / 18 / 19 slab1 /
- * slab1w / slab2 (march1 / march1 / march2 for the full operator); -1 restores the
+ * slab1w / slab2 (march1 / march1 / march2 for the full operator), 20 slabd (FP32; slab1
+ * for FP64, march1 for the full operator and for FP16); -1 restores the
  * default), for the full operator (full = 1) or the even-odd hop (full = 0) at precision
  * prec. */
 int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);

@@ -307,11 +307,11 @@ HOP_MAP_REG2, HOP_MAP_REG4, HOP_MAP_REG2_SWEEP, HOP_MAP_REG4_SWEEP = 7, 8, 9, 10
 HOP_MAP_MARCH1, HOP_MAP_MARCH2, HOP_MAP_MARCH4 = 11, 12, 13
 HOP_MAP_WALK1, HOP_MAP_WALK2 = 14, 15
 HOP_MAP_BAND1 = 16
-HOP_MAP_SLAB1, HOP_MAP_SLAB1W, HOP_MAP_SLAB2 = 17, 18, 19
-HOP_NMAP = 20
+HOP_MAP_SLAB1, HOP_MAP_SLAB1W, HOP_MAP_SLAB2, HOP_MAP_SLABD = 17, 18, 19, 20
+HOP_NMAP = 21
 HOP_MAP_NAMES = ["site", "lane4", "wave4", "stream", "site_sweep", "lane4_sweep", "wave4_sweep", "reg2", "reg4",
                  "reg2_sweep", "reg4_sweep", "march1", "march2", "march4", "walk1", "walk2", "band1",
-                 "slab1", "slab1w", "slab2"]
+                 "slab1", "slab1w", "slab2", "slabd"]
 
 
 def sap_set_hop_map(ctx, full, prec, nrhs, hop_map):

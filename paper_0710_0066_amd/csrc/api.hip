@@ -39,7 +39,7 @@ static std::string geom_problem(const sap_geom* g) {
 
 extern "C" {
 
-int sap_version(void) { return 101; }
+int sap_version(void) { return 102; }
 
 int sap_check_geom(const sap_geom* g) {
   std::string p = geom_problem(g);

@@ -1182,6 +1182,291 @@ void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
   }
 }
 
+// Slab hop with direct memory-to-LDS staging (FP32, one rhs per workgroup). The band and
+// tile are those of the slab kernel, but the LDS holds one input slice of the tile together
+// with its x1 / x2 halo, written by global_load_lds (16 bytes per lane, no registers) after
+// a barrier, so that every spatial neighbour of a step is read from LDS and the memory
+// latency of a step is paid once, in the load of the next slice. The forward time hop of
+// output x0 - 1 uses the same LDS copy of slice x0 at the start of the step, so the partial
+// output x0 - 1 (spatial hops and backward hop) is held in registers across the load; the
+// backward half-spinor of output x0 + 1 is computed from slice x0 before it is replaced.
+// A halo site is also the input of a neighbouring tile's workgroup in the same step; it is
+// read from L2 only while the two workgroups stay within a fraction of a step of each
+// other. LDS: [6 pair units][kSlabdUnit] holding S tile sites, then H
+// halo sites (2 TB L3h in x1, 2 TA L3h in x2; none where the tile spans the direction),
+// S + H <= kSlabdUnit; the fixed unit stride keeps the unit offsets immediate.
+constexpr int kSlabdUnit = 416;
+
+template <bool LIN, bool G5I, bool G5O>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
+void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
+  typedef float R;
+  typedef float2 V2;
+  extern __shared__ char smem_raw[];
+  const lds_ptr<f4v> lds = (lds_ptr<f4v>)smem_raw;
+  const Geo& g = A.g;
+  const int L3h = g.L3h;
+  const int S = TA * TB * L3h;
+  const int F1 = TA < g.L1 ? TB * L3h : 0, F2 = TB < g.L2 ? TA * L3h : 0;   // halo face sizes
+  const int H = 2 * (F1 + F2);
+  constexpr int SH = kSlabdUnit;
+  const int nt2 = g.L2 / TB, ntile = (g.L1 / TA) * nt2;
+  // XCD k walks x0 band k of 8 over all tiles, the rhs of a tile next to each other (they
+  // share its links)
+  const int xcd = blockIdx.x & 7;
+  const int l = blockIdx.x >> 3;
+  const int tile = l / A.nrhs;
+  const int r0 = l - tile * A.nrhs;
+  const int x0a = g.L0 * xcd / 8, x0b = g.L0 * (xcd + 1) / 8;
+  if (tile >= ntile || x0a >= x0b) return;      // whole workgroup, before any barrier
+  const int x1a = (tile / nt2) * TA, x2a = (tile % nt2) * TB;
+  const int t = threadIdx.x;
+  const bool act = t < S, hact = t < H;
+  const int lx3 = act ? t % L3h : 0;
+  const int lx2 = act ? (t / L3h) % TB : 0;
+  const int lx1 = act ? t / (L3h * TB) : 0;
+  const int x1 = x1a + lx1, x2 = x2a + lx2;
+  const int s = (x1 * g.L2 + x2) * L3h + lx3;
+  const int p = A.parity_out, q = 1 - p;
+  const long long V3h = g.V3h, Vhp = g.Vhp;
+  const int lb = A.lb;
+  const int b_even = (p + x1 + x2) & 1;           // x3 bit of the site at even x0
+
+  // halo site loaded by this thread (t < H), faces in the order x1+, x1-, x2+, x2-
+  int hs = 0;
+  if (hact) {
+    int y1, y2, idx;
+    if (t < 2 * F1) {
+      idx = t < F1 ? t : t - F1;
+      y1 = t < F1 ? (x1a + TA == g.L1 ? 0 : x1a + TA) : (x1a == 0 ? g.L1 - 1 : x1a - 1);
+      y2 = x2a + idx / L3h;
+    } else {
+      const int u = t - 2 * F1;
+      idx = u < F2 ? u : u - F2;
+      y2 = u < F2 ? (x2a + TB == g.L2 ? 0 : x2a + TB) : (x2a == 0 ? g.L2 - 1 : x2a - 1);
+      y1 = x1a + idx / L3h;
+    }
+    hs = (y1 * g.L2 + y2) * L3h + idx % L3h;
+  }
+  // x1 / x2 neighbours (d: 0 x1+, 1 x1-, 2 x2+, 3 x2-): slice-local index offset (for the
+  // backward links) and LDS slot (tile or halo)
+  int dsn[4], kn[4];
+  {
+    const int y1f = x1 + 1 == g.L1 ? 0 : x1 + 1, y1b = x1 == 0 ? g.L1 - 1 : x1 - 1;
+    const int y2f = x2 + 1 == g.L2 ? 0 : x2 + 1, y2b = x2 == 0 ? g.L2 - 1 : x2 - 1;
+    const int st1 = g.L2 * L3h;
+    dsn[0] = (y1f - x1) * st1;
+    dsn[1] = (y1b - x1) * st1;
+    dsn[2] = (y2f - x2) * L3h;
+    dsn[3] = (y2b - x2) * L3h;
+    const int f1 = lx2 * L3h + lx3, f2 = lx1 * L3h + lx3;
+    kn[0] = (y1f - x1a >= 0 && y1f - x1a < TA) ? t + (y1f - x1) * L3h * TB : S + f1;
+    kn[1] = (y1b - x1a >= 0 && y1b - x1a < TA) ? t + (y1b - x1) * L3h * TB : S + F1 + f1;
+    kn[2] = (y2f - x2a >= 0 && y2f - x2a < TB) ? t + (y2f - x2) * L3h : S + 2 * F1 + f2;
+    kn[3] = (y2b - x2a >= 0 && y2b - x2a < TB) ? t + (y2b - x2) * L3h : S + 2 * F1 + F2 + f2;
+  }
+  // 16-byte word of site (x0, sl) in a 64-site tile row of W words per site: a slice base
+  // (uniform) plus a 32-bit site offset when the slices are whole tile rows (LIN)
+  auto word = [&](const f4v* base, int x0, int sl, int W) -> const f4v* {
+    if constexpr (LIN) return base + (long long)x0 * V3h * W + ((sl >> 6) * (64 * W) + (sl & 63));
+    else {
+      const long long j = (long long)x0 * V3h + sl;
+      return base + (j >> 6) * (64 * W) + (j & 63);
+    }
+  };
+  const f4v* inb = (const f4v*)(A.in.ptr + r0 * A.in.rs + q * A.in.ps);
+  // slice x (tile, and halo if asked) into LDS; lane i of a wave writes slot base + i
+  auto stage = [&](int x, bool halo) {
+    const int w64 = t & ~63;
+    if (act) {
+      const f4v* src = word(inb, x, s, 6);
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + u * TILE),
+                                         (__attribute__((address_space(3))) void*)(lds + u * SH + w64), 16, 0, 0);
+    }
+    if (halo && hact) {
+      const f4v* src = word(inb, x, hs, 6);
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + u * TILE),
+                                         (__attribute__((address_space(3))) void*)(lds + u * SH + S + w64), 16, 0,
+                                         0);
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads have landed
+    __syncthreads();
+  };
+  // spinor of LDS slot k (volatile: stays a ds_read); gamma5 on input applied here
+  auto get = [&](int k, cx<R> sp[4][3]) {
+    cx<R> v[12];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
+      const f4v w = *a;
+      v[2 * u] = {w.x, w.y};
+      v[2 * u + 1] = {w.z, w.w};
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sp[a][c] = (G5I && a >= 2) ? -v[a * 3 + c] : v[a * 3 + c];
+  };
+  auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
+  auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
+  // two stored rows of a link: U_mu at slice-local site sl of slice x, parity par (the
+  // FP32 copy: three pair words per link, 12 words per site)
+  auto link_raw = [&](int mu, int par, int x, int sl, cx<R> raw[6]) {
+    const f4v* u = word((const f4v*)A.U + par * 12 * Vhp, x, sl, 12) + 192 * mu;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const f4v v = u[64 * k];
+      raw[2 * k] = {v.x, v.y};
+      raw[2 * k + 1] = {v.z, v.w};
+    }
+  };
+
+  cx<R> acc[4][3], carry[2][3], nxt[6];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[a][c] = {R(0), R(0)};
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) carry[h][c] = {R(0), R(0)};
+
+  // prologue: the backward half-spinor of output x0a from slice x0a - 1, then slice x0a
+  if (hop_selected(A, x0a) && bwd_on(x0a)) {
+    const int xp = x0a == 0 ? g.L0 - 1 : x0a - 1;
+    if (act) link_raw(0, q, xp, s, nxt);
+    stage(xp, false);
+    if (act) {
+      cx<R> m[9], sp[4][3], h[2][3];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+      third_row<R>(m);
+      get(t, sp);
+      project<R>(0, true, sp, h);
+      su3_dag_mul<R>(m, h[0], carry[0]);
+      su3_dag_mul<R>(m, h[1], carry[1]);
+      if (x0a == 0)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) carry[k][c] = -carry[k][c];
+    }
+    __syncthreads();
+  }
+  stage(x0a, hop_selected(A, x0a));
+
+  for (int x0 = x0a; x0 <= x0b; ++x0) {
+    // LDS: slice x0 (x0 == x0b: tile only, wrapped); acc: output x0 - 1 without its forward
+    // time hop; carry: backward half-spinor of output x0
+    const int xo = x0 - 1;                        // output finished in this step
+    const bool last = x0 == x0b;
+    const bool sel = !last && hop_selected(A, x0);
+    const bool fin = x0 > x0a;
+    const bool use_f = fin && hop_selected(A, xo) && fwd_on(xo);
+    const bool carry_next = !last && x0 + 1 < x0b && hop_selected(A, x0 + 1) && bwd_on(x0 + 1);
+    if (act) {
+      if (fin) {
+        if (use_f) {
+          cx<R> m[9], sp[4][3], h[2][3], uh[2][3];
+#pragma unroll
+          for (int e = 0; e < 6; ++e) m[e] = nxt[e];   // loaded with this slice
+          third_row<R>(m);
+          get(t, sp);
+          project<R>(0, false, sp, h);
+          su3_mul<R>(m, h[0], uh[0]);
+          su3_mul<R>(m, h[1], uh[1]);
+          if (xo == g.L0 - 1)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+          accum_recon<R>(0, false, uh, acc);
+        }
+        V2* o = A.out.ptr + r0 * A.out.rs + p * A.out.ps;
+        const V2* xv = A.x.ptr ? A.x.ptr + r0 * A.x.rs + p * A.x.ps : nullptr;
+        store_out<R, true>(o, xv, (long long)xo * V3h + s, hop_selected(A, xo), G5O, A.a, A.b, acc);
+      }
+      if (!last) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[a][c] = {R(0), R(0)};
+        if (sel && bwd_on(x0)) accum_recon<R>(0, true, carry, acc);
+        if (sel) {
+          const int b = b_even ^ (x0 & 1);
+          const int h3f = b ? (lx3 + 1 == L3h ? 0 : lx3 + 1) : lx3;
+          const int h3b = b ? lx3 : (lx3 == 0 ? L3h - 1 : lx3 - 1);
+          // spatial hop i = 2 (mu - 1) + dir; the link of hop i + 1 is loaded before the
+          // arithmetic of hop i
+          auto hop_link = [&](int i, cx<R> raw[6]) {
+            const int mu = 1 + i / 2;
+            if (i & 1) link_raw(mu, q, x0, i >= 4 ? s - lx3 + h3b : s + dsn[i], raw);
+            else link_raw(mu, p, x0, s, raw);
+          };
+          hop_link(0, nxt);
+#pragma unroll
+          for (int i = 0; i < 6; ++i) {
+            const int mu = 1 + i / 2, dir = i & 1;
+            const int k = i >= 4 ? t - lx3 + (i == 4 ? h3f : h3b) : kn[i];
+            cx<R> m[9], sp[4][3], h[2][3], uh[2][3];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+            if (i < 5) hop_link(i + 1, nxt);
+            else if (carry_next) link_raw(0, q, x0, s, nxt);
+            get(k, sp);
+            third_row<R>(m);
+            project<R>(mu, dir == 1, sp, h);
+            if (dir == 0) {
+              su3_mul<R>(m, h[0], uh[0]);
+              su3_mul<R>(m, h[1], uh[1]);
+            } else {
+              su3_dag_mul<R>(m, h[0], uh[0]);
+              su3_dag_mul<R>(m, h[1], uh[1]);
+            }
+            accum_recon<R>(mu, dir == 1, uh, acc);
+            // the accumulator is next read in the following step: without this pin the
+            // compiler sinks the arithmetic of all six hops below their loads and spills
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(acc[a][c].r), "+v"(acc[a][c].i));
+          }
+        }
+        // backward half-spinor of output x0 + 1 from slice x0
+        if (carry_next) {
+          cx<R> m[9], sp[4][3], h[2][3];
+          if (sel) {
+#pragma unroll
+            for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+          } else {
+            link_raw(0, q, x0, s, m);
+          }
+          third_row<R>(m);
+          get(t, sp);
+          project<R>(0, true, sp, h);
+          su3_dag_mul<R>(m, h[0], carry[0]);
+          su3_dag_mul<R>(m, h[1], carry[1]);
+        }
+      }
+    }
+    if (!last) {
+      // replace slice x0 by slice x0 + 1 (tile only for the last one, which serves the
+      // forward hop of output x0b - 1)
+      const int xn = x0 + 1 == g.L0 ? 0 : x0 + 1;
+      const bool f_next = hop_selected(A, x0) && fwd_on(x0);   // forward hop of output x0
+      __syncthreads();
+      if (x0 + 1 < x0b || f_next) {
+        if (act && f_next) link_raw(0, p, x0, s, nxt);
+        stage(xn, x0 + 1 < x0b && hop_selected(A, x0 + 1));
+      }
+    }
+  }
+}
+
 static inline long long round8(long long n) { return (n + 7) / 8 * 8; }
 
 template <class R, int NR, bool SWEEP> static void launch_reg(const HopArgs<R>& A, hipStream_t st) {
@@ -1269,6 +1554,56 @@ template <class R, int NR> static void launch_slab(const HopArgs<R>& A, hipStrea
 #undef SAP_SLAB
 }
 
+// Tile of the LDS-staged slab kernel: TA x TB x L3h sites whose slice and x1 / x2 halo fit
+// the kSlabdUnit LDS slots, with the fewest halo sites per tile site, then the largest tile.
+static void slabd_tile(const Geo& g, int& TA, int& TB, int& S, int& H) {
+  TA = TB = 1;
+  double best = 1e30;
+  for (int a = 1; a <= g.L1; ++a) {
+    if (g.L1 % a) continue;
+    for (int b = 1; b <= g.L2; ++b) {
+      if (g.L2 % b) continue;
+      const int s = a * b * g.L3h;
+      const int h = 2 * ((a < g.L1 ? b * g.L3h : 0) + (b < g.L2 ? a * g.L3h : 0));
+      if (s + h > kSlabdUnit || s > 512 || h > 512) continue;
+      const double ratio = (double)h / s;
+      if (ratio < best - 1e-12 || (ratio < best + 1e-12 && a * b > TA * TB)) {
+        best = ratio;
+        TA = a;
+        TB = b;
+      }
+    }
+  }
+  S = TA * TB * g.L3h;
+  H = 2 * ((TA < g.L1 ? TB * g.L3h : 0) + (TB < g.L2 ? TA * g.L3h : 0));
+}
+
+// FP32 only; FP64 runs the slab kernel of the same tile budget
+template <class R> static void launch_slabd(const HopArgs<R>& A, hipStream_t st) {
+  if constexpr (!std::is_same<R, float>::value) {
+    launch_slab<R, 1>(A, st, 40 * 1024);
+  } else {
+    int TA, TB, S, H;
+    slabd_tile(A.g, TA, TB, S, H);
+    const int ntile = (A.g.L1 / TA) * (A.g.L2 / TB);
+    const dim3 grid((unsigned)(8LL * ntile * A.nrhs)), blk((std::max(S, H) + 63) / 64 * 64);
+    const size_t lds = (size_t)kSlabdUnit * 96;
+    const bool lin = A.g.V3h % TILE == 0;
+#define SAP_SLABD(LIN, G5I, G5O) hipLaunchKernelGGL((hop_slabd_kernel<LIN, G5I, G5O>), grid, blk, lds, st, A, TA, TB)
+#define SAP_SLABD_G5(LIN)                                     \
+  do {                                                        \
+    if (A.g5_in && A.g5_out) SAP_SLABD(LIN, true, true);      \
+    else if (A.g5_in) SAP_SLABD(LIN, true, false);            \
+    else if (A.g5_out) SAP_SLABD(LIN, false, true);           \
+    else SAP_SLABD(LIN, false, false);                        \
+  } while (0)
+    if (lin) SAP_SLABD_G5(true);
+    else SAP_SLABD_G5(false);
+#undef SAP_SLABD_G5
+#undef SAP_SLABD
+  }
+}
+
 template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {
   typedef typename vec2<R>::type V2;
   constexpr int S = sizeof(R) == 8 ? 128 : 256;     // 48 KB of LDS either way
@@ -1313,6 +1648,10 @@ template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t st) {
     case HOP_MAP_SLAB2:
       if (full) launch_march<R, 2>(A, st);
       else launch_slab<R, 2>(A, st, 80 * 1024);
+      return;
+    case HOP_MAP_SLABD:
+      if (full) launch_march<R, 1>(A, st);
+      else launch_slabd<R>(A, st);
       return;
     default: break;
   }

@@ -170,7 +170,8 @@ template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t st) {
     case HOP_MAP_WALK1:
     case HOP_MAP_BAND1:
     case HOP_MAP_SLAB1:
-    case HOP_MAP_SLAB1W: launch_march16<1>(A, st); return;
+    case HOP_MAP_SLAB1W:
+    case HOP_MAP_SLABD: launch_march16<1>(A, st); return;
     case HOP_MAP_MARCH2:
     case HOP_MAP_WALK2:
     case HOP_MAP_SLAB2: launch_march16<2>(A, st); return;

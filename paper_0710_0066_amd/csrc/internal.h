@@ -86,8 +86,11 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
                             //   hops carried in registers, 1 rhs per work-item
        HOP_MAP_SLAB1 = 17,  // even-odd hop only: band order, a workgroup owns a spatial tile
        HOP_MAP_SLAB1W = 18, //   of the slice staged in LDS and walks the band; 1 rhs per
-       HOP_MAP_SLAB2 = 19,  //   work-item (SLAB1W: tiles up to twice as large), or 2
-       HOP_NMAP = 20 };
+       HOP_MAP_SLAB2 = 19,  //   work-item (SLAB1W: tiles up to twice as large), or 2 (SLAB2)
+       HOP_MAP_SLABD = 20,  // even-odd FP32 hop only: the slab order with the slice and its
+                            //   x1 / x2 halo staged in LDS by direct memory-to-LDS loads,
+                            //   1 rhs per work-item (FP64: as SLAB1, FP16: as MARCH1)
+       HOP_NMAP = 21 };
 constexpr int HOP_WALK_T = 8;   // slices per walk
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);

@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version():
     import paper_0710_0066_amd as sap
-    assert sap.sap_version() == 101
+    assert sap.sap_version() == 102
 
 
 @pytest.mark.parametrize("L,l0,l0_sub,kappa,max_rhs,ok", [

@@ -94,7 +94,7 @@ def test_apply_Dslash_eo_matches_oracle(gu, L, l0, l0_sub, k, nrhs):
             assert gu.rel_err(got * m_out, ref) <= tol, (parity, prec)
 
 
-@pytest.mark.parametrize("hop_map", list(range(20)))
+@pytest.mark.parametrize("hop_map", list(range(21)))
 @pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15),
                                           ((16, 10, 10, 12), 4, 2, 0.14)])
 def test_every_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
