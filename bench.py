@@ -34,6 +34,7 @@ FLOP_PER_SITE = 1320      # hop of eq. 2 per output site and rhs (secondary figu
 # hop mappings of the timed 12-rhs even-odd launches (one kernel per line, profile and
 # counter set); the full-size parity test sets the same ones
 HEADLINE_MAPS = {"f32": "slabd", "f64": "slab1w", "f16": "march2"}
+ROTATE = 3                # contexts the single-rhs operators rotate over
 
 
 def hop_map_id(sap, name):
@@ -79,6 +80,8 @@ def parse():
                     help="run only this batched block solve of both levels once (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--only-force", action="store_true",
+                    help="run only the force-kernel timings (for profiler runs)")
     return ap.parse_args()
 
 
@@ -320,6 +323,53 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=5):
                 fb1["seconds"] / methods["bicgstab"]["seconds"] if "seconds" in methods["bicgstab"] else None}
 
 
+def force_kernels(sap, torch, ctx, V, reps):
+    """Time per call of the molecular-dynamics kernels on the 24^3x48 links (the context's
+    own): the gauge force (k_gauge_force: F += c Im tr(lambda^a U A) from the staples) and
+    the link update (k_update_links: U <- exp(dt P) U by its Taylor series, reunitarised),
+    timed as a step forward and back. Algorithmic bytes per call: links read (and written)
+    once as 18 FP64 reals, forces and momenta as 8 FP64 reals per link. The context's
+    links change by rounding; the caller sets them again."""
+    import numpy as np
+    F = ctx.new_momenta()
+    P = ctx.new_momenta()
+    g = torch.Generator(device="cpu").manual_seed(7)
+    P.copy_(0.01 * torch.randn(P.numel(), generator=g, dtype=torch.float64))
+    links = 4 * V
+    res = {}
+    for name, fn, nbytes in [
+            ("gauge_force", lambda: sap.gauge_force(ctx, F, 1.0, 5.6), links * (18 + 8 + 8) * 8),
+            ("update_links", lambda: (sap.sap_update_links(ctx, P, 1e-3), sap.sap_update_links(ctx, P, -1e-3)),
+             2 * links * (18 + 8 + 18) * 8)]:
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res[name] = {"ms_per_call": round(dt * 1e3, 3), "algorithmic_bytes": nbytes,
+                     "GB/s": round(nbytes / dt / 1e9, 1)}
+        print(f"[bench] {name}: {dt * 1e3:.3f} ms per call", file=sys.stderr, flush=True)
+    # pseudo-fermion force of the block action (FP64 block solve + k_pair_force); the kernel's
+    # own time is in the rocprofv3 trace of --only-force
+    phi = ctx.new_field(1)
+    phi.copy_(torch.randn(phi.numel(), generator=g, dtype=torch.float64))
+    opts = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F32, inner_tol=1e-5)
+    sap.block_pf_force(ctx, F, 1.0, phi, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = max(2, reps // 5)
+    for _ in range(n):
+        sap.block_pf_force(ctx, F, 1.0, phi, opts)
+    torch.cuda.synchronize()
+    res["block_pf_force_call"] = {"ms_per_call": round((time.perf_counter() - t0) / n * 1e3, 2),
+                                  "pair_force_algorithmic_bytes": V * 1472,
+                                  "note": "includes the block solves; k_pair_force alone is in the profile"}
+    del F, P, phi
+    return res
+
+
 def time_op(sap, torch, fn, steps, warmup):
     """Average time (ms) per launch of fn(k) over `steps` launches after `warmup`."""
     for k in range(warmup):
@@ -367,25 +417,48 @@ def main():
     ctx.set_gauge(Ud)      # pack into the tiled layout and make the FP32 / FP16 link copies
     torch.cuda.synchronize()
     gauge_upload_s = time.perf_counter() - t0
-    del Ud
     PREC = {"f64": sap.SAP_F64, "f32": sap.SAP_F32, "f16": sap.SAP_F16}
+    # single-rhs operators rotate over ROTATE contexts, each with its own links and fields,
+    # so that a launch finds little of its ~0.2-0.4 GB working set in the 256 MB MALL
+    rot = [ctx]
+    tuned1 = {}               # ctx's single-rhs mappings, used by every rotation context
+
+    def rotation():
+        if not tuned1:
+            tuned1.update(sap.sap_tune(ctx, 1))
+        while len(rot) < ROTATE:
+            c = sap.Context(L, l0, k, l0_sub=l0s, max_rhs=1)
+            c.set_gauge(Ud)
+            for key, us in tuned1.items():
+                kind, prec = key.split("_")
+                sap.sap_set_hop_map(c, int(kind == "full"), PREC[prec], 1, hop_map_id(sap, min(us, key=us.get)))
+            rot.append(c)
+        return rot
     fields = {}
 
-    def field(prec, n):
-        key = (prec, n)
+    def field(c, prec, n):
+        key = (id(c), prec, n)
         if key not in fields:
-            fin = ctx.new_field(n, PREC[prec])
-            ctx.pack_spinor(fin, torch.from_numpy(np.ascontiguousarray(psi[:n])).cuda(), n, PREC[prec])
-            fields[key] = (fin, ctx.new_field(n, PREC[prec]))
+            fin = c.new_field(n, PREC[prec])
+            c.pack_spinor(fin, torch.from_numpy(np.ascontiguousarray(psi[:n])).cuda(), n, PREC[prec])
+            fields[key] = (fin, c.new_field(n, PREC[prec]))
         return fields[key]
 
     def eo(prec, n):
-        fin, fout = field(prec, n)
-        return lambda s: sap.apply_Dslash_eo(ctx, fout, fin, n, s & 1, PREC[prec])
+        if n == nrhs:
+            fin, fout = field(ctx, prec, n)
+            return lambda s: sap.apply_Dslash_eo(ctx, fout, fin, n, s & 1, PREC[prec])
+        ops = [(c,) + field(c, prec, n) for c in rotation()]
+        return lambda s: sap.apply_Dslash_eo(ops[s % ROTATE][0], ops[s % ROTATE][2], ops[s % ROTATE][1], n,
+                                             (s // ROTATE) & 1, PREC[prec])
 
     def full(prec):
-        fin, fout = field(prec, 1)
-        return lambda s: sap.apply_M(ctx, fout, fin, 1, PREC[prec])
+        ops = [(c,) + field(c, prec, 1) for c in rotation()]
+        return lambda s: sap.apply_M(ops[s % ROTATE][0], ops[s % ROTATE][2], ops[s % ROTATE][1], 1, PREC[prec])
+
+    if args.only_force:
+        force_kernels(sap, torch, ctx, V, args.steps)
+        return
 
     if args.only_solve:        # one batched block solve of both levels, for profiler runs
         meth, p = args.only_solve.split("_")
@@ -411,14 +484,20 @@ def main():
         n_op = args.nrhs if args.op == "eo" else 1
         maps = [m for m in args.hop_map.split(",") if m]
         if not maps:
-            sap.sap_tune(ctx, n_op)
             if args.op == "eo" and args.nrhs == nrhs and args.prec in HEADLINE_MAPS:
                 maps = [HEADLINE_MAPS[args.prec]]
+            else:     # the tuner's choice, set on every context the launches rotate over
+                res = sap.sap_tune(ctx, n_op)
+                us = res[("eo" if args.op == "eo" else "full") + "_" + args.prec]
+                maps = [min(us, key=us.get)]
+                if n_op == 1:
+                    tuned1.update(res)
         fn = eo(args.prec, args.nrhs) if args.op == "eo" else full(args.prec)
         for m in maps or [None]:     # the given mappings only (no tuner launches in the profile)
             if m is not None:
                 mid = int(m) if m.isdigit() else hop_map_id(sap, m)
-                sap.sap_set_hop_map(ctx, int(args.op == "M"), PREC[args.prec], n_op, mid)
+                for c in (rot if n_op == 1 else [ctx]):
+                    sap.sap_set_hop_map(c, int(args.op == "M"), PREC[args.prec], n_op, mid)
             ms = time_op(sap, torch, fn, args.steps, args.warmup)
             print(f"[bench] {args.op} {args.prec} nrhs={args.nrhs if args.op == 'eo' else 1} map {m}: "
                   f"{ms * 1e3:.1f} us/launch", file=sys.stderr, flush=True)
@@ -428,6 +507,7 @@ def main():
 
     print("[bench] tuning the hop mapping", file=sys.stderr, flush=True)
     tuning = {"nrhs_%d" % n: sap.sap_tune(ctx, n) for n in (1, nrhs)}
+    tuned1.update(tuning["nrhs_1"])
     # the 12-rhs launches use fixed mappings (HEADLINE_MAPS, the tuner's choices on this
     # workload, whose runner-up mappings are within a few percent), so that the line, its
     # profile and its counters describe one kernel
@@ -464,9 +544,16 @@ def main():
                         "roofline": roofline(g, name)}
         print(f"[bench] {name}: {t * 1e3:.1f} us, {g:.0f} GB/s", file=sys.stderr, flush=True)
     result["other_operators"] = others
+    result["single_rhs_rotation"] = (f"single-rhs operators rotate over {ROTATE} contexts (own links and fields), "
+                                     "so consecutive launches do not reuse each other's data from the MALL")
+    result["force_kernels"] = force_kernels(sap, torch, ctx, V, max(10, args.steps // 10))
+    ctx.set_gauge(Ud)
     result["hop_tuning_us"] = {n: {k: {m: round(v, 1) for m, v in d.items()} for k, d in t.items()}
                                for n, t in tuning.items()}
     fields.clear()
+    del Ud
+    for c in rot[1:]:
+        c.close()
     result["hbm_probe"] = hbm_probe(sap, torch)
     if not args.skip_solve:
         result["block_solve"] = block_solve_comparison(sap, torch, ctx, cfg, L)
