@@ -39,10 +39,12 @@ inline SysGrid make_sysgrid(long long Vh, int V3h, int lb, int L0, int colour) {
 }
 
 template <class R> void blas_norm2(const SysGrid& G, int nrhs, Field<R> a, int npar, double* part, hipStream_t s);
-template <class R> void blas_cg_xs(const SysGrid& G, int nrhs, Field<R> x, Field<R> p, Field<R> sf, Field<R> q,
-                                   const double* alpha, double* part, hipStream_t s);
-template <class R> void blas_xpay(const SysGrid& G, int nrhs, Field<R> p, Field<R> r, const double* beta,
-                                  hipStream_t s);
+// s -= alpha q with partial ||s||^2 per system
+template <class R> void blas_cg_s(const SysGrid& G, int nrhs, Field<R> sf, Field<R> q, const double* alpha,
+                                  double* part, hipStream_t s);
+// x += alpha p, then p = r + beta p
+template <class R> void blas_cg_xp(const SysGrid& G, int nrhs, Field<R> x, Field<R> p, Field<R> r,
+                                   const double* alpha, const double* beta, hipStream_t s);
 template <class Ro, class Ri> void blas_convert(const SysGrid& G, int nrhs, Field<Ro> out, Field<Ri> in,
                                                 int npar, hipStream_t s);
 template <class R> void blas_add_mixed(const SysGrid& G, int nrhs, Field<double> x, Field<R> e, hipStream_t s);
@@ -53,7 +55,8 @@ void fin_sum(int nsys, int nchunk, const double* part, double* out, hipStream_t 
 void fin_init(const SysScal& S, int nsys, int nchunk, const double* pb, const double* pr, const int* sel,
               const double* target2, hipStream_t s);
 void fin_alpha(const SysScal& S, int nsys, int nchunk, const double* pq, hipStream_t s);
-void fin_beta(const SysScal& S, int nsys, int nchunk, const double* ps_, const double* pr,
+// ps_ holds nchunk partials per system, pr nchunk_r
+void fin_beta(const SysScal& S, int nsys, int nchunk, const double* ps_, int nchunk_r, const double* pr,
               const double* target2, hipStream_t s);
 
 // ---- BiCGstab on the even-odd system: complex per-system scalars in cs[8 * sys] =

@@ -68,29 +68,26 @@ __global__ __launch_bounds__(256) void k_norm2(SysGrid G, Field<R> a, int npar, 
   if (threadIdx.x == 0) part[t.sys * G.nchunk + blockIdx.x] = s;
 }
 
-// x += alpha p ; s -= alpha q ; partial ||s||^2
+// s -= alpha q ; partial ||s||^2
 template <class R>
-__global__ __launch_bounds__(256) void k_cg_xs(SysGrid G, Field<R> x, Field<R> p, Field<R> s,
-                                               Field<R> q, const double* alpha, double* part) {
+__global__ __launch_bounds__(256) void k_cg_s(SysGrid G, Field<R> s, Field<R> q, const double* alpha,
+                                              double* part) {
   typedef arith_t<R> A;
   const Tile t = tile_of(G);
   double acc = 0.0;
   if (t.selected) {
     const A al = (A)alpha[t.sys];
     for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
-      const SiteR<R> xr = site_r(x, t.rhs, 0, j, G.Vhp), pr = site_r(p, t.rhs, 0, j, G.Vhp);
       const SiteR<R> sr = site_r(s, t.rhs, 0, j, G.Vhp), qr = site_r(q, t.rhs, 0, j, G.Vhp);
-      SiteW<R> xw = site_w(x, t.rhs, 0, j, G.Vhp), sw = site_w(s, t.rhs, 0, j, G.Vhp);
+      SiteW<R> sw = site_w(s, t.rhs, 0, j, G.Vhp);
 #pragma unroll
       for (int c = 0; c < 12; ++c) {
-        cx<A> xv = get(xr, c), pv = get(pr, c), sv = get(sr, c), qv = get(qr, c);
-        xv.r += al * pv.r; xv.i += al * pv.i;
+        cx<A> sv = get(sr, c);
+        const cx<A> qv = get(qr, c);
         sv.r -= al * qv.r; sv.i -= al * qv.i;
-        put(xw, c, xv);
         put(sw, c, sv);
         acc += (double)sv.r * sv.r + (double)sv.i * sv.i;
       }
-      close(xw);
       close(sw);
     }
   }
@@ -98,24 +95,30 @@ __global__ __launch_bounds__(256) void k_cg_xs(SysGrid G, Field<R> x, Field<R> p
   if (threadIdx.x == 0) part[t.sys * G.nchunk + blockIdx.x] = sm;
 }
 
-// p = r + beta p
+// x += alpha p ; p = r + beta p  (the solution update of an iteration, deferred to the
+// direction update so that p is read once)
 template <class R>
-__global__ __launch_bounds__(256) void k_xpay(SysGrid G, Field<R> p, Field<R> r, const double* beta) {
+__global__ __launch_bounds__(256) void k_cg_xp(SysGrid G, Field<R> x, Field<R> p, Field<R> r, const double* alpha,
+                                               const double* beta) {
   typedef arith_t<R> A;
   const Tile t = tile_of(G);
   if (!t.selected) return;
-  const A be = (A)beta[t.sys];
+  const A al = (A)alpha[t.sys], be = (A)beta[t.sys];
   for (long long j = t.j0 + threadIdx.x; j < t.j1; j += 256) {
-    const SiteR<R> pr = site_r(p, t.rhs, 0, j, G.Vhp), rr = site_r(r, t.rhs, 0, j, G.Vhp);
-    SiteW<R> pw = site_w(p, t.rhs, 0, j, G.Vhp);
+    const SiteR<R> xr = site_r(x, t.rhs, 0, j, G.Vhp), pr = site_r(p, t.rhs, 0, j, G.Vhp);
+    const SiteR<R> rr = site_r(r, t.rhs, 0, j, G.Vhp);
+    SiteW<R> xw = site_w(x, t.rhs, 0, j, G.Vhp), pw = site_w(p, t.rhs, 0, j, G.Vhp);
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-      cx<A> pv = get(pr, c);
+      cx<A> xv = get(xr, c), pv = get(pr, c);
       const cx<A> rv = get(rr, c);
+      xv.r += al * pv.r; xv.i += al * pv.i;
       pv.r = rv.r + be * pv.r;
       pv.i = rv.i + be * pv.i;
+      put(xw, c, xv);
       put(pw, c, pv);
     }
+    close(xw);
     close(pw);
   }
 }
@@ -227,14 +230,14 @@ __global__ void k_fin_alpha(SysScal S, int nsys, int nchunk, const double* part_
   }
 }
 
-__global__ void k_fin_beta(SysScal S, int nsys, int nchunk, const double* part_s, const double* part_r,
-                           const double* target2) {
+__global__ void k_fin_beta(SysScal S, int nsys, int nchunk, const double* part_s, int nchunk_r,
+                           const double* part_r, const double* target2) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
   for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
     const double ss = sys_total(part_s, s, nchunk);
-    const double gm = sys_total(part_r, s, nchunk);
+    const double gm = sys_total(part_r, s, nchunk_r);
     if (!(isfinite(ss) && isfinite(gm))) S.flags[0] = 3;
     int act = S.active[s];
     if (act) {
@@ -584,13 +587,13 @@ static inline dim3 grid_of(const SysGrid& G, int nrhs) { return dim3(G.nchunk, G
 template <class R> void blas_norm2(const SysGrid& G, int nrhs, Field<R> a, int npar, double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_norm2<R>, grid_of(G, nrhs), dim3(256), 0, s, G, a, npar, part);
 }
-template <class R> void blas_cg_xs(const SysGrid& G, int nrhs, Field<R> x, Field<R> p, Field<R> sf,
-                                   Field<R> q, const double* alpha, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_xs<R>, grid_of(G, nrhs), dim3(256), 0, s, G, x, p, sf, q, alpha, part);
+template <class R> void blas_cg_s(const SysGrid& G, int nrhs, Field<R> sf, Field<R> q, const double* alpha,
+                                  double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_s<R>, grid_of(G, nrhs), dim3(256), 0, s, G, sf, q, alpha, part);
 }
-template <class R> void blas_xpay(const SysGrid& G, int nrhs, Field<R> p, Field<R> r, const double* beta,
-                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_xpay<R>, grid_of(G, nrhs), dim3(256), 0, s, G, p, r, beta);
+template <class R> void blas_cg_xp(const SysGrid& G, int nrhs, Field<R> x, Field<R> p, Field<R> r,
+                                   const double* alpha, const double* beta, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xp<R>, grid_of(G, nrhs), dim3(256), 0, s, G, x, p, r, alpha, beta);
 }
 template <class Ro, class Ri> void blas_convert(const SysGrid& G, int nrhs, Field<Ro> out, Field<Ri> in,
                                                 int npar, hipStream_t s) {
@@ -613,9 +616,9 @@ void fin_init(const SysScal& S, int nsys, int nchunk, const double* pb, const do
 void fin_alpha(const SysScal& S, int nsys, int nchunk, const double* pq, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(256), 0, s, S, nsys, nchunk, pq);
 }
-void fin_beta(const SysScal& S, int nsys, int nchunk, const double* ps_, const double* pr,
+void fin_beta(const SysScal& S, int nsys, int nchunk, const double* ps_, int nchunk_r, const double* pr,
               const double* target2, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, s, S, nsys, nchunk, ps_, pr, target2);
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(256), 0, s, S, nsys, nchunk, ps_, nchunk_r, pr, target2);
 }
 
 template <class R> void blas_cdot3(const SysGrid& G, int nrhs, Field<R> a, Field<R> b, Field<R> c, double* part,
@@ -663,9 +666,9 @@ void fin_geom(const SysScal& S, int nsys, int nchunk, const double* part, const 
 
 #define INST(R)                                                                                         \
   template void blas_norm2<R>(const SysGrid&, int, Field<R>, int, double*, hipStream_t);                 \
-  template void blas_cg_xs<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, Field<R>, const double*, \
-                              double*, hipStream_t);                                                     \
-  template void blas_xpay<R>(const SysGrid&, int, Field<R>, Field<R>, const double*, hipStream_t);       \
+  template void blas_cg_s<R>(const SysGrid&, int, Field<R>, Field<R>, const double*, double*, hipStream_t); \
+  template void blas_cg_xp<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, const double*,           \
+                              const double*, hipStream_t);                                               \
   template void blas_add_mixed<R>(const SysGrid&, int, Field<double>, Field<R>, hipStream_t);           \
   template void blas_cdot3<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, double*, hipStream_t);  \
   template void blas_bicg_p<R>(const SysGrid&, int, Field<R>, Field<R>, Field<R>, const double*, hipStream_t); \

@@ -29,7 +29,8 @@ __device__ __forceinline__ void load_spinor(const typename vec2<R>::type* p, lon
 // site is not selected; xb: the same block of x, or null (NT: non-temporal stores)
 template <class R, bool NT>
 __device__ __forceinline__ void store_out(typename vec2<R>::type* ob, const typename vec2<R>::type* xb, long long j,
-                                          bool sel, bool g5o, R a, R b, const cx<R> acc[4][3]) {
+                                          bool sel, bool g5o, R a, R b, const cx<R> acc[4][3],
+                                          double* n2 = nullptr) {
   cx<R> v[12], xv[12];
   if (sel && xb) ld_site<R>(xb, j, xv);
 #pragma unroll
@@ -45,6 +46,7 @@ __device__ __forceinline__ void store_out(typename vec2<R>::type* ob, const type
         r.i += a * xv[k].i;
       }
       v[k] = sel ? r : cx<R>{R(0), R(0)};
+      if (n2) *n2 += (double)v[k].r * v[k].r + (double)v[k].i * v[k].i;
     }
   st_site<R, NT>(ob, j, v);
 }
@@ -1182,6 +1184,13 @@ void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
   }
 }
 
+// x0 band (XCD share, bands [L0 k / 8, L0 (k + 1) / 8)) holding slice x
+__device__ __host__ __forceinline__ int slice_band(int L0, int x) {
+  int k = 0;
+  while (k < 7 && L0 * (k + 1) / 8 <= x) ++k;
+  return k;
+}
+
 // Slab hop with direct memory-to-LDS staging (FP32, one rhs per workgroup). The band and
 // tile are those of the slab kernel, but the LDS holds one input slice of the tile together
 // with its x1 / x2 halo, written by global_load_lds (16 bytes per lane, no registers) after
@@ -1197,7 +1206,7 @@ void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
 // S + H <= kSlabdUnit; the fixed unit stride keeps the unit offsets immediate.
 constexpr int kSlabdUnit = 416;
 
-template <bool LIN, bool G5I, bool G5O>
+template <bool LIN, bool G5I, bool G5O, bool NRM>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
 void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
   typedef float R;
@@ -1325,6 +1334,36 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
     }
   };
 
+  // fused ||out||^2 (A.npart): per-thread sum over the outputs of the current block of
+  // A.nlb slices, reduced over the workgroup when the block ends; the partial of (system,
+  // tile, band) goes to slot tile + ntile * (band - first band of the block), and the
+  // workgroup of the first band zeroes the slots no band fills
+  double nacc = 0.0;
+  __shared__ double nsh[8];
+  auto flush = [&](int blk) {
+    double v = nacc;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((t & 63) == 0) nsh[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += nsh[w];
+      const int xa = blk * A.nlb, xb = min(xa + A.nlb, g.L0) - 1;
+      const int first = slice_band(g.L0, xa), last = slice_band(g.L0, xb);
+      double* dst = A.npart + ((long long)r0 * (g.L0 / A.nlb) + blk) * A.nslot;
+      dst[tile + ntile * (xcd - first)] = sum;
+      if (xcd == first)
+        for (int pc = 1; pc < A.nslot / ntile; ++pc) {
+          const int k = first + pc;
+          if (k > last || g.L0 * k / 8 == g.L0 * (k + 1) / 8) dst[tile + ntile * pc] = 0.0;
+        }
+    }
+    __syncthreads();
+    nacc = 0.0;
+  };
+  constexpr bool nrm = NRM;
+
   cx<R> acc[4][3], carry[2][3], nxt[6];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -1368,6 +1407,7 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
     const bool fin = x0 > x0a;
     const bool use_f = fin && hop_selected(A, xo) && fwd_on(xo);
     const bool carry_next = !last && x0 + 1 < x0b && hop_selected(A, x0 + 1) && bwd_on(x0 + 1);
+    if (nrm && fin && xo > x0a && xo / A.nlb != (xo - 1) / A.nlb) flush((xo - 1) / A.nlb);
     if (act) {
       if (fin) {
         if (use_f) {
@@ -1388,7 +1428,8 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
         }
         V2* o = A.out.ptr + r0 * A.out.rs + p * A.out.ps;
         const V2* xv = A.x.ptr ? A.x.ptr + r0 * A.x.rs + p * A.x.ps : nullptr;
-        store_out<R, true>(o, xv, (long long)xo * V3h + s, hop_selected(A, xo), G5O, A.a, A.b, acc);
+        store_out<R, true>(o, xv, (long long)xo * V3h + s, hop_selected(A, xo), G5O, A.a, A.b, acc,
+                           nrm ? &nacc : nullptr);
       }
       if (!last) {
 #pragma unroll
@@ -1465,6 +1506,7 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
       }
     }
   }
+  if (nrm) flush((x0b - 1) / A.nlb);
 }
 
 static inline long long round8(long long n) { return (n + 7) / 8 * 8; }
@@ -1589,19 +1631,34 @@ template <class R> static void launch_slabd(const HopArgs<R>& A, hipStream_t st)
     const dim3 grid((unsigned)(8LL * ntile * A.nrhs)), blk((std::max(S, H) + 63) / 64 * 64);
     const size_t lds = (size_t)kSlabdUnit * 96;
     const bool lin = A.g.V3h % TILE == 0;
-#define SAP_SLABD(LIN, G5I, G5O) hipLaunchKernelGGL((hop_slabd_kernel<LIN, G5I, G5O>), grid, blk, lds, st, A, TA, TB)
-#define SAP_SLABD_G5(LIN)                                     \
-  do {                                                        \
-    if (A.g5_in && A.g5_out) SAP_SLABD(LIN, true, true);      \
-    else if (A.g5_in) SAP_SLABD(LIN, true, false);            \
-    else if (A.g5_out) SAP_SLABD(LIN, false, true);           \
-    else SAP_SLABD(LIN, false, false);                        \
+#define SAP_SLABD(LIN, G5I, G5O, NRM) \
+  hipLaunchKernelGGL((hop_slabd_kernel<LIN, G5I, G5O, NRM>), grid, blk, lds, st, A, TA, TB)
+    // the fused norm exists without gamma_5 on the input (the solvers' second half hops;
+    // they set npart only there)
+#define SAP_SLABD_G5(LIN)                                                     \
+  do {                                                                        \
+    if (A.npart && !A.g5_in && A.g5_out) SAP_SLABD(LIN, false, true, true);   \
+    else if (A.npart && !A.g5_in) SAP_SLABD(LIN, false, false, true);         \
+    else if (A.g5_in && A.g5_out) SAP_SLABD(LIN, true, true, false);          \
+    else if (A.g5_in) SAP_SLABD(LIN, true, false, false);                     \
+    else if (A.g5_out) SAP_SLABD(LIN, false, true, false);                    \
+    else SAP_SLABD(LIN, false, false, false);                                 \
   } while (0)
     if (lin) SAP_SLABD_G5(true);
     else SAP_SLABD_G5(false);
 #undef SAP_SLABD_G5
 #undef SAP_SLABD
   }
+}
+
+int slabd_norm_slots(const Geo& g, int nlb) {
+  if (nlb <= 0 || g.L0 % nlb) return 0;
+  int TA, TB, S, H;
+  slabd_tile(g, TA, TB, S, H);
+  const int ntile = (g.L1 / TA) * (g.L2 / TB);
+  int maxp = 0;
+  for (int xa = 0; xa < g.L0; xa += nlb) maxp = std::max(maxp, slice_band(g.L0, xa + nlb - 1) - slice_band(g.L0, xa) + 1);
+  return ntile * maxp;
 }
 
 template <class R> static void launch_stream(const HopArgs<R>& A, hipStream_t st) {

@@ -64,6 +64,10 @@ template <class R> struct HopArgs {
   typename arith<R>::type a, b;
   int g5_in, g5_out;       // multiply the hop input / the hop result by gamma_5
   int map;                 // work-item mapping (HOP_MAP_*), nrhs > 1 only
+  // optional (HOP_MAP_SLABD only): partial ||out||^2 per system (rhs, block of nlb slices),
+  // nslot partials per system at npart[sys * nslot + k] (see slabd_norm_slots)
+  double* npart = nullptr;
+  int nlb = 0, nslot = 0;
 };
 
 // Work-item mappings of the hop kernel for several right-hand sides.
@@ -94,6 +98,9 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
 constexpr int HOP_WALK_T = 8;   // slices per walk
 
 template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
+// partials per system of the norm the LDS-staged slab kernel (HOP_MAP_SLABD, FP32 even-odd
+// hop) can add to its output for systems of nlb slices
+int slabd_norm_slots(const Geo& g, int nlb);
 template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t s);   // half.hip
 
 // layout conversions

@@ -127,9 +127,12 @@ __global__ void k_targets(int nsys, const double* partb, int nchunk, const doubl
 namespace {
 
 // out = a*x + b*D(in) on one parity or both, block-restricted
+// npart (even-odd FP32 hop with the LDS-staged slab mapping only, g5i = 0): also write the
+// partial ||out||^2 of each system of nlb slices, nslot per system (slabd_norm_slots)
 template <class R>
 void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int parity_out, int nrhs, int lb,
-         int colour, typename arith<R>::type a, typename arith<R>::type b, int g5i, int g5o, hipStream_t st) {
+         int colour, typename arith<R>::type a, typename arith<R>::type b, int g5i, int g5o, hipStream_t st,
+         double* npart = nullptr, int nlb = 0, int nslot = 0) {
   HopArgs<R> A;
   A.out = out;
   A.in = in;
@@ -147,6 +150,9 @@ void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int p
   A.g5_in = g5i;
   A.g5_out = g5o;
   A.map = hop_map_for(c, parity_out < 0, prec_of<R>(), nrhs);
+  A.npart = npart;
+  A.nlb = nlb;
+  A.nslot = nslot;
   launch_hop<R>(A, st);
 }
 
@@ -258,22 +264,31 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
       fin_geom(SC, nsys, G.nchunk, w->partB, w->selected, w->target2, 1, st);
     }
     SAP_HIP_CHECK(c, hipGetLastError());
+    // the LDS-staged FP32 hop writes ||M_hat p||^2 and ||M_hat^dagger s||^2 itself
+    int nslot = 0;
+    if (std::is_same<R, float>::value && hop_map_for(c, false, prec_of<R>(), nrhs) == HOP_MAP_SLABD) {
+      nslot = slabd_norm_slots(c->g, lb ? lb : c->geom.L[0]);
+      if (nslot > G.nchunk) nslot = 0;       // the partial buffers hold G.nchunk per system
+    }
+    const int nlb = lb ? lb : c->geom.L[0];
+    const int nq = nslot ? nslot : G.nchunk;
     // iterations on all systems (no host interaction; scalars stay on the device)
     auto iterate = [&](hipStream_t q) {
       if (method == SAP_CG) {
         // q = M_hat p
         hop<R>(c, U, T, P, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 0, 0, q);
-        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
-        blas_norm2<R>(G, nrhs, Q, 1, w->partA, q);
-        fin_alpha(SC, nsys, G.nchunk, w->partA, q);
-        // x += alpha p, s -= alpha q
-        blas_cg_xs<R>(G, nrhs, Ee, P, S, Q, w->alpha, w->partB, q);
+        hop<R>(c, U, Q, T, P, 0, nrhs, lb, colour, aI, k2R, 0, 0, q, nslot ? w->partA : nullptr, nlb, nslot);
+        if (!nslot) blas_norm2<R>(G, nrhs, Q, 1, w->partA, q);
+        fin_alpha(SC, nsys, nq, w->partA, q);
+        // s -= alpha q (x += alpha p waits for the direction update)
+        blas_cg_s<R>(G, nrhs, S, Q, w->alpha, w->partB, q);
         // r = M_hat^dagger s
         hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 1, 0, q);
-        hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 1, q);
-        blas_norm2<R>(G, nrhs, Rr, 1, w->partC, q);
-        fin_beta(SC, nsys, G.nchunk, w->partB, w->partC, w->target2, q);
-        blas_xpay<R>(G, nrhs, P, Rr, w->beta, q);
+        hop<R>(c, U, Rr, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 1, q, nslot ? w->partC : nullptr, nlb, nslot);
+        if (!nslot) blas_norm2<R>(G, nrhs, Rr, 1, w->partC, q);
+        fin_beta(SC, nsys, G.nchunk, w->partB, nq, w->partC, w->target2, q);
+        // x += alpha p, p = r + beta p
+        blas_cg_xp<R>(G, nrhs, Ee, P, Rr, w->alpha, w->beta, q);
       } else if (method == SAP_BICGSTAB) {
         // residual r in S, shadow r0 in Rr, v in Q, t in HX
         blas_bicg_p<R>(G, nrhs, P, S, Q, w->cs, q);
