@@ -32,6 +32,7 @@ int apply_op_any(sap_ctx* ctx, void* out, const void* in, int nrhs, int lb, int 
 
 struct SolverWS {
   int max_rhs, max_sys, max_chunk;
+  size_t part_cap;                       // doubles in each of partA / partB / partC
   double2 *hx, *s, *r, *p, *q, *t;       // half fields (sized for FP64, max_rhs)
   double2 *x64, *r64, *ax, *rin, *e;     // full fields
   double *partA, *partB, *partC;
@@ -67,6 +68,7 @@ extern "C" int sap_solver_create(sap_ctx* c) {
   // three partials per (system, chunk); a level of nblk blocks has at most max_chunk + nblk
   // chunks per rhs
   const size_t npart = (size_t)3 * w->max_rhs * (w->max_chunk + c->geom.L[0] / minlb + 1);
+  w->part_cap = npart;
   auto A = [&](void** p, size_t n) { return hipMalloc(p, n) == hipSuccess; };
   bool ok = A((void**)&w->hx, half) && A((void**)&w->s, half) && A((void**)&w->r, half) &&
             A((void**)&w->p, half) && A((void**)&w->q, half) && A((void**)&w->t, half) &&
@@ -268,7 +270,7 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
     int nslot = 0;
     if (std::is_same<R, float>::value && hop_map_for(c, false, prec_of<R>(), nrhs) == HOP_MAP_SLABD) {
       nslot = slabd_norm_slots(c->g, lb ? lb : c->geom.L[0]);
-      if (nslot > G.nchunk) nslot = 0;       // the partial buffers hold G.nchunk per system
+      if ((size_t)nslot * nsys > w->part_cap) nslot = 0;   // no room in the partial buffers
     }
     const int nlb = lb ? lb : c->geom.L[0];
     const int nq = nslot ? nslot : G.nchunk;
