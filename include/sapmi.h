@@ -29,8 +29,10 @@
  *           ((rhs*2 + parity)*12*Vhp) + ((j/64)*12 + c - c%2)*64 + 2*(j%64) + c%2
  *                                                                   (SAP_F32, complex64:
  *           the components 2k and 2k + 1 of a site are adjacent, one 16-byte word).
- *           SAP_F16: the same component order with a half-precision complex (two FP16)
- *           per entry and rhs blocks of 26*Vhp entries: parity 0 and 1 components
+ *           SAP_F16: a half-precision complex (two FP16, 4 bytes) per entry at
+ *           ((rhs*26 + parity*12)*Vhp) + ((j/64)*12 + c - c%4)*64 + 4*(j%64) + c%4
+ *           (the components 4k .. 4k + 3 of a site are adjacent, one 16-byte word),
+ *           rhs blocks of 26*Vhp entries: parity 0 and 1 components
  *           (24*Vhp), then one FP32 norm per (parity, j) at float index
  *           rhs*26*Vhp + 24*Vhp + parity*Vhp + j; a component's value is the stored one
  *           times the norm of its site (the largest component magnitude of the site).

@@ -95,9 +95,14 @@ __device__ __host__ __forceinline__ long long tiled(long long j, int c, int NC) 
 // each pair one 16-byte word, in the same tiled scheme with 6 components: pair k of site j
 // is float4 number tiled(j, k, 6) of the (rhs, parity) block, i.e. complex number
 // ((j / 64) * 12 + 2k) * 64 + 2 (j % 64) + (c % 2) for component c = 2k + c % 2. A work-item
-// then moves a site with 6 loads or stores instead of 12.
+// then moves a site with 6 loads or stores instead of 12. FP16 fields (two-half complex,
+// 4 bytes) store the components in quads (4k .. 4k + 3), one 16-byte word each: entry
+// ((j / 64) * 12 + 4k) * 64 + 4 (j % 64) + (c % 4) for component c = 4k + c % 4, so a site
+// is 3 loads.
 template <class R> __device__ __host__ __forceinline__ long long sidx(long long j, int c) {
   if constexpr (std::is_same<R, float>::value) return ((j >> 6) * 12 + (c & ~1)) * TILE + 2 * (j & (TILE - 1)) + (c & 1);
+  else if constexpr (std::is_same<R, h16>::value)
+    return ((j >> 6) * 12 + (c & ~3)) * TILE + 4 * (j & (TILE - 1)) + (c & 3);
   else return tiled(j, c, 12);
 }
 
@@ -303,6 +308,38 @@ __device__ __forceinline__ void accum_recon(int mu, bool plus, const cx<R> g[2][
       default:
         if (plus) { acc[2][c] = acc[2][c] + times_i(g[0][c]); acc[3][c] = acc[3][c] - times_i(g[1][c]); }
         else      { acc[2][c] = acc[2][c] - times_i(g[0][c]); acc[3][c] = acc[3][c] + times_i(g[1][c]); }
+        break;
+    }
+  }
+}
+
+// acc += w * reconstruct(g) (w real), with one fused multiply-add per real component
+template <class R>
+__device__ __forceinline__ void accum_recon_scaled(int mu, bool plus, const cx<R> g[2][3], R w, cx<R> acc[4][3]) {
+  auto fma_c = [&](cx<R>& a, const cx<R>& v, R s) {   // a += s * v (contracted to FMA)
+    a.r = s * v.r + a.r;
+    a.i = s * v.i + a.i;
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    fma_c(acc[0][c], g[0][c], w);
+    fma_c(acc[1][c], g[1][c], w);
+    switch (mu) {
+      case 0:
+        fma_c(acc[2][c], g[0][c], plus ? -w : w);
+        fma_c(acc[3][c], g[1][c], plus ? -w : w);
+        break;
+      case 1:
+        fma_c(acc[2][c], times_i(g[1][c]), plus ? w : -w);
+        fma_c(acc[3][c], times_i(g[0][c]), plus ? w : -w);
+        break;
+      case 2:
+        fma_c(acc[2][c], g[1][c], plus ? w : -w);
+        fma_c(acc[3][c], g[0][c], plus ? -w : w);
+        break;
+      default:
+        fma_c(acc[2][c], times_i(g[0][c]), plus ? w : -w);
+        fma_c(acc[3][c], times_i(g[1][c]), plus ? -w : w);
         break;
     }
   }

@@ -11,6 +11,7 @@
 // 4), FP64 or FP32 arithmetic matching the storage. Workgroups are numbered rhs-fastest
 // and renumbered per XCD; with several rhs four of them share each link load.
 #include "internal.h"
+#include "site_io.h"
 
 namespace sap {
 
@@ -1184,6 +1185,62 @@ void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
   }
 }
 
+// FP16 output site j of parity p and rhs r: out = a x + b (g5) acc, zero on unselected
+// sites, stored as three quad words (non-temporal) divided by the site norm (the largest
+// component magnitude), and the norm. n2 (optional): += the squared norm of the values
+// before rounding to FP16.
+__device__ __forceinline__ void store_out16(const Field<h16>& out, const Field<h16>& x, int r, int p, long long j,
+                                            long long Vhp, bool sel, bool g5o, float a, float b,
+                                            const cx<float> acc[4][3], double* n2) {
+  cx<float> v[12];
+  const bool wx = sel && x.ptr;
+  float xq[24];
+  if (wx) {
+    const __half2* xb = x.ptr + r * x.rs + p * x.ps + sidx<h16>(j, 0);
+    const float xm = ((const float*)(x.ptr + r * x.rs + x.no))[(x.ps ? p : 0) * Vhp + j];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const u4v w = *(const u4v*)(xb + 4 * k * TILE);
+      const unsigned e[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 h = __half22float2(h2_of(e[i]));
+        xq[8 * k + 2 * i] = h.x * xm;
+        xq[8 * k + 2 * i + 1] = h.y * xm;
+      }
+    }
+  }
+  float m = 0.0f;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = sp * 3 + c;
+      cx<float> h = acc[sp][c];
+      if (g5o && sp >= 2) h = -h;
+      cx<float> val = {b * h.r, b * h.i};
+      if (wx) {
+        val.r += a * xq[2 * k];
+        val.i += a * xq[2 * k + 1];
+      }
+      v[k] = sel ? val : cx<float>{0.0f, 0.0f};
+      m = fmaxf(m, fmaxf(fabsf(v[k].r), fabsf(v[k].i)));
+      if (n2) *n2 += (double)v[k].r * v[k].r + (double)v[k].i * v[k].i;
+    }
+  const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+  __half2* ob = out.ptr + r * out.rs + p * out.ps + sidx<h16>(j, 0);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    u4v w;
+    w.x = u_of(__floats2half2_rn(v[4 * k].r * inv, v[4 * k].i * inv));
+    w.y = u_of(__floats2half2_rn(v[4 * k + 1].r * inv, v[4 * k + 1].i * inv));
+    w.z = u_of(__floats2half2_rn(v[4 * k + 2].r * inv, v[4 * k + 2].i * inv));
+    w.w = u_of(__floats2half2_rn(v[4 * k + 3].r * inv, v[4 * k + 3].i * inv));
+    __builtin_nontemporal_store(w, (u4v*)(ob + 4 * k * TILE));
+  }
+  __builtin_nontemporal_store(m, (float*)(out.ptr + r * out.rs + out.no) + (out.ps ? p : 0) * Vhp + j);
+}
+
 // x0 band (XCD share, bands [L0 k / 8, L0 (k + 1) / 8)) holding slice x
 __device__ __host__ __forceinline__ int slice_band(int L0, int x) {
   int k = 0;
@@ -1191,7 +1248,8 @@ __device__ __host__ __forceinline__ int slice_band(int L0, int x) {
   return k;
 }
 
-// Slab hop with direct memory-to-LDS staging (FP32, one rhs per workgroup). The band and
+// Slab hop with direct memory-to-LDS staging (FP32 or FP16 storage, FP32 arithmetic, one
+// rhs per workgroup). The band and
 // tile are those of the slab kernel, but the LDS holds one input slice of the tile together
 // with its x1 / x2 halo, written by global_load_lds (16 bytes per lane, no registers) after
 // a barrier, so that every spatial neighbour of a step is read from LDS and the memory
@@ -1201,18 +1259,27 @@ __device__ __host__ __forceinline__ int slice_band(int L0, int x) {
 // backward half-spinor of output x0 + 1 is computed from slice x0 before it is replaced.
 // A halo site is also the input of a neighbouring tile's workgroup in the same step; it is
 // read from L2 only while the two workgroups stay within a fraction of a step of each
-// other. LDS: [6 pair units][kSlabdUnit] holding S tile sites, then H
-// halo sites (2 TB L3h in x1, 2 TA L3h in x2; none where the tile spans the direction),
-// S + H <= kSlabdUnit; the fixed unit stride keeps the unit offsets immediate.
+// other. LDS: [NW 16-byte words][kSlabdUnit] holding S tile sites, then H halo sites
+// (2 TB L3h in x1, 2 TA L3h in x2; none where the tile spans the direction), S + H <=
+// kSlabdUnit; the fixed stride keeps the word offsets immediate. A site is 6 pair words in
+// FP32 and 3 quad words, plus an FP32 norm in a [kSlabdUnit] array after the words, in
+// FP16 (larger FP16 tiles, 4 x 8 x 12 on 24^3 in 35 KB, ran slower: two 6-wave
+// workgroups per CU hide the loads of a step less well than four 3-wave ones).
 constexpr int kSlabdUnit = 416;
+template <class SR> constexpr size_t slabd_lds() {
+  return std::is_same<SR, h16>::value ? (size_t)kSlabdUnit * (3 * 16 + 4) : (size_t)kSlabdUnit * 96;
+}
 
-template <bool LIN, bool G5I, bool G5O, bool NRM>
+template <class SR, bool LIN, bool G5I, bool G5O, bool NRM>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
-void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
+void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
   typedef float R;
-  typedef float2 V2;
+  typedef typename vec2<SR>::type V2;
+  constexpr bool F16 = std::is_same<SR, h16>::value;
+  constexpr int NW = F16 ? 3 : 6;               // 16-byte words per site
   extern __shared__ char smem_raw[];
-  const lds_ptr<f4v> lds = (lds_ptr<f4v>)smem_raw;
+  const lds_ptr<f4v> lds = (lds_ptr<f4v>)smem_raw;   // FP16: the words' bits
+  const lds_ptr<float> ldn = (lds_ptr<float>)(smem_raw + NW * kSlabdUnit * 16);   // FP16 norms
   const Geo& g = A.g;
   const int L3h = g.L3h;
   const int S = TA * TB * L3h;
@@ -1284,53 +1351,97 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
     }
   };
   const f4v* inb = (const f4v*)(A.in.ptr + r0 * A.in.rs + q * A.in.ps);
+  const float* inn = F16 ? (const float*)(A.in.ptr + r0 * A.in.rs + A.in.no) + (A.in.ps ? q : 0) * Vhp : nullptr;
+  // words (and FP16 norm) of slice-local site sl of slice x to LDS slot base + lane
+  auto dma = [&](int x, int sl, int base) {
+    const f4v* src = word(inb, x, sl, NW);
+#pragma unroll
+    for (int u = 0; u < NW; ++u)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + u * TILE),
+                                       (__attribute__((address_space(3))) void*)(lds + u * SH + base), 16, 0, 0);
+    if constexpr (F16)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(inn + (long long)x * V3h + sl),
+                                       (__attribute__((address_space(3))) void*)(ldn + base), 4, 0, 0);
+  };
   // slice x (tile, and halo if asked) into LDS; lane i of a wave writes slot base + i
   auto stage = [&](int x, bool halo) {
     const int w64 = t & ~63;
-    if (act) {
-      const f4v* src = word(inb, x, s, 6);
-#pragma unroll
-      for (int u = 0; u < 6; ++u)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + u * TILE),
-                                         (__attribute__((address_space(3))) void*)(lds + u * SH + w64), 16, 0, 0);
-    }
-    if (halo && hact) {
-      const f4v* src = word(inb, x, hs, 6);
-#pragma unroll
-      for (int u = 0; u < 6; ++u)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)(src + u * TILE),
-                                         (__attribute__((address_space(3))) void*)(lds + u * SH + S + w64), 16, 0,
-                                         0);
-    }
+    if (act) dma(x, s, w64);
+    if (halo && hact) dma(x, hs, S + w64);
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's loads have landed
     __syncthreads();
   };
-  // spinor of LDS slot k (volatile: stays a ds_read); gamma5 on input applied here
-  auto get = [&](int k, cx<R> sp[4][3]) {
+  cx<R> acc[4][3], carry[2][3];
+  // spinor of LDS slot k (volatile: stays a ds_read); gamma5 on input applied here. Returns
+  // the factor the spinor still has to be multiplied by: the FP16 site norm, which the
+  // callers fold into the multiply-adds of the reconstruction (1 for FP32).
+  auto get = [&](int k, cx<R> sp[4][3]) -> R {
     cx<R> v[12];
+    R m = R(1);
+    if constexpr (F16) {
+      m = *(const volatile __attribute__((address_space(3))) float*)(ldn + k);
 #pragma unroll
-    for (int u = 0; u < 6; ++u) {
-      const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
-      const f4v w = *a;
-      v[2 * u] = {w.x, w.y};
-      v[2 * u + 1] = {w.z, w.w};
+      for (int u = 0; u < 3; ++u) {
+        const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
+        const f4v w = *a;
+        const float e[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float2 h = __half22float2(__builtin_bit_cast(__half2, e[i]));
+          v[4 * u + i] = {h.x, h.y};
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
+        const f4v w = *a;
+        v[2 * u] = {w.x, w.y};
+        v[2 * u + 1] = {w.z, w.w};
+      }
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int c = 0; c < 3; ++c) sp[a][c] = (G5I && a >= 2) ? -v[a * 3 + c] : v[a * 3 + c];
+    return m;
+  };
+  // acc += w * reconstruct(g)
+  auto recon = [&](int mu, bool plus, const cx<R> g[2][3], R w) {
+    if constexpr (F16) accum_recon_scaled<R>(mu, plus, g, w, acc);
+    else accum_recon<R>(mu, plus, g, acc);
+  };
+  // carry = w * U^+ h
+  auto carry_of = [&](const cx<R> m[9], const cx<R> h[2][3], R w) {
+    su3_dag_mul<R>(m, h[0], carry[0]);
+    su3_dag_mul<R>(m, h[1], carry[1]);
+    if constexpr (F16)
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) carry[kk][c] = {w * carry[kk][c].r, w * carry[kk][c].i};
   };
   auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
   auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
   // two stored rows of a link: U_mu at slice-local site sl of slice x, parity par (the
-  // FP32 copy: three pair words per link, 12 words per site)
+  // FP32 copy: three pair words per link, 12 words per site; the FP16 copy: a quad and a
+  // pair of half2 entries)
   auto link_raw = [&](int mu, int par, int x, int sl, cx<R> raw[6]) {
-    const f4v* u = word((const f4v*)A.U + par * 12 * Vhp, x, sl, 12) + 192 * mu;
+    if constexpr (F16) {
+      const __half2* ub = A.U + par * 24 * Vhp + 6 * mu * TILE;
+      if constexpr (LIN) load_link16_raw(ub + (long long)x * V3h * 24 + (sl >> 6) * (64 * 24), sl & 63, raw);
+      else {
+        const long long j = (long long)x * V3h + sl;
+        load_link16_raw(ub + (j >> 6) * (64 * 24), (int)(j & 63), raw);
+      }
+    } else {
+      const f4v* u = word((const f4v*)A.U + par * 12 * Vhp, x, sl, 12) + 192 * mu;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const f4v v = u[64 * k];
-      raw[2 * k] = {v.x, v.y};
-      raw[2 * k + 1] = {v.z, v.w};
+      for (int k = 0; k < 3; ++k) {
+        const f4v v = u[64 * k];
+        raw[2 * k] = {v.x, v.y};
+        raw[2 * k + 1] = {v.z, v.w};
+      }
     }
   };
 
@@ -1364,7 +1475,7 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
   };
   constexpr bool nrm = NRM;
 
-  cx<R> acc[4][3], carry[2][3], nxt[6];
+  cx<R> nxt[6];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1384,10 +1495,9 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
 #pragma unroll
       for (int e = 0; e < 6; ++e) m[e] = nxt[e];
       third_row<R>(m);
-      get(t, sp);
+      const R w = get(t, sp);
       project<R>(0, true, sp, h);
-      su3_dag_mul<R>(m, h[0], carry[0]);
-      su3_dag_mul<R>(m, h[1], carry[1]);
+      carry_of(m, h, w);
       if (x0a == 0)
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -1415,7 +1525,7 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
 #pragma unroll
           for (int e = 0; e < 6; ++e) m[e] = nxt[e];   // loaded with this slice
           third_row<R>(m);
-          get(t, sp);
+          const R w = get(t, sp);
           project<R>(0, false, sp, h);
           su3_mul<R>(m, h[0], uh[0]);
           su3_mul<R>(m, h[1], uh[1]);
@@ -1424,12 +1534,17 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
             for (int k = 0; k < 2; ++k)
 #pragma unroll
               for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
-          accum_recon<R>(0, false, uh, acc);
+          recon(0, false, uh, w);
         }
-        V2* o = A.out.ptr + r0 * A.out.rs + p * A.out.ps;
-        const V2* xv = A.x.ptr ? A.x.ptr + r0 * A.x.rs + p * A.x.ps : nullptr;
-        store_out<R, true>(o, xv, (long long)xo * V3h + s, hop_selected(A, xo), G5O, A.a, A.b, acc,
-                           nrm ? &nacc : nullptr);
+        if constexpr (F16) {
+          store_out16(A.out, A.x, r0, p, (long long)xo * V3h + s, Vhp, hop_selected(A, xo), G5O, A.a, A.b, acc,
+                      nrm ? &nacc : nullptr);
+        } else {
+          V2* o = A.out.ptr + r0 * A.out.rs + p * A.out.ps;
+          const V2* xv = A.x.ptr ? A.x.ptr + r0 * A.x.rs + p * A.x.ps : nullptr;
+          store_out<R, true>(o, xv, (long long)xo * V3h + s, hop_selected(A, xo), G5O, A.a, A.b, acc,
+                             nrm ? &nacc : nullptr);
+        }
       }
       if (!last) {
 #pragma unroll
@@ -1458,7 +1573,7 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
             for (int e = 0; e < 6; ++e) m[e] = nxt[e];
             if (i < 5) hop_link(i + 1, nxt);
             else if (carry_next) link_raw(0, q, x0, s, nxt);
-            get(k, sp);
+            const R w = get(k, sp);
             third_row<R>(m);
             project<R>(mu, dir == 1, sp, h);
             if (dir == 0) {
@@ -1468,7 +1583,7 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
               su3_dag_mul<R>(m, h[0], uh[0]);
               su3_dag_mul<R>(m, h[1], uh[1]);
             }
-            accum_recon<R>(mu, dir == 1, uh, acc);
+            recon(mu, dir == 1, uh, w);
             // the accumulator is next read in the following step: without this pin the
             // compiler sinks the arithmetic of all six hops below their loads and spills
 #pragma unroll
@@ -1487,10 +1602,9 @@ void hop_slabd_kernel(HopArgs<float> A, int TA, int TB) {
             link_raw(0, q, x0, s, m);
           }
           third_row<R>(m);
-          get(t, sp);
+          const R w = get(t, sp);
           project<R>(0, true, sp, h);
-          su3_dag_mul<R>(m, h[0], carry[0]);
-          su3_dag_mul<R>(m, h[1], carry[1]);
+          carry_of(m, h, w);
         }
       }
     }
@@ -1597,8 +1711,8 @@ template <class R, int NR> static void launch_slab(const HopArgs<R>& A, hipStrea
 }
 
 // Tile of the LDS-staged slab kernel: TA x TB x L3h sites whose slice and x1 / x2 halo fit
-// the kSlabdUnit LDS slots, with the fewest halo sites per tile site, then the largest tile.
-static void slabd_tile(const Geo& g, int& TA, int& TB, int& S, int& H) {
+// the unit LDS slots, with the fewest halo sites per tile site, then the largest tile.
+static void slabd_tile(const Geo& g, int unit, int& TA, int& TB, int& S, int& H) {
   TA = TB = 1;
   double best = 1e30;
   for (int a = 1; a <= g.L1; ++a) {
@@ -1607,7 +1721,7 @@ static void slabd_tile(const Geo& g, int& TA, int& TB, int& S, int& H) {
       if (g.L2 % b) continue;
       const int s = a * b * g.L3h;
       const int h = 2 * ((a < g.L1 ? b * g.L3h : 0) + (b < g.L2 ? a * g.L3h : 0));
-      if (s + h > kSlabdUnit || s > 512 || h > 512) continue;
+      if (s + h > unit || s > 512 || h > 512) continue;
       const double ratio = (double)h / s;
       if (ratio < best - 1e-12 || (ratio < best + 1e-12 && a * b > TA * TB)) {
         best = ratio;
@@ -1620,19 +1734,19 @@ static void slabd_tile(const Geo& g, int& TA, int& TB, int& S, int& H) {
   H = 2 * ((TA < g.L1 ? TB * g.L3h : 0) + (TB < g.L2 ? TA * g.L3h : 0));
 }
 
-// FP32 only; FP64 runs the slab kernel of the same tile budget
+// FP32 and FP16 storage; FP64 runs the slab kernel of the same tile budget
 template <class R> static void launch_slabd(const HopArgs<R>& A, hipStream_t st) {
-  if constexpr (!std::is_same<R, float>::value) {
+  if constexpr (std::is_same<R, double>::value) {
     launch_slab<R, 1>(A, st, 40 * 1024);
   } else {
     int TA, TB, S, H;
-    slabd_tile(A.g, TA, TB, S, H);
+    slabd_tile(A.g, kSlabdUnit, TA, TB, S, H);
     const int ntile = (A.g.L1 / TA) * (A.g.L2 / TB);
     const dim3 grid((unsigned)(8LL * ntile * A.nrhs)), blk((std::max(S, H) + 63) / 64 * 64);
-    const size_t lds = (size_t)kSlabdUnit * 96;
+    const size_t lds = slabd_lds<R>();
     const bool lin = A.g.V3h % TILE == 0;
 #define SAP_SLABD(LIN, G5I, G5O, NRM) \
-  hipLaunchKernelGGL((hop_slabd_kernel<LIN, G5I, G5O, NRM>), grid, blk, lds, st, A, TA, TB)
+  hipLaunchKernelGGL((hop_slabd_kernel<R, LIN, G5I, G5O, NRM>), grid, blk, lds, st, A, TA, TB)
     // the fused norm exists without gamma_5 on the input (the solvers' second half hops;
     // they set npart only there)
 #define SAP_SLABD_G5(LIN)                                                     \
@@ -1651,10 +1765,12 @@ template <class R> static void launch_slabd(const HopArgs<R>& A, hipStream_t st)
   }
 }
 
+void launch_slabd16(const HopArgs<h16>& A, hipStream_t st) { launch_slabd<h16>(A, st); }
+
 int slabd_norm_slots(const Geo& g, int nlb) {
   if (nlb <= 0 || g.L0 % nlb) return 0;
   int TA, TB, S, H;
-  slabd_tile(g, TA, TB, S, H);
+  slabd_tile(g, kSlabdUnit, TA, TB, S, H);
   const int ntile = (g.L1 / TA) * (g.L2 / TB);
   int maxp = 0;
   for (int xa = 0; xa < g.L0; xa += nlb) maxp = std::max(maxp, slice_band(g.L0, xa + nlb - 1) - slice_band(g.L0, xa) + 1);

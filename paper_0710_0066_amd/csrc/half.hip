@@ -16,12 +16,7 @@ namespace sap {
 // third is rebuilt in FP32 from unitarity and unit determinant
 __device__ __forceinline__ void load_link16(const __half2* U, long long Vhp, int mu, int par, long long j,
                                             cx<float> m[9]) {
-  const __half2* p = U + par * 24 * Vhp + tiled(j, 6 * mu, 24);
-#pragma unroll
-  for (int e = 0; e < 6; ++e) {
-    const float2 v = __half22float2(p[e * TILE]);
-    m[e] = {v.x, v.y};
-  }
+  load_link16_raw(U + par * 24 * Vhp + (j >> 6) * (24 * TILE) + 6 * mu * TILE, (int)(j & (TILE - 1)), m);
   third_row<float>(m);
 }
 
@@ -170,8 +165,11 @@ template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t st) {
     case HOP_MAP_WALK1:
     case HOP_MAP_BAND1:
     case HOP_MAP_SLAB1:
-    case HOP_MAP_SLAB1W:
-    case HOP_MAP_SLABD: launch_march16<1>(A, st); return;
+    case HOP_MAP_SLAB1W: launch_march16<1>(A, st); return;
+    case HOP_MAP_SLABD:
+      if (A.parity_out < 0) launch_march16<1>(A, st);
+      else launch_slabd16(A, st);
+      return;
     case HOP_MAP_MARCH2:
     case HOP_MAP_WALK2:
     case HOP_MAP_SLAB2: launch_march16<2>(A, st); return;

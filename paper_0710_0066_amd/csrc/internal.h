@@ -22,7 +22,8 @@ namespace sap {
 //   p*36*Vhp + tiled(j, 9*mu + e, 36)   (FP64);
 // the copies the hop kernels read (FP64, FP32, FP16) hold rows 0 and 1 only (e < 6), at
 // p*24*Vhp + tiled(j, 6*mu + e, 24) (FP32: the entries of a tile row stored in pairs, one
-// 16-byte word per lane, see gauge_to_f32_kernel), and the kernels rebuild row 2 from
+// 16-byte word per lane; FP16: a quad and a pair of entries per link, see
+// gauge_to_f32_kernel), and the kernels rebuild row 2 from
 // unitarity and unit determinant.
 // Momenta / forces (float64): (p, j, mu, a) at  p*32*Vhp + tiled(j, 8*mu + a, 32).
 template <class R> struct Field {
@@ -91,9 +92,9 @@ enum { HOP_MAP_SITE = 0,    // one (site, rhs) per work-item, workgroups rhs-fas
        HOP_MAP_SLAB1 = 17,  // even-odd hop only: band order, a workgroup owns a spatial tile
        HOP_MAP_SLAB1W = 18, //   of the slice staged in LDS and walks the band; 1 rhs per
        HOP_MAP_SLAB2 = 19,  //   work-item (SLAB1W: tiles up to twice as large), or 2 (SLAB2)
-       HOP_MAP_SLABD = 20,  // even-odd FP32 hop only: the slab order with the slice and its
-                            //   x1 / x2 halo staged in LDS by direct memory-to-LDS loads,
-                            //   1 rhs per work-item (FP64: as SLAB1, FP16: as MARCH1)
+       HOP_MAP_SLABD = 20,  // even-odd FP32 / FP16 hop only: the slab order with the slice
+                            //   and its x1 / x2 halo staged in LDS by direct memory-to-LDS
+                            //   loads, 1 rhs per work-item (FP64: as SLAB1)
        HOP_NMAP = 21 };
 constexpr int HOP_WALK_T = 8;   // slices per walk
 
@@ -101,6 +102,8 @@ template <class R> void launch_hop(const HopArgs<R>& A, hipStream_t s);
 // partials per system of the norm the LDS-staged slab kernel (HOP_MAP_SLABD, FP32 even-odd
 // hop) can add to its output for systems of nlb slices
 int slabd_norm_slots(const Geo& g, int nlb);
+// the LDS-staged slab kernel on FP16 storage (even-odd hop; dslash.hip)
+void launch_slabd16(const HopArgs<h16>& A, hipStream_t s);
 template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t s);   // half.hip
 
 // layout conversions

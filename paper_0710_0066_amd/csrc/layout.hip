@@ -87,7 +87,11 @@ __global__ void unpack_gauge_kernel(Geo g, double2* out, const double2* U64) {
 // p*24*Vhp + tiled(j, c, 24). The FP32 copy stores the entries of a tile row in pairs
 // (2k, 2k + 1) of one link, one 16-byte word per lane:
 //   p*24*Vhp + (j / 64)*24*64 + (c - c % 2)*64 + 2*(j % 64) + c % 2,
-// so that a link is three 16-byte loads per work-item.
+// so that a link is three 16-byte loads per work-item. The FP16 copy stores the six
+// entries of a link of a tile row as a quad (e = 0..3, one 16-byte word per lane) and a
+// pair (e = 4, 5, 8 bytes per lane):
+//   p*24*Vhp + (j / 64)*24*64 + 6 mu*64 + (e < 4 ? 4*(j % 64) + e : 256 + 2*(j % 64) + e - 4),
+// two loads per link.
 __global__ void gauge_to_f32_kernel(long long Vhp, double2* U64c, float2* U32, __half2* U16, const double2* U64) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= 48 * Vhp) return;
@@ -97,11 +101,14 @@ __global__ void gauge_to_f32_kernel(long long Vhp, double2* U64c, float2* U32, _
   const double2 v = U64[p * 36 * Vhp + tiled(j, (int)(9 * (c / 6) + c % 6), 36)];
   U64c[k] = v;
   U32[p * 24 * Vhp + tile * 24 * TILE + (c - (c & 1)) * TILE + 2 * lane + (c & 1)] = make_float2((float)v.x, (float)v.y);
-  U16[k] = __floats2half2_rn((float)v.x, (float)v.y);
+  const long long e = c % 6, mu = c / 6;
+  U16[p * 24 * Vhp + tile * 24 * TILE + 6 * mu * TILE + (e < 4 ? 4 * lane + e : 4 * TILE + 2 * lane + e - 4)] =
+      __floats2half2_rn((float)v.x, (float)v.y);
 }
 
 // FP16 spinor fields: components divided by the site norm (the largest component
-// magnitude), norm in FP32 (rhs blocks of 26*Vhp four-byte entries)
+// magnitude), in quads of components (sidx), norm in FP32 (rhs blocks of 26*Vhp
+// four-byte entries)
 __global__ void pack_spinor16_kernel(Geo g, __half2* out, const double2* in, int nrhs) {
   const long long V = 2 * g.Vh;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,7 +123,7 @@ __global__ void pack_spinor16_kernel(Geo g, __half2* out, const double2* in, int
   for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf((float)src[k].x), fabsf((float)src[k].y)));
   const float inv = m > 0.0f ? 1.0f / m : 0.0f;
   for (int k = 0; k < 12; ++k)
-    blk[p * 12 * g.Vhp + tiled(j, k, 12)] = __floats2half2_rn((float)src[k].x * inv, (float)src[k].y * inv);
+    blk[p * 12 * g.Vhp + sidx<h16>(j, k)] = __floats2half2_rn((float)src[k].x * inv, (float)src[k].y * inv);
   ((float*)(blk + 24 * g.Vhp))[p * g.Vhp + j] = m;
 }
 
@@ -132,7 +139,7 @@ __global__ void unpack_spinor16_kernel(Geo g, double2* out, const __half2* in, i
   const float m = ((const float*)(blk + 24 * g.Vhp))[p * g.Vhp + j];
   double2* o = out + (rhs * V + i) * 12;
   for (int k = 0; k < 12; ++k) {
-    const float2 v = __half22float2(blk[p * 12 * g.Vhp + tiled(j, k, 12)]);
+    const float2 v = __half22float2(blk[p * 12 * g.Vhp + sidx<h16>(j, k)]);
     o[k] = make_double2((double)(v.x * m), (double)(v.y * m));
   }
 }

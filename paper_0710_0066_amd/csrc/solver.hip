@@ -416,13 +416,13 @@ static int tune_one(sap_ctx* c, bool full, int nrhs, hipStream_t st, float* us_o
                                (m >= HOP_SWEEP && m != HOP_MAP_MARCH1 && m != HOP_MAP_WALK1 &&
                                 m != HOP_MAP_BAND1 && m != HOP_MAP_SLAB1 && m != HOP_MAP_SLAB1W &&
                                 m != HOP_MAP_SLABD);
-    // the LDS-staged slab kernel is FP32 only (FP64 runs SLAB1)
-    const bool f32_only = m == HOP_MAP_SLABD && !std::is_same<R, float>::value;
+    // the LDS-staged slab kernel exists for FP32 and FP16 storage (FP64 runs SLAB1)
+    const bool f64_alias = m == HOP_MAP_SLABD && std::is_same<R, double>::value;
     const bool half_only = m == HOP_MAP_STREAM || m >= HOP_MAP_WALK1;
     // FP16 storage has the site and marching kernels only
-    const bool f16_alias = f16 && m != HOP_MAP_SITE && m != HOP_MAP_MARCH1 && m != HOP_MAP_MARCH2 &&
+    const bool f16_alias = f16 && m != HOP_MAP_SITE && m != HOP_MAP_MARCH1 && m != HOP_MAP_MARCH2 && m != HOP_MAP_SLABD &&
                            m != HOP_MAP_MARCH4;
-    if ((full && half_only) || (nrhs == 1 && one_rhs_alias) || f16_alias || f32_only) {
+    if ((full && half_only) || (nrhs == 1 && one_rhs_alias) || f16_alias || f64_alias) {
       // the streaming, walking and band kernels exist for half hops only (the full
       // operator runs the walking and band maps as MARCH1 / MARCH2); with one rhs the
       // grouped and sweep orders coincide with SITE, MARCH2 / MARCH4 with MARCH1 and

@@ -250,13 +250,15 @@ def test_precision_16x16x16x32_operator_error_and_solves(gu, prec_name):
     assert res <= 1e-10
 
 
-@pytest.mark.parametrize("hop_map", [0, 11, 12, 13, 14])
-@pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15)])
+@pytest.mark.parametrize("hop_map", [0, 11, 12, 13, 14, 20])
+@pytest.mark.parametrize("L,l0,l0_sub,k", [SHAPES[1], SHAPES[3], ((32, 4, 4, 6), 4, 2, 0.15),
+                                          ((16, 10, 10, 12), 4, 2, 0.14)])
 def test_every_f16_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
     """The FP16 hop with each of its work-item mappings (site, x0-marching with 1 / 2 / 4
-    rhs per work-item; walk1 runs as march1) gives the oracle's D_eo and M with 1 and 5
-    right-hand sides, and the block solves that use the gamma_5-folded, block-restricted
-    and colour-selected forms reach a 1e-10 residual."""
+    rhs per work-item, walk1 running as march1, and the LDS-staged slab kernel) gives the
+    oracle's D_eo and M with 1 and 5 right-hand sides, and the block solves that use the
+    gamma_5-folded, block-restricted and colour-selected forms reach a 1e-10 residual. On
+    the 16 x 10^2 x 12 lattice the slab tile (5 x 5 x 6 sites) has halos in x1 and x2."""
     import paper_0710_0066_amd as sap
     print(f"f16 hop map {hop_map} L={L}", flush=True)
     U = synth.gauge_field(L, 0.5, 1121)
