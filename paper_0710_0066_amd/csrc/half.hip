@@ -53,7 +53,11 @@ __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long lo
         for (int r = 0; r < NR; ++r) {
           if (r >= nr) continue;
           cx<float> sp[4][3], h[2][3], uh[2][3];
-          const SiteR<h16> in = site_r(A.in, r0 + r, 1 - p, jn, Vhp);
+          // the stored (norm-divided) components; the site norm goes into the
+          // multiply-adds of the reconstruction
+          SiteR<h16> in = site_r(A.in, r0 + r, 1 - p, jn, Vhp);
+          const float w = flip ? -in.m : in.m;
+          in.m = 1.0f;
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -69,12 +73,7 @@ __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long lo
             su3_dag_mul<float>(m, h[0], uh[0]);
             su3_dag_mul<float>(m, h[1], uh[1]);
           }
-          if (flip)
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-#pragma unroll
-              for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
-          accum_recon<float>(mu, dir == 1, uh, acc[r]);
+          accum_recon_scaled<float>(mu, dir == 1, uh, w, acc[r]);
         }
       }
     }
