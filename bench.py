@@ -76,7 +76,8 @@ def parse():
                     help="also time the oracle's apply_M / apply_W1 / CGLS iterations on the host")
     ap.add_argument("--only-dslash", action="store_true",
                     help="time only the Dslash loop (for profiler runs)")
-    ap.add_argument("--only-solve", choices=["cg_f32", "bicgstab_f32", "cg_f16", "bicgstab_f16", "cg_f64"],
+    ap.add_argument("--only-solve", choices=["cg_f32", "bicgstab_f32", "cg_f16", "bicgstab_f16", "cg_f64",
+                                             "bicgstab_f64"],
                     help="run only this batched block solve of both levels once (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
@@ -243,6 +244,7 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=5):
       mixed_batched       FP32 inner solves inside the FP64 defect correction, every block
                           and rhs of a level in one batched solve;
       fp64_batched        the same batching, FP64 inner solve (the precision gain alone);
+      fp64_batched_bicgstab  the same with BiCGstab (the precision gain of that method);
       fp64_rhs_loop       FP64, one rhs per call, the blocks of a level together;
       fp64_per_block_loop FP64, one block and one rhs per call (the plain, unbatched
                           solve: 432 calls, timed once);
@@ -308,15 +310,24 @@ def block_solve_comparison(sap, torch, ctx, cfg, L, repeats=5):
             half[name] = {"error": str(e)}
     print("[bench] block solves: fp64 batched", file=sys.stderr, flush=True)
     f = run(plain, "batched", repeats)
+    print("[bench] block solves: fp64 batched bicgstab", file=sys.stderr, flush=True)
+    try:
+        fbi = run(sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F64, inner_tol=0.0, method=sap.SAP_BICGSTAB),
+                  "batched", repeats)
+    except sap.SapError as e:
+        fbi = {"error": str(e)}
     print("[bench] block solves: fp64 one rhs per call", file=sys.stderr, flush=True)
     fl = run(plain, "rhs", 1)
     print("[bench] block solves: fp64 one block and rhs per call", file=sys.stderr, flush=True)
     fb1 = run(plain, "block", 1)
     return {"systems": f"{nrhs} rhs x (12 blocks 24^3x4 + 24 blocks 24^3x2) = {nrhs * 36}",
             "tol": 1e-10, "mixed_batched": m, "fp64_batched": f, "fp64_rhs_loop": fl,
-            "fp64_per_block_loop": fb1, "mixed_batched_by_method": methods,
+            "fp64_per_block_loop": fb1, "fp64_batched_bicgstab": fbi, "mixed_batched_by_method": methods,
             "mixed_f16_storage_by_method": half,
             "speedup_vs_fp64_batched": f["seconds"] / m["seconds"],
+            "speedup_bicgstab_vs_fp64_batched_bicgstab":
+                fbi["seconds"] / methods["bicgstab"]["seconds"]
+                if "seconds" in fbi and "seconds" in methods["bicgstab"] else None,
             "speedup_vs_fp64_rhs_loop": fl["seconds"] / m["seconds"],
             "speedup_vs_fp64_per_block_loop": fb1["seconds"] / m["seconds"],
             "speedup_bicgstab_vs_fp64_per_block_loop":

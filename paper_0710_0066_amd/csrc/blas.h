@@ -77,7 +77,8 @@ template <class R> void blas_bicg_xr(const SysGrid& G, int nrhs, Field<R> x, Fie
 void fin_bicg_rho(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, const int* sel,
                   const double* target2, int init, hipStream_t s);
 void fin_bicg_alpha(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, hipStream_t s);
-void fin_bicg_omega(const SysScal& S, double* cs, int nsys, int nchunk, const double* part,
+// part: nchunk triples per system (<t, s>, ||t||^2), part_s: nchunk_s partials of ||s||^2
+void fin_bicg_omega(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, int nchunk_s,
                     const double* part_s, const double* target2, hipStream_t s);
 
 // y = c0 y + c1 u + c2 w (w.ptr may be null; y is not read when c0 = 0) with complex

@@ -467,12 +467,12 @@ __global__ void k_fin_bicg_alpha(SysScal S, double* cs, int nsys, int nchunk, co
 // omega = <t, s> / ||t||^2. When ||s||^2 already meets the target the step ends with
 // x += alpha p (omega = 0, r = s); when <t, s> (nearly) vanishes the system stops after
 // that same update (breakdown, restarted by the defect-correction loop).
-__global__ void k_fin_bicg_omega(SysScal S, double* cs, int nsys, int nchunk, const double* part,
+__global__ void k_fin_bicg_omega(SysScal S, double* cs, int nsys, int nchunk, const double* part, int nchunk_s,
                                  const double* part_s, const double* target2) {
   for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
     double v[3];
     sys_total3(part, s, nchunk, v);
-    const double ss = sys_total(part_s, s, nchunk);
+    const double ss = sys_total(part_s, s, nchunk_s);
     if (!(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(ss))) S.flags[0] = 6;
     cx<double> om = {0.0, 0.0};
     if (S.active[s]) {
@@ -644,9 +644,10 @@ void fin_bicg_rho(const SysScal& S, double* cs, int nsys, int nchunk, const doub
 void fin_bicg_alpha(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, hipStream_t s) {
   hipLaunchKernelGGL(k_fin_bicg_alpha, dim3(1), dim3(256), 0, s, S, cs, nsys, nchunk, part);
 }
-void fin_bicg_omega(const SysScal& S, double* cs, int nsys, int nchunk, const double* part,
+void fin_bicg_omega(const SysScal& S, double* cs, int nsys, int nchunk, const double* part, int nchunk_s,
                     const double* part_s, const double* target2, hipStream_t s) {
-  hipLaunchKernelGGL(k_fin_bicg_omega, dim3(1), dim3(256), 0, s, S, cs, nsys, nchunk, part, part_s, target2);
+  hipLaunchKernelGGL(k_fin_bicg_omega, dim3(1), dim3(256), 0, s, S, cs, nsys, nchunk, part, nchunk_s, part_s,
+                     target2);
 }
 template <class R> void blas_geom_add(const SysGrid& G, int nrhs, Field<R> x, Field<R> t, const int* active,
                                       hipStream_t s) {

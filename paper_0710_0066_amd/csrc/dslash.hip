@@ -52,6 +52,44 @@ __device__ __forceinline__ void store_out(typename vec2<R>::type* ob, const type
   st_site<R, NT>(ob, j, v);
 }
 
+// store_out with reductions of the stored values v (red[0..2], see HopArgs::red): RED 1
+// ||v||^2; RED 3 <v, x> and ||v||^2. The 12 components of the site are summed at the
+// arithmetic precision and the site sums added in FP64.
+template <class R, bool NT, int RED>
+__device__ __forceinline__ void store_out_red(typename vec2<R>::type* ob, const typename vec2<R>::type* xb,
+                                              long long j, bool sel, bool g5o, R a, R b, const cx<R> acc[4][3],
+                                              double red[3]) {
+  cx<R> v[12], xv[12];
+  R s0 = R(0), s1 = R(0), s2 = R(0);
+  if (sel && xb) ld_site<R>(xb, j, xv);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int k = sp * 3 + c;
+      cx<R> h = acc[sp][c];
+      if (g5o && sp >= 2) h = -h;
+      cx<R> r = {b * h.r, b * h.i};
+      if (xb) {
+        r.r += a * xv[k].r;
+        r.i += a * xv[k].i;
+      }
+      v[k] = sel ? r : cx<R>{R(0), R(0)};
+      if (RED == 1 || RED == 3) s2 += v[k].r * v[k].r + v[k].i * v[k].i;
+      if (RED == 3 && sel && xb) {
+        s0 += v[k].r * xv[k].r + v[k].i * xv[k].i;
+        s1 += v[k].r * xv[k].i - v[k].i * xv[k].r;
+      }
+    }
+  if (RED == 1) red[0] += (double)s2;
+  if (RED == 3) {
+    red[0] += (double)s0;
+    red[1] += (double)s1;
+    red[2] += (double)s2;
+  }
+  st_site<R, NT>(ob, j, v);
+}
+
 // The hop kernels read two-row link copies (FP64 or FP32) and rebuild the third row from
 // unitarity and unit determinant: row 3 = conj(row 1 x row 2). o24 is the offset of the
 // site's tile row, tiled(j, 0, 24) with the lane j % 64. FP64 entries are 16 bytes each
@@ -1270,7 +1308,7 @@ template <class SR> constexpr size_t slabd_lds() {
   return std::is_same<SR, h16>::value ? (size_t)kSlabdUnit * (3 * 16 + 4) : (size_t)kSlabdUnit * 96;
 }
 
-template <class SR, bool LIN, bool G5I, bool G5O, bool NRM>
+template <class SR, bool LIN, bool G5I, bool G5O, int RED>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3)))
 void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
   typedef float R;
@@ -1445,35 +1483,42 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
     }
   };
 
-  // fused ||out||^2 (A.npart): per-thread sum over the outputs of the current block of
-  // A.nlb slices, reduced over the workgroup when the block ends; the partial of (system,
-  // tile, band) goes to slot tile + ntile * (band - first band of the block), and the
-  // workgroup of the first band zeroes the slots no band fills
-  double nacc = 0.0;
-  __shared__ double nsh[8];
+  // fused reductions (A.npart, RED = A.red): per-thread sums over the outputs of the
+  // current block of A.nlb slices, reduced over the workgroup when the block ends; the
+  // partials of (system, tile, band) go to slot tile + ntile * (band - first band of the
+  // block), and the workgroup of the first band zeroes the slots no band fills
+  constexpr bool nrm = RED > 0;
+  constexpr int NV = RED == 1 ? 1 : 3;          // values per slot
+  double nacc[3] = {0.0, 0.0, 0.0};
+  __shared__ double nsh[3][8];
   auto flush = [&](int blk) {
-    double v = nacc;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    if ((t & 63) == 0) nsh[t >> 6] = v;
+    for (int i = 0; i < NV; ++i) {
+      double v = nacc[i];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+      if ((t & 63) == 0) nsh[i][t >> 6] = v;
+    }
     __syncthreads();
     if (t == 0) {
-      double sum = 0.0;
-      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += nsh[w];
       const int xa = blk * A.nlb, xb = min(xa + A.nlb, g.L0) - 1;
       const int first = slice_band(g.L0, xa), last = slice_band(g.L0, xb);
-      double* dst = A.npart + ((long long)r0 * (g.L0 / A.nlb) + blk) * A.nslot;
-      dst[tile + ntile * (xcd - first)] = sum;
+      double* dst = A.npart + ((long long)r0 * (g.L0 / A.nlb) + blk) * A.nslot * NV;
+      for (int i = 0; i < NV; ++i) {
+        double sum = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += nsh[i][w];
+        dst[(tile + ntile * (xcd - first)) * NV + i] = sum;
+      }
       if (xcd == first)
         for (int pc = 1; pc < A.nslot / ntile; ++pc) {
           const int k = first + pc;
-          if (k > last || g.L0 * k / 8 == g.L0 * (k + 1) / 8) dst[tile + ntile * pc] = 0.0;
+          if (k > last || g.L0 * k / 8 == g.L0 * (k + 1) / 8)
+            for (int i = 0; i < NV; ++i) dst[(tile + ntile * pc) * NV + i] = 0.0;
         }
     }
     __syncthreads();
-    nacc = 0.0;
+    nacc[0] = nacc[1] = nacc[2] = 0.0;
   };
-  constexpr bool nrm = NRM;
 
   cx<R> nxt[6];
 #pragma unroll
@@ -1537,13 +1582,14 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
           recon(0, false, uh, w);
         }
         if constexpr (F16) {
+          static_assert(!F16 || RED <= 1, "FP16 storage fuses the norm only");
           store_out16(A.out, A.x, r0, p, (long long)xo * V3h + s, Vhp, hop_selected(A, xo), G5O, A.a, A.b, acc,
-                      nrm ? &nacc : nullptr);
+                      nrm ? &nacc[0] : nullptr);
         } else {
           V2* o = A.out.ptr + r0 * A.out.rs + p * A.out.ps;
           const V2* xv = A.x.ptr ? A.x.ptr + r0 * A.x.rs + p * A.x.ps : nullptr;
-          store_out<R, true>(o, xv, (long long)xo * V3h + s, hop_selected(A, xo), G5O, A.a, A.b, acc,
-                             nrm ? &nacc : nullptr);
+          store_out_red<R, true, RED>(o, xv, (long long)xo * V3h + s, hop_selected(A, xo), G5O, A.a, A.b, acc,
+                                      nacc);
         }
       }
       if (!last) {
@@ -1745,18 +1791,21 @@ template <class R> static void launch_slabd(const HopArgs<R>& A, hipStream_t st)
     const dim3 grid((unsigned)(8LL * ntile * A.nrhs)), blk((std::max(S, H) + 63) / 64 * 64);
     const size_t lds = slabd_lds<R>();
     const bool lin = A.g.V3h % TILE == 0;
-#define SAP_SLABD(LIN, G5I, G5O, NRM) \
-  hipLaunchKernelGGL((hop_slabd_kernel<R, LIN, G5I, G5O, NRM>), grid, blk, lds, st, A, TA, TB)
-    // the fused norm exists without gamma_5 on the input (the solvers' second half hops;
-    // they set npart only there)
-#define SAP_SLABD_G5(LIN)                                                     \
-  do {                                                                        \
-    if (A.npart && !A.g5_in && A.g5_out) SAP_SLABD(LIN, false, true, true);   \
-    else if (A.npart && !A.g5_in) SAP_SLABD(LIN, false, false, true);         \
-    else if (A.g5_in && A.g5_out) SAP_SLABD(LIN, true, true, false);          \
-    else if (A.g5_in) SAP_SLABD(LIN, true, false, false);                     \
-    else if (A.g5_out) SAP_SLABD(LIN, false, true, false);                    \
-    else SAP_SLABD(LIN, false, false, false);                                 \
+#define SAP_SLABD(LIN, G5I, G5O, RED) \
+  hipLaunchKernelGGL((hop_slabd_kernel<R, LIN, G5I, G5O, RED>), grid, blk, lds, st, A, TA, TB)
+    // the fused reductions exist without gamma_5 on the input (the solvers' second half
+    // hops; they set npart only there): the norm with and without gamma_5 on the output
+    // (CG), the dot product and norm without (BiCGstab, FP32 only)
+    constexpr bool f32 = std::is_same<R, float>::value;
+#define SAP_SLABD_G5(LIN)                                                                  \
+  do {                                                                                     \
+    if (A.npart && A.red == 1 && !A.g5_in && A.g5_out) SAP_SLABD(LIN, false, true, 1);     \
+    else if (A.npart && A.red == 1 && !A.g5_in) SAP_SLABD(LIN, false, false, 1);           \
+    else if (f32 && A.npart && A.red == 3 && !A.g5_in && !A.g5_out) SAP_SLABD(LIN, false, false, f32 ? 3 : 0); \
+    else if (A.g5_in && A.g5_out) SAP_SLABD(LIN, true, true, 0);                           \
+    else if (A.g5_in) SAP_SLABD(LIN, true, false, 0);                                      \
+    else if (A.g5_out) SAP_SLABD(LIN, false, true, 0);                                     \
+    else SAP_SLABD(LIN, false, false, 0);                                                  \
   } while (0)
     if (lin) SAP_SLABD_G5(true);
     else SAP_SLABD_G5(false);

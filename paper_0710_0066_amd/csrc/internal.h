@@ -65,10 +65,13 @@ template <class R> struct HopArgs {
   typename arith<R>::type a, b;
   int g5_in, g5_out;       // multiply the hop input / the hop result by gamma_5
   int map;                 // work-item mapping (HOP_MAP_*), nrhs > 1 only
-  // optional (HOP_MAP_SLABD only): partial ||out||^2 per system (rhs, block of nlb slices),
-  // nslot partials per system at npart[sys * nslot + k] (see slabd_norm_slots)
+  // optional (HOP_MAP_SLABD only): per-system partial reductions of the output over
+  // systems (rhs, block of nlb slices), nslot partials per system (see slabd_norm_slots):
+  //   red = 1: ||out||^2 at npart[sys * nslot + k];
+  //   red = 3 (FP32): (Re, Im <out, x>, ||out||^2) with out conjugated, at
+  //   npart[3 (sys * nslot + k) + i].
   double* npart = nullptr;
-  int nlb = 0, nslot = 0;
+  int nlb = 0, nslot = 0, red = 0;
 };
 
 // Work-item mappings of the hop kernel for several right-hand sides.

@@ -67,7 +67,12 @@ extern "C" int sap_solver_create(sap_ctx* c) {
   const size_t full = 2 * half;
   // three partials per (system, chunk); a level of nblk blocks has at most max_chunk + nblk
   // chunks per rhs
-  const size_t npart = (size_t)3 * w->max_rhs * (w->max_chunk + c->geom.L[0] / minlb + 1);
+  size_t npart = (size_t)3 * w->max_rhs * (w->max_chunk + c->geom.L[0] / minlb + 1);
+  // room for the hop-fused reductions too (three values per slot; systems of l0, l0_sub
+  // or all L0 slices)
+  for (int nlb : {c->geom.l0, c->geom.l0_sub, c->geom.L[0]})
+    if (nlb > 0)
+      npart = std::max(npart, (size_t)3 * w->max_rhs * (c->geom.L[0] / nlb) * slabd_norm_slots(c->g, nlb));
   w->part_cap = npart;
   auto A = [&](void** p, size_t n) { return hipMalloc(p, n) == hipSuccess; };
   bool ok = A((void**)&w->hx, half) && A((void**)&w->s, half) && A((void**)&w->r, half) &&
@@ -130,11 +135,12 @@ namespace {
 
 // out = a*x + b*D(in) on one parity or both, block-restricted
 // npart (even-odd FP32 hop with the LDS-staged slab mapping only, g5i = 0): also write the
-// partial ||out||^2 of each system of nlb slices, nslot per system (slabd_norm_slots)
+// partial reductions red of each system of nlb slices, nslot per system (slabd_norm_slots):
+// 1 ||out||^2, 3 <out, x> and ||out||^2 (HopArgs::red)
 template <class R>
 void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int parity_out, int nrhs, int lb,
          int colour, typename arith<R>::type a, typename arith<R>::type b, int g5i, int g5o, hipStream_t st,
-         double* npart = nullptr, int nlb = 0, int nslot = 0) {
+         double* npart = nullptr, int nlb = 0, int nslot = 0, int red = 1) {
   HopArgs<R> A;
   A.out = out;
   A.in = in;
@@ -155,6 +161,7 @@ void hop(sap_ctx* c, const void* U, Field<R> out, Field<R> in, Field<R> x, int p
   A.npart = npart;
   A.nlb = nlb;
   A.nslot = nslot;
+  A.red = red;
   launch_hop<R>(A, st);
 }
 
@@ -266,11 +273,13 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
       fin_geom(SC, nsys, G.nchunk, w->partB, w->selected, w->target2, 1, st);
     }
     SAP_HIP_CHECK(c, hipGetLastError());
-    // the LDS-staged FP32 hop writes ||M_hat p||^2 and ||M_hat^dagger s||^2 itself
+    // the LDS-staged FP32 hop writes the reductions of its output itself: ||M_hat p||^2 and
+    // ||M_hat^dagger s||^2 (CG), <t, s> and ||t||^2 (BiCGstab, three values per slot)
     int nslot = 0;
     if (std::is_same<R, float>::value && hop_map_for(c, false, prec_of<R>(), nrhs) == HOP_MAP_SLABD) {
       nslot = slabd_norm_slots(c->g, lb ? lb : c->geom.L[0]);
-      if ((size_t)nslot * nsys > w->part_cap) nslot = 0;   // no room in the partial buffers
+      const size_t per = method == SAP_CG ? 1 : 3;
+      if (per * nslot * nsys > w->part_cap) nslot = 0;   // no room in the partial buffers
     }
     const int nlb = lb ? lb : c->geom.L[0];
     const int nq = nslot ? nslot : G.nchunk;
@@ -300,9 +309,9 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
         fin_bicg_alpha(SC, w->cs, nsys, G.nchunk, w->partB, q);
         blas_bicg_s<R>(G, nrhs, S, Q, w->cs, w->partB, q);
         hop<R>(c, U, T, S, NONE, 1, nrhs, lb, colour, Ar(0), Ar(1), 0, 0, q);
-        hop<R>(c, U, HX, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 0, q);
-        blas_cdot3<R>(G, nrhs, HX, S, HX, w->partC, q);
-        fin_bicg_omega(SC, w->cs, nsys, G.nchunk, w->partC, w->partB, w->target2, q);
+        hop<R>(c, U, HX, T, S, 0, nrhs, lb, colour, aI, k2R, 0, 0, q, nslot ? w->partC : nullptr, nlb, nslot, 3);
+        if (!nslot) blas_cdot3<R>(G, nrhs, HX, S, HX, w->partC, q);
+        fin_bicg_omega(SC, w->cs, nsys, nq, w->partC, G.nchunk, w->partB, w->target2, q);
         blas_bicg_xr<R>(G, nrhs, Ee, P, S, HX, Rr, w->cs, w->partA, q);
         fin_bicg_rho(SC, w->cs, nsys, G.nchunk, w->partA, w->selected, w->target2, 0, q);
       } else {

@@ -104,9 +104,10 @@ def test_every_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
     carried in registers, the x0-band kernel with one band of slices per XCD and the slab
     kernels with LDS-staged spatial tiles) gives the oracle's D_eo, M and W, with 1 and 5
     right-hand sides, including the gamma_5-folded and block-restricted forms the solvers
-    use (through solve_blocks). On the 16 x 10^2 x 12 lattice the slab tiles (5 x 5 x 12
-    sites in FP32, 2 x 5 x 12 in FP64) leave halos in both x1 and x2 and every XCD walks a
-    band of two slices."""
+    use (through solve_blocks with CG and BiCGstab, which with the LDS-staged FP32 mapping
+    also take their norms and dot products from the hop). On the 16 x 10^2 x 12 lattice
+    the slab tiles (5 x 5 x 12 sites in FP32, 2 x 5 x 12 in FP64) leave halos in both x1
+    and x2 and every XCD walks a band of two slices."""
     import paper_0710_0066_amd as sap
     print(f"hop map {hop_map} L={L}", flush=True)
     U = synth.gauge_field(L, 0.5, 1021)
@@ -132,16 +133,18 @@ def test_every_hop_mapping_matches_oracle(gu, hop_map, L, l0, l0_sub, k):
         b = psi
         fb = gu.to_sap(ctx, b, nrhs)
         fx = ctx.new_field(nrhs)
-        opts = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F32, inner_tol=1e-5)
-        cases = [(1, l0, sap.SAP_BLACK, "black")] + ([(2, l0_sub, sap.SAP_ALL, "all")] if l0_sub else [])
-        for level, lb, colour, cname in cases:
+        cases = [(1, l0, sap.SAP_BLACK, "black", sap.SAP_CG)]
+        if l0_sub:
+            cases += [(2, l0_sub, sap.SAP_ALL, "all", sap.SAP_CG), (2, l0_sub, sap.SAP_ALL, "all", sap.SAP_BICGSTAB)]
+        for level, lb, colour, cname, method in cases:
+            opts = sap.solve_opts(tol=1e-10, inner_prec=sap.SAP_F32, inner_tol=1e-5, method=method)
             sap.solve_blocks(ctx, fx, fb, nrhs, level, colour, opts)
             x = gu.from_sap(ctx, fx, nrhs, b.shape)
             msk = lattice.site_mask(L, lattice.colour_x0_mask(L, lb, cname))
             r = (b - dirac.apply_W(U, x, k, lb)) * msk
             ax = tuple(range(r.ndim - 6, r.ndim))
             res = np.sqrt(np.sum(np.abs(r) ** 2, axis=ax) / np.sum(np.abs(b * msk) ** 2, axis=ax))
-            assert np.all(res <= 1e-10), (level, res)
+            assert np.all(res <= 1e-10), (level, method, res)
 
 
 @pytest.mark.parametrize("name", ["plain_16x16x16x32", "batched_24x24x24x48"])
