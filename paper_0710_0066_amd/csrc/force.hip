@@ -267,12 +267,15 @@ __global__ __launch_bounds__(256) void k_su3_dev(Geo g, const double2* U, double
   if (threadIdx.x == 0) part[blockIdx.x] = nanmax(nanmax(sh[0], sh[1]), nanmax(sh[2], sh[3]));
 }
 
+// one wavefront of 64 lanes: lane l takes part[l], part[l + 64], ... in order, then a
+// fixed shuffle tree combines the lanes (the result does not depend on timing)
 __global__ void k_max_parts(int n, const double* part, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double m = 0.0;
-    for (int i = 0; i < n; ++i) m = nanmax(m, part[i]);
-    out[0] = m;
-  }
+  const int l = threadIdx.x;
+  double m = 0.0;
+  for (int i = l; i < n; i += 64) m = nanmax(m, part[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = nanmax(m, __shfl_down(m, off, 64));
+  if (l == 0) out[0] = m;
 }
 
 // Per-workgroup partial of 1/2 sum p^2 over valid sites
@@ -291,12 +294,15 @@ __global__ __launch_bounds__(256) void k_kinetic(Geo g, const double* P, double*
   if (threadIdx.x == 0) part[blockIdx.x] = 0.5 * t;
 }
 
+// one wavefront, as k_max_parts: a fixed order of additions, so the sum is bitwise
+// reproducible
 __global__ void k_sum_parts(int n, const double* part, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    out[0] = s;
-  }
+  const int l = threadIdx.x;
+  double s = 0.0;
+  for (int i = l; i < n; i += 64) s += part[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (l == 0) out[0] = s;
 }
 
 // exp(A) for anti-Hermitian 3x3 A (Taylor degree 16 after scaling by 2^-k, |A/2^k| <= 1/2)
