@@ -170,35 +170,46 @@ __device__ M3 staples(const Geo& g, const double2* U, int p, long long j, const 
   for (int e = 0; e < 9; ++e) A.m[e] = {0.0, 0.0};
   const long long jpm = nbr(g, s, j, mu, +1);                 // x+mu, parity 1-p
   const Site spm = decode(g, jpm, 1 - p);
+  // one direction at a time: unrolling would keep the links of all six staples live
+#pragma unroll 1
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == mu) continue;
     const long long jpn = nbr(g, s, j, nu, +1);               // x+nu, parity 1-p
     const long long jmn = nbr(g, s, j, nu, -1);               // x-nu, parity 1-p
     const long long jpmmn = nbr(g, spm, jpm, nu, -1);         // x+mu-nu, parity p
-    // U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
-    const M3 up = mmul_nd(mmul_nd(load_U(U, Vhp, 1 - p, jpm, nu), load_U(U, Vhp, 1 - p, jpn, mu)),
-                          load_U(U, Vhp, p, j, nu));
+    // U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+ (the memory fences keep the scheduler from
+    // loading the links of both staples at once, which would cost occupancy)
+    const M3 ab = mmul_nd(load_U(U, Vhp, 1 - p, jpm, nu), load_U(U, Vhp, 1 - p, jpn, mu));
+    asm volatile("" ::: "memory");
+    const M3 up = mmul_nd(ab, load_U(U, Vhp, p, j, nu));
+#pragma unroll
+    for (int e = 0; e < 9; ++e) A.m[e] = A.m[e] + up.m[e];
+    asm volatile("" ::: "memory");
     // U_nu(x+mu-nu)^+ U_mu(x-nu)^+ U_nu(x-nu) = (U_mu(x-nu) U_nu(x+mu-nu))^+ U_nu(x-nu)
     const M3 t = mmul(load_U(U, Vhp, 1 - p, jmn, mu), load_U(U, Vhp, p, jpmmn, nu));
+    asm volatile("" ::: "memory");
     const M3 lo = mmul_dn(t, load_U(U, Vhp, 1 - p, jmn, nu));
 #pragma unroll
-    for (int e = 0; e < 9; ++e) A.m[e] = A.m[e] + up.m[e] + lo.m[e];
+    for (int e = 0; e < 9; ++e) A.m[e] = A.m[e] + lo.m[e];
+    asm volatile("" ::: "memory");
   }
   return A;
 }
 
-__global__ __launch_bounds__(256) void k_gauge_force(Geo g, double* F, double c, const double2* U,
-                                                     const double* sx) {
-  const int p = threadIdx.x >> 7;
-  const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
+// One work-item per link: a workgroup holds 64 sites of one parity (blockIdx.y) and one
+// wavefront per direction mu, so that the staple sums of the four links of a site run in
+// parallel and the registers of one staple sum decide the occupancy.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_gauge_force(Geo g, double* F, double c, const double2* U, const double* sx) {
+  const int mu = threadIdx.x >> 6;
+  const int p = blockIdx.y;
+  const long long j = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
   if (j >= g.Vh) return;
   const Site s = decode(g, j, p);
-  for (int mu = 0; mu < 4; ++mu) {
-    const M3 W = mmul(load_U(U, g.Vhp, p, j, mu), staples(g, U, p, j, s, mu));
-    double v[8];
-    im_tr_lambda(W, v);
-    add_force(F, g.Vhp, p, j, mu, c * (sx ? sx[s.x0 * 4 + mu] : 1.0), v);
-  }
+  const M3 W = mmul(load_U(U, g.Vhp, p, j, mu), staples(g, U, p, j, s, mu));
+  double v[8];
+  im_tr_lambda(W, v);
+  add_force(F, g.Vhp, p, j, mu, c * (sx ? sx[s.x0 * 4 + mu] : 1.0), v);
 }
 
 __device__ __forceinline__ double wsum(double v) {
@@ -538,7 +549,7 @@ void launch_pair_force(const Geo& g, double* F, double coef_times_minus_kappa, c
                      sx);
 }
 void launch_gauge_force(const Geo& g, double* F, double c, const double2* U, hipStream_t s, const double* sx) {
-  hipLaunchKernelGGL(k_gauge_force, dim3(site_blocks(g)), dim3(256), 0, s, g, F, c, U, sx);
+  hipLaunchKernelGGL(k_gauge_force, dim3((unsigned)((g.Vh + 63) / 64), 2), dim3(256), 0, s, g, F, c, U, sx);
 }
 void launch_shift_links(const Geo& g, double2* out, const double2* in, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_shift_links, dim3(site_blocks(g)), dim3(256), 0, s, g, out, in, n);
