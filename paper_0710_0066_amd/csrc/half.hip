@@ -21,8 +21,10 @@ __device__ __forceinline__ void load_link16(const __half2* U, long long Vhp, int
 }
 
 // all eight hops of output site j of parity p for the rhs r0 .. r0 + nr - 1 (nr <= NR):
-// out = a x + b (g5_out) D (g5_in in), zero on unselected sites; each link is loaded once
-template <int NR>
+// out = a x + b (g5_out) D (g5_in in), zero on unselected sites; each link is loaded once.
+// G5I / G5O: A.g5_in / A.g5_out, as template arguments so that the signs are not selected
+// per component at run time.
+template <int NR, bool G5I, bool G5O>
 __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long long j, int r0, int nr) {
   const Geo& g = A.g;
   const long long Vhp = g.Vhp;
@@ -36,7 +38,7 @@ __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long lo
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[r][a][c] = {0.0f, 0.0f};
   if (sel) {
-    const bool g5i = A.g5_in != 0;
+    constexpr bool g5i = G5I;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
@@ -90,7 +92,7 @@ __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long lo
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         cx<float> hv = acc[r][a][c];
-        if (A.g5_out && a >= 2) hv = -hv;
+        if (G5O && a >= 2) hv = -hv;
         cx<float> v = A.b * hv;
         if (with_x) v = v + A.a * get(xr, 3 * a + c);
         put(ow, 3 * a + c, sel ? v : cx<float>{0.0f, 0.0f});
@@ -99,7 +101,7 @@ __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long lo
   }
 }
 
-template <bool FULL>
+template <bool FULL, bool G5I, bool G5O>
 __global__ __launch_bounds__(256) void hop16_kernel(HopArgs<h16> A) {
   const long long nwg = gridDim.x;
   const long long w = xcd_logical_block(blockIdx.x, nwg);
@@ -115,14 +117,14 @@ __global__ __launch_bounds__(256) void hop16_kernel(HopArgs<h16> A) {
     j = chunk * 256 + threadIdx.x;
   }
   if (j >= A.g.Vh) return;
-  hop16_site<1>(A, p, j, rhs, 1);
+  hop16_site<1, G5I, G5O>(A, p, j, rhs, 1);
 }
 
 // x0-marching order (as hop_march_kernel in dslash.hip): the slice-local sites of each
 // parity are cut into 8 contiguous pieces, one per XCD (workgroup id % 8), and each XCD
 // walks its piece slice by slice in increasing x0 with the rhs groups of a chunk back to
 // back. A workgroup is 128 sites of one parity, or 64 sites of each parity (full operator).
-template <bool FULL, int NR>
+template <bool FULL, int NR, bool G5I, bool G5O>
 __global__ __launch_bounds__(128) void hop16_march_kernel(HopArgs<h16> A, int nck) {
   const int xcd = blockIdx.x & 7;
   const long long l = blockIdx.x >> 3;
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(128) void hop16_march_kernel(HopArgs<h16> A, int nc
     s = lo + chunk * 128 + threadIdx.x;
   }
   if (s >= hi) return;
-  hop16_site<NR>(A, p, (long long)x0 * A.g.V3h + s, r0, min(NR, A.nrhs - r0));
+  hop16_site<NR, G5I, G5O>(A, p, (long long)x0 * A.g.V3h + s, r0, min(NR, A.nrhs - r0));
 }
 
 template <int NR> static void launch_march16(const HopArgs<h16>& A, hipStream_t st) {
@@ -154,8 +156,18 @@ template <int NR> static void launch_march16(const HopArgs<h16>& A, hipStream_t 
   const int nck = (piece + per - 1) / per;
   const long long groups = (A.nrhs + NR - 1) / NR;
   const dim3 grid((unsigned)(8LL * A.g.L0 * nck * groups)), blk(128);
-  if (full) hipLaunchKernelGGL((hop16_march_kernel<true, NR>), grid, blk, 0, st, A, nck);
-  else hipLaunchKernelGGL((hop16_march_kernel<false, NR>), grid, blk, 0, st, A, nck);
+#define SAP_M16(FULL, G5I, G5O) hipLaunchKernelGGL((hop16_march_kernel<FULL, NR, G5I, G5O>), grid, blk, 0, st, A, nck)
+#define SAP_M16_G5(FULL)                                   \
+  do {                                                     \
+    if (A.g5_in && A.g5_out) SAP_M16(FULL, true, true);    \
+    else if (A.g5_in) SAP_M16(FULL, true, false);          \
+    else if (A.g5_out) SAP_M16(FULL, false, true);         \
+    else SAP_M16(FULL, false, false);                      \
+  } while (0)
+  if (full) SAP_M16_G5(true);
+  else SAP_M16_G5(false);
+#undef SAP_M16_G5
+#undef SAP_M16
 }
 
 template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t st) {
@@ -180,8 +192,18 @@ template <> void launch_hop<h16>(const HopArgs<h16>& A, hipStream_t st) {
   const long long chunks = (A.g.Vh + per - 1) / per;
   const long long n = chunks * A.nrhs;
   const dim3 grid((unsigned)((n + 7) / 8 * 8)), blk(256);
-  if (full) hipLaunchKernelGGL(hop16_kernel<true>, grid, blk, 0, st, A);
-  else hipLaunchKernelGGL(hop16_kernel<false>, grid, blk, 0, st, A);
+#define SAP_S16(FULL, G5I, G5O) hipLaunchKernelGGL((hop16_kernel<FULL, G5I, G5O>), grid, blk, 0, st, A)
+#define SAP_S16_G5(FULL)                                   \
+  do {                                                     \
+    if (A.g5_in && A.g5_out) SAP_S16(FULL, true, true);    \
+    else if (A.g5_in) SAP_S16(FULL, true, false);          \
+    else if (A.g5_out) SAP_S16(FULL, false, true);         \
+    else SAP_S16(FULL, false, false);                      \
+  } while (0)
+  if (full) SAP_S16_G5(true);
+  else SAP_S16_G5(false);
+#undef SAP_S16_G5
+#undef SAP_S16
 }
 
 }  // namespace sap
