@@ -123,42 +123,45 @@ __device__ __forceinline__ M3 outer2(const C h1[2][3], const C h2[2][3]) {
   return r;
 }
 
-// One work-item per site (128 sites of each parity per workgroup), its four forward links.
-__global__ __launch_bounds__(256) void k_pair_force(Geo g, double* F, double c, const double2* a,
-                                                    const double2* b, const double2* U, int lb,
-                                                    const double* sx) {
-  const int p = threadIdx.x >> 7;
-  const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
+// One work-item per link: a workgroup holds 64 sites of one parity (blockIdx.y) and one
+// wavefront per direction mu (the four wavefronts read the same site spinors through L2).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_pair_force(Geo g, double* F, double c, const double2* a, const double2* b, const double2* U, int lb,
+                  const double* sx) {
+  const int mu = threadIdx.x >> 6;
+  const int p = blockIdx.y;
+  const long long j = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
   if (j >= g.Vh) return;
   const long long Vhp = g.Vhp;
   const Site s = decode(g, j, p);
-  C ax[4][3], bx[4][3];
-  load_sp(a + p * 12 * Vhp, j, ax);
-  load_sp(b + p * 12 * Vhp, j, bx);
+  if (lb && mu == 0 && (s.x0 % lb) == lb - 1) return;    // link absent from W
+  const long long jn = nbr(g, s, j, mu, +1);
+  const double2* ap = a + p * 12 * Vhp;
+  const double2* bp = b + p * 12 * Vhp;
   const double2* aq = a + (1 - p) * 12 * Vhp;
   const double2* bq = b + (1 - p) * 12 * Vhp;
-  for (int mu = 0; mu < 4; ++mu) {
-    if (lb && mu == 0 && (s.x0 % lb) == lb - 1) continue;    // link absent from W
-    const long long jn = nbr(g, s, j, mu, +1);
-    C af[4][3], bf[4][3], hb[2][3], ha[2][3];
-    load_sp(aq, jn, af);
-    load_sp(bq, jn, bf);
-    project<double>(mu, false, bf, hb);
-    project<double>(mu, false, ax, ha);
-    const M3 X = outer2(hb, ha);
-    project<double>(mu, true, bx, hb);
-    project<double>(mu, true, af, ha);
-    const M3 Y = outer2(hb, ha);
-    const M3 Um = load_U(U, Vhp, p, j, mu);
-    const M3 YU = mmul_nd(Y, Um), UX = mmul(Um, X);
-    M3 Q;
+  C sp[4][3], hb[2][3], ha[2][3];
+  // X = sum_k hb_k (x) ha_k^*: (1 - gamma_mu) b(x + mu) and a(x)
+  load_sp(bq, jn, sp);
+  project<double>(mu, false, sp, hb);
+  load_sp(ap, j, sp);
+  project<double>(mu, false, sp, ha);
+  const M3 X = outer2(hb, ha);
+  // Y: (1 + gamma_mu) b(x) and a(x + mu)
+  load_sp(bp, j, sp);
+  project<double>(mu, true, sp, hb);
+  load_sp(aq, jn, sp);
+  project<double>(mu, true, sp, ha);
+  const M3 Y = outer2(hb, ha);
+  const M3 Um = load_U(U, Vhp, p, j, mu);
+  const M3 YU = mmul_nd(Y, Um), UX = mmul(Um, X);
+  M3 Q;
 #pragma unroll
-    for (int e = 0; e < 9; ++e) Q.m[e] = YU.m[e] - UX.m[e];
-    double v[8];
-    im_tr_lambda(Q, v);
-    const double sgn = (mu == 0 && s.x0 == g.L0 - 1) ? -1.0 : 1.0;
-    add_force(F, Vhp, p, j, mu, c * sgn * (sx ? sx[s.x0 * 4 + mu] : 1.0), v);
-  }
+  for (int e = 0; e < 9; ++e) Q.m[e] = YU.m[e] - UX.m[e];
+  double v[8];
+  im_tr_lambda(Q, v);
+  const double sgn = (mu == 0 && s.x0 == g.L0 - 1) ? -1.0 : 1.0;
+  add_force(F, Vhp, p, j, mu, c * sgn * (sx ? sx[s.x0 * 4 + mu] : 1.0), v);
 }
 
 // Staple sum of U_mu(x):
@@ -545,8 +548,8 @@ static inline unsigned site_blocks(const Geo& g) { return (unsigned)((g.Vh + 127
 
 void launch_pair_force(const Geo& g, double* F, double coef_times_minus_kappa, const double2* a, const double2* b,
                        const double2* U, int lb, hipStream_t s, const double* sx) {
-  hipLaunchKernelGGL(k_pair_force, dim3(site_blocks(g)), dim3(256), 0, s, g, F, coef_times_minus_kappa, a, b, U, lb,
-                     sx);
+  hipLaunchKernelGGL(k_pair_force, dim3((unsigned)((g.Vh + 63) / 64), 2), dim3(256), 0, s, g, F,
+                     coef_times_minus_kappa, a, b, U, lb, sx);
 }
 void launch_gauge_force(const Geo& g, double* F, double c, const double2* U, hipStream_t s, const double* sx) {
   hipLaunchKernelGGL(k_gauge_force, dim3((unsigned)((g.Vh + 63) / 64), 2), dim3(256), 0, s, g, F, c, U, sx);
