@@ -74,8 +74,10 @@ typedef enum {
   SAP_E_STATE = -6       /* call out of order (e.g. no gauge field set) */
 } sap_status;
 
-/* storage precision; arithmetic is FP64 for SAP_F64 and FP32 for SAP_F32 and SAP_F16 (FP16
- * spinors with a per-site FP32 norm and FP16 links, FP32 accumulation) */
+/* storage precision; arithmetic is FP64 for SAP_F64 and FP32 for SAP_F32. SAP_F16: FP16
+ * spinors with a per-site FP32 norm and FP16 links; each hop term projects the stored
+ * halves with one FP16 rounding and multiplies them by the link in FP16 x FP16 products
+ * (exact in FP32) summed in FP32; accumulation, norms and BLAS work are FP32 */
 typedef enum { SAP_F64 = 0, SAP_F32 = 1, SAP_F16 = 2 } sap_prec;
 typedef enum { SAP_ALL = 0, SAP_BLACK = 1, SAP_WHITE = 2 } sap_color;
 
@@ -107,7 +109,7 @@ typedef struct {
   int max_iter;      /* cap on inner iterations summed over outer cycles (SAP_SAP_BICGSTAB:
                       * on BiCGstab iterations) */
   sap_prec inner_prec; /* storage precision of the inner Krylov solve (FP32 arithmetic for
-                        * SAP_F32 and SAP_F16) */
+                        * SAP_F32; for SAP_F16 see sap_prec) */
   double inner_tol;  /* relative reduction asked of each inner solve (defect correction);
                       * must lie in (0, 1) for SAP_F32 and SAP_F16 (about 1e-5 and 2e-3
                       * suit their rounding); <= 0 with SAP_F64 means tol */
@@ -239,7 +241,8 @@ int sap_unpack_momenta(sap_ctx* ctx, double* out, const double* in, void* stream
 
 /* out = M in (Sec. 1, eq. 2) for nrhs fields in the sap layout at precision prec
  * (FP64: float64 arithmetic; FP32: float32 storage and arithmetic; FP16: FP16 storage
- * with per-site norms and FP16 links, float32 arithmetic, each output site rounded once).
+ * with per-site norms and FP16 links, FP16 products summed in float32 (see sap_prec), each
+ * output site rounded once).
  * out and in must not overlap. */
 int apply_M(sap_ctx* ctx, void* out, const void* in, int nrhs, sap_prec prec, void* stream);
 
@@ -280,10 +283,11 @@ int apply_Dslash_eo(sap_ctx* ctx, void* out, const void* in, int nrhs, int parit
  * values by TB x2 values by all of x3, staged in LDS so that the spatial hops inside the
  * tile read the LDS copy; 1 rhs per work-item with tiles of up to 40 KB / 80 KB of LDS
  * (slab1 / slab1w) or 2 rhs per work-item (slab2); the full operator runs them as march1 /
- * march1 / march2), 20 slabd (even-odd FP32 hop: the slab order with each slice of the
+ * march1 / march2), 20 slabd (even-odd FP32 / FP16 hop: the slab order with each slice of the
  * tile and its x1 / x2 halo staged in LDS by direct memory-to-LDS loads, so that every
  * spatial neighbour is read from LDS; FP64 runs it as slab1, the full operator as march1).
- * FP16 storage has site and march1 / 2 / 4 only (the other maps run as one of these).
+ * FP16 storage has site, march1 / 2 / 4 and slabd (even-odd hop only) (the other maps run
+ * as march1 or march2).
  * us_out (host, may be NULL): 126 floats, microseconds per launch (-1: not applicable),
  * ordered [full f64, full f32, even-odd f64, even-odd f32, full f16, even-odd f16] x the
  * 21 mappings. Uses the solver
@@ -296,8 +300,8 @@ int sap_tune(sap_ctx* ctx, int nrhs, float* us_out, void* stream);
  * order, 7 reg2, 8 reg4, 9 / 10 reg2 / reg4 group-slowest, 11 / 12 / 13 x0-marching with
  * 1 / 2 / 4 rhs per work-item, 14 / 15 x0-walking with 1 / 2 rhs (march1 / march2 for
  * the full operator), 16 x0-band (march1 for the full operator), 17 / 18 / 19 slab1 /
- * slab1w / slab2 (march1 / march1 / march2 for the full operator), 20 slabd (FP32; slab1
- * for FP64, march1 for the full operator and for FP16); -1 restores the
+ * slab1w / slab2 (march1 / march1 / march2 for the full operator), 20 slabd (FP32 and FP16;
+ * slab1 for FP64, march1 for the full operator); -1 restores the
  * default), for the full operator (full = 1) or the even-odd hop (full = 0) at precision
  * prec. */
 int sap_set_hop_map(sap_ctx* ctx, int full, sap_prec prec, int nrhs, int map);

@@ -1286,8 +1286,8 @@ __device__ __host__ __forceinline__ int slice_band(int L0, int x) {
   return k;
 }
 
-// Slab hop with direct memory-to-LDS staging (FP32 or FP16 storage, FP32 arithmetic, one
-// rhs per workgroup). The band and
+// Slab hop with direct memory-to-LDS staging (FP32 storage and arithmetic, or FP16 storage
+// with the packed FP16 hop terms of site_io.h; one rhs per workgroup). The band and
 // tile are those of the slab kernel, but the LDS holds one input slice of the tile together
 // with its x1 / x2 halo, written by global_load_lds (16 bytes per lane, no registers) after
 // a barrier, so that every spatial neighbour of a step is read from LDS and the memory
@@ -1315,6 +1315,7 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
   typedef typename vec2<SR>::type V2;
   constexpr bool F16 = std::is_same<SR, h16>::value;
   constexpr int NW = F16 ? 3 : 6;               // 16-byte words per site
+  using LW = std::conditional_t<F16, unsigned, cx<float>>;   // a stored link entry
   extern __shared__ char smem_raw[];
   const lds_ptr<f4v> lds = (lds_ptr<f4v>)smem_raw;   // FP16: the words' bits
   const lds_ptr<float> ldn = (lds_ptr<float>)(smem_raw + NW * kSlabdUnit * 16);   // FP16 norms
@@ -1410,33 +1411,17 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
     __syncthreads();
   };
   cx<R> acc[4][3], carry[2][3];
-  // spinor of LDS slot k (volatile: stays a ds_read); gamma5 on input applied here. Returns
-  // the factor the spinor still has to be multiplied by: the FP16 site norm, which the
-  // callers fold into the multiply-adds of the reconstruction (1 for FP32).
+  // FP32: spinor of LDS slot k (volatile: stays a ds_read); gamma5 on input applied here.
+  // Returns 1, the factor the reconstruction multiplies by (FP16 uses term16 below).
   auto get = [&](int k, cx<R> sp[4][3]) -> R {
     cx<R> v[12];
-    R m = R(1);
-    if constexpr (F16) {
-      m = *(const volatile __attribute__((address_space(3))) float*)(ldn + k);
+    const R m = R(1);
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
-        const f4v w = *a;
-        const float e[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float2 h = __half22float2(__builtin_bit_cast(__half2, e[i]));
-          v[4 * u + i] = {h.x, h.y};
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
-        const f4v w = *a;
-        v[2 * u] = {w.x, w.y};
-        v[2 * u + 1] = {w.z, w.w};
-      }
+    for (int u = 0; u < 6; ++u) {
+      const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
+      const f4v w = *a;
+      v[2 * u] = {w.x, w.y};
+      v[2 * u + 1] = {w.z, w.w};
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -1449,28 +1434,23 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
     if constexpr (F16) accum_recon_scaled<R>(mu, plus, g, w, acc);
     else accum_recon<R>(mu, plus, g, acc);
   };
-  // carry = w * U^+ h
-  auto carry_of = [&](const cx<R> m[9], const cx<R> h[2][3], R w) {
+  // FP32: carry = U^+ h (w = 1)
+  auto carry_of = [&](const cx<R> m[9], const cx<R> h[2][3], R) {
     su3_dag_mul<R>(m, h[0], carry[0]);
     su3_dag_mul<R>(m, h[1], carry[1]);
-    if constexpr (F16)
-#pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) carry[kk][c] = {w * carry[kk][c].r, w * carry[kk][c].i};
   };
   auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
   auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
   // two stored rows of a link: U_mu at slice-local site sl of slice x, parity par (the
   // FP32 copy: three pair words per link, 12 words per site; the FP16 copy: a quad and a
   // pair of half2 entries)
-  auto link_raw = [&](int mu, int par, int x, int sl, cx<R> raw[6]) {
+  auto link_raw = [&](int mu, int par, int x, int sl, LW raw[6]) {
     if constexpr (F16) {
       const __half2* ub = A.U + par * 24 * Vhp + 6 * mu * TILE;
-      if constexpr (LIN) load_link16_raw(ub + (long long)x * V3h * 24 + (sl >> 6) * (64 * 24), sl & 63, raw);
+      if constexpr (LIN) load_link16_words(ub + (long long)x * V3h * 24 + (sl >> 6) * (64 * 24), sl & 63, raw);
       else {
         const long long j = (long long)x * V3h + sl;
-        load_link16_raw(ub + (j >> 6) * (64 * 24), (int)(j & 63), raw);
+        load_link16_words(ub + (j >> 6) * (64 * 24), (int)(j & 63), raw);
       }
     } else {
       const f4v* u = word((const f4v*)A.U + par * 12 * Vhp, x, sl, 12) + 192 * mu;
@@ -1481,6 +1461,41 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
         raw[2 * k + 1] = {v.z, v.w};
       }
     }
+  };
+
+  // FP16: w = U h (plus false) or U^dagger h (plus true) of the projection of LDS slot k,
+  // in packed FP16 (hop16_term) with the link entries lw; returns the site norm of slot k
+  // (the factor the callers fold into the reconstruction)
+  auto term16 = [&](int mu, bool plus, int k, const LW lw[6], cx<R> w[2][3]) -> R {
+    if constexpr (F16) {
+      unsigned e[9], sw[12];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) e[i] = lw[i];
+      third_row16(e);
+      const R m = *(const volatile __attribute__((address_space(3))) float*)(ldn + k);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const volatile __attribute__((address_space(3))) f4v* a = lds + u * SH + k;
+        // the whole word is reinterpreted (a bit cast of one vector element reads the
+        // vector's first element with this compiler)
+        const u4v v = __builtin_bit_cast(u4v, (f4v)*a);
+        sw[4 * u] = v.x;
+        sw[4 * u + 1] = v.y;
+        sw[4 * u + 2] = v.z;
+        sw[4 * u + 3] = v.w;
+      }
+      hop16_term<G5I>(mu, plus, e, sw, w);
+      return m;
+    } else {
+      return R(0);
+    }
+  };
+  // FP16: carry = w * uh
+  auto carry16 = [&](const cx<R> uh[2][3], R w) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) carry[kk][c] = {w * uh[kk][c].r, w * uh[kk][c].i};
   };
 
   // fused reductions (A.npart, RED = A.red): per-thread sums over the outputs of the
@@ -1520,7 +1535,7 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
     nacc[0] = nacc[1] = nacc[2] = 0.0;
   };
 
-  cx<R> nxt[6];
+  LW nxt[6];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1536,13 +1551,19 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
     if (act) link_raw(0, q, xp, s, nxt);
     stage(xp, false);
     if (act) {
-      cx<R> m[9], sp[4][3], h[2][3];
+      if constexpr (F16) {
+        cx<R> uh[2][3];
+        const R w = term16(0, true, t, nxt, uh);
+        carry16(uh, w);
+      } else {
+        cx<R> m[9], sp[4][3], h[2][3];
 #pragma unroll
-      for (int e = 0; e < 6; ++e) m[e] = nxt[e];
-      third_row<R>(m);
-      const R w = get(t, sp);
-      project<R>(0, true, sp, h);
-      carry_of(m, h, w);
+        for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+        third_row<R>(m);
+        const R w = get(t, sp);
+        project<R>(0, true, sp, h);
+        carry_of(m, h, w);
+      }
       if (x0a == 0)
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -1566,20 +1587,26 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
     if (act) {
       if (fin) {
         if (use_f) {
-          cx<R> m[9], sp[4][3], h[2][3], uh[2][3];
+          if constexpr (F16) {
+            cx<R> uh[2][3];
+            const R w = term16(0, false, t, nxt, uh);    // link loaded with this slice
+            recon(0, false, uh, xo == g.L0 - 1 ? -w : w);
+          } else {
+            cx<R> m[9], sp[4][3], h[2][3], uh[2][3];
 #pragma unroll
-          for (int e = 0; e < 6; ++e) m[e] = nxt[e];   // loaded with this slice
-          third_row<R>(m);
-          const R w = get(t, sp);
-          project<R>(0, false, sp, h);
-          su3_mul<R>(m, h[0], uh[0]);
-          su3_mul<R>(m, h[1], uh[1]);
-          if (xo == g.L0 - 1)
+            for (int e = 0; e < 6; ++e) m[e] = nxt[e];   // loaded with this slice
+            third_row<R>(m);
+            const R w = get(t, sp);
+            project<R>(0, false, sp, h);
+            su3_mul<R>(m, h[0], uh[0]);
+            su3_mul<R>(m, h[1], uh[1]);
+            if (xo == g.L0 - 1)
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+              for (int k = 0; k < 2; ++k)
 #pragma unroll
-              for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
-          recon(0, false, uh, w);
+                for (int c = 0; c < 3; ++c) uh[k][c] = -uh[k][c];
+            recon(0, false, uh, w);
+          }
         }
         if constexpr (F16) {
           static_assert(!F16 || RED <= 1, "FP16 storage fuses the norm only");
@@ -1604,7 +1631,7 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
           const int h3b = b ? lx3 : (lx3 == 0 ? L3h - 1 : lx3 - 1);
           // spatial hop i = 2 (mu - 1) + dir; the link of hop i + 1 is loaded before the
           // arithmetic of hop i
-          auto hop_link = [&](int i, cx<R> raw[6]) {
+          auto hop_link = [&](int i, LW raw[6]) {
             const int mu = 1 + i / 2;
             if (i & 1) link_raw(mu, q, x0, i >= 4 ? s - lx3 + h3b : s + dsn[i], raw);
             else link_raw(mu, p, x0, s, raw);
@@ -1614,22 +1641,33 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
           for (int i = 0; i < 6; ++i) {
             const int mu = 1 + i / 2, dir = i & 1;
             const int k = i >= 4 ? t - lx3 + (i == 4 ? h3f : h3b) : kn[i];
-            cx<R> m[9], sp[4][3], h[2][3], uh[2][3];
+            if constexpr (F16) {
+              LW cur[6];
 #pragma unroll
-            for (int e = 0; e < 6; ++e) m[e] = nxt[e];
-            if (i < 5) hop_link(i + 1, nxt);
-            else if (carry_next) link_raw(0, q, x0, s, nxt);
-            const R w = get(k, sp);
-            third_row<R>(m);
-            project<R>(mu, dir == 1, sp, h);
-            if (dir == 0) {
-              su3_mul<R>(m, h[0], uh[0]);
-              su3_mul<R>(m, h[1], uh[1]);
+              for (int e = 0; e < 6; ++e) cur[e] = nxt[e];
+              if (i < 5) hop_link(i + 1, nxt);
+              else if (carry_next) link_raw(0, q, x0, s, nxt);
+              cx<R> uh[2][3];
+              const R w = term16(mu, dir == 1, k, cur, uh);
+              recon(mu, dir == 1, uh, w);
             } else {
-              su3_dag_mul<R>(m, h[0], uh[0]);
-              su3_dag_mul<R>(m, h[1], uh[1]);
+              cx<R> m[9], sp[4][3], h[2][3], uh[2][3];
+#pragma unroll
+              for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+              if (i < 5) hop_link(i + 1, nxt);
+              else if (carry_next) link_raw(0, q, x0, s, nxt);
+              const R w = get(k, sp);
+              third_row<R>(m);
+              project<R>(mu, dir == 1, sp, h);
+              if (dir == 0) {
+                su3_mul<R>(m, h[0], uh[0]);
+                su3_mul<R>(m, h[1], uh[1]);
+              } else {
+                su3_dag_mul<R>(m, h[0], uh[0]);
+                su3_dag_mul<R>(m, h[1], uh[1]);
+              }
+              recon(mu, dir == 1, uh, w);
             }
-            recon(mu, dir == 1, uh, w);
             // the accumulator is next read in the following step: without this pin the
             // compiler sinks the arithmetic of all six hops below their loads and spills
 #pragma unroll
@@ -1640,17 +1678,30 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
         }
         // backward half-spinor of output x0 + 1 from slice x0
         if (carry_next) {
-          cx<R> m[9], sp[4][3], h[2][3];
-          if (sel) {
+          if constexpr (F16) {
+            LW cur[6];
+            if (sel) {
 #pragma unroll
-            for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+              for (int e = 0; e < 6; ++e) cur[e] = nxt[e];
+            } else {
+              link_raw(0, q, x0, s, cur);
+            }
+            cx<R> uh[2][3];
+            const R w = term16(0, true, t, cur, uh);
+            carry16(uh, w);
           } else {
-            link_raw(0, q, x0, s, m);
+            cx<R> m[9], sp[4][3], h[2][3];
+            if (sel) {
+#pragma unroll
+              for (int e = 0; e < 6; ++e) m[e] = nxt[e];
+            } else {
+              link_raw(0, q, x0, s, m);
+            }
+            third_row<R>(m);
+            const R w = get(t, sp);
+            project<R>(0, true, sp, h);
+            carry_of(m, h, w);
           }
-          third_row<R>(m);
-          const R w = get(t, sp);
-          project<R>(0, true, sp, h);
-          carry_of(m, h, w);
         }
       }
     }

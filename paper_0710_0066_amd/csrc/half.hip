@@ -1,7 +1,8 @@
-// FP16 storage: the Wilson hop on FP16 spinors (per-site FP32 norm) and FP16 links with
-// FP32 arithmetic (Sec. 1, eq. 2; the same operator as dslash.hip). Loads and stores are
-// per site: a site's 12 components are scaled by its norm on load, and on store the norm
-// is recomputed as the largest component magnitude.
+// FP16 storage: the Wilson hop on FP16 spinors (per-site FP32 norm) and FP16 links (Sec. 1,
+// eq. 2; the same operator as dslash.hip). Each hop term runs on the stored halves
+// (site_io.h, hop16_term: packed FP16 projection, v_dot2_f32_f16 products summed in FP32);
+// the neighbour's norm scales the term in the FP32 reconstruction, and on store the
+// output site's norm is recomputed as its largest component magnitude.
 //
 // Two work-item mappings: one (output site, rhs) per work-item with workgroups
 // rhs-fastest and renumbered per XCD (SITE), and the x0-marching order of dslash.hip with
@@ -11,14 +12,6 @@
 #include "site_io.h"
 
 namespace sap {
-
-// FP16 links keep the first two rows (see the layout of the reduced link copies); the
-// third is rebuilt in FP32 from unitarity and unit determinant
-__device__ __forceinline__ void load_link16(const __half2* U, long long Vhp, int mu, int par, long long j,
-                                            cx<float> m[9]) {
-  load_link16_raw(U + par * 24 * Vhp + (j >> 6) * (24 * TILE) + 6 * mu * TILE, (int)(j & (TILE - 1)), m);
-  third_row<float>(m);
-}
 
 // all eight hops of output site j of parity p for the rhs r0 .. r0 + nr - 1 (nr <= NR):
 // out = a x + b (g5_out) D (g5_in in), zero on unselected sites; each link is loaded once.
@@ -38,7 +31,6 @@ __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long lo
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc[r][a][c] = {0.0f, 0.0f};
   if (sel) {
-    constexpr bool g5i = G5I;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
 #pragma unroll
@@ -47,34 +39,29 @@ __device__ __forceinline__ void hop16_site(const HopArgs<h16>& A, int p, long lo
                                  : !(A.lb && mu == 0 && (s.x0 % A.lb) == 0);
         if (!on) continue;
         const long long jn = nbr(g, s, j, mu, dir == 0 ? +1 : -1);
-        cx<float> m[9];
-        if (dir == 0) load_link16(A.U, Vhp, mu, p, j, m);
-        else load_link16(A.U, Vhp, mu, 1 - p, jn, m);
+        unsigned e[9];
+        if (dir == 0)
+          load_link16_words(A.U + p * 24 * Vhp + (j >> 6) * (24 * TILE) + 6 * mu * TILE, (int)(j & (TILE - 1)), e);
+        else
+          load_link16_words(A.U + (1 - p) * 24 * Vhp + (jn >> 6) * (24 * TILE) + 6 * mu * TILE,
+                            (int)(jn & (TILE - 1)), e);
+        third_row16(e);
         const bool flip = mu == 0 && (dir == 0 ? s.x0 == g.L0 - 1 : s.x0 == 0);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           if (r >= nr) continue;
-          cx<float> sp[4][3], h[2][3], uh[2][3];
           // the stored (norm-divided) components; the site norm goes into the
           // multiply-adds of the reconstruction
-          SiteR<h16> in = site_r(A.in, r0 + r, 1 - p, jn, Vhp);
-          const float w = flip ? -in.m : in.m;
-          in.m = 1.0f;
+          const SiteR<h16> in = site_r(A.in, r0 + r, 1 - p, jn, Vhp);
+          unsigned sw[12];
 #pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const cx<float> v = get(in, 3 * a + c);
-              sp[a][c] = (g5i && a >= 2) ? -v : v;
-            }
-          project<float>(mu, dir == 1, sp, h);
-          if (dir == 0) {
-            su3_mul<float>(m, h[0], uh[0]);
-            su3_mul<float>(m, h[1], uh[1]);
-          } else {
-            su3_dag_mul<float>(m, h[0], uh[0]);
-            su3_dag_mul<float>(m, h[1], uh[1]);
+          for (int k = 0; k < 3; ++k) {
+            const u4v q = *(const u4v*)(in.b + 4 * k * TILE);
+            sw[4 * k] = q.x; sw[4 * k + 1] = q.y; sw[4 * k + 2] = q.z; sw[4 * k + 3] = q.w;
           }
+          const float w = flip ? -in.m : in.m;
+          cx<float> uh[2][3];
+          hop16_term<G5I>(mu, dir == 1, e, sw, uh);
           accum_recon_scaled<float>(mu, dir == 1, uh, w, acc[r]);
         }
       }

@@ -42,18 +42,117 @@ typedef unsigned u4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ __half2 h2_of(unsigned u) { return __builtin_bit_cast(__half2, u); }
 __device__ __forceinline__ unsigned u_of(__half2 h) { return __builtin_bit_cast(unsigned, h); }
 
-// the six stored entries of an FP16 link: t points at the link's block of its tile row
-// (p*24*Vhp + (j / 64)*24*64 + 6 mu*64), lane = j % 64 (a quad and a pair, see the layout)
-__device__ __forceinline__ void load_link16_raw(const __half2* t, int lane, cx<float> raw[6]) {
+// ---------------------------------------------------------------------------------
+// Packed-FP16 form of one hop term (FP16 storage). A site's stored (norm-divided) half2
+// components are projected with packed FP16 adds: each projected component is the sum of
+// two halves rounded once, the value of an FP32 sum rounded to FP16. The SU(3) product
+// runs on v_dot2_f32_f16: its two FP16 x FP16 products are exact in FP32 and added in
+// FP32. Apart from the rounding of the projected half spinor (and of the rebuilt third
+// link row) to FP16, the term is thus computed in FP32, without converting the stored
+// components of the neighbour. The projection writes each colour component h of the
+// half spinor as the two operands the complex products need:
+//   w = u h:        re = dot2(u, (h.r, -h.i)),  im = dot2(u, (h.i,  h.r))
+//   w = conj(u) h:  re = dot2(u, (h.r,  h.i)),  im = dot2(u, (h.i, -h.r))
+// with u = (u.r, u.i) the stored link entry; the swaps and signs fold into the operand
+// modifiers of the packed adds.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2v hv(unsigned u) { return __builtin_bit_cast(h2v, u); }
+
+// the compiler's own dot2 (not inline asm: a DOT result read soon after by another DOT or
+// VALU instruction needs wait states that only the compiler's hazard recognizer inserts)
+__device__ __forceinline__ float dot2(unsigned a, h2v b, float c) { return __builtin_amdgcn_fdot2(hv(a), b, c, false); }
+
+// the six stored entries (rows 0 and 1) of an FP16 link as half2 words: t points at the
+// link's block of its tile row (p*24*Vhp + (j / 64)*24*64 + 6 mu*64), lane = j % 64 (a quad
+// and a pair, see the layout of the reduced link copies)
+__device__ __forceinline__ void load_link16_words(const __half2* t, int lane, unsigned e[6]) {
   const u4v q = *(const u4v*)(t + 4 * lane);
   typedef unsigned u2v __attribute__((ext_vector_type(2)));
   const u2v d = *(const u2v*)(t + 4 * TILE + 2 * lane);
-  const unsigned e[6] = {q.x, q.y, q.z, q.w, d.x, d.y};
+  e[0] = q.x; e[1] = q.y; e[2] = q.z; e[3] = q.w; e[4] = d.x; e[5] = d.y;
+}
+
+// e[6..8] = third row of the link from its stored rows e[0..5], rebuilt in FP32 (unitarity
+// and unit determinant) and rounded to FP16
+__device__ __forceinline__ void third_row16(unsigned e[9]) {
+  cx<float> m[9];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float2 h = __half22float2(h2_of(e[i]));
-    raw[i] = {h.x, h.y};
+    const float2 f = __half22float2(h2_of(e[i]));
+    m[i] = {f.x, f.y};
   }
+  third_row<float>(m);
+#pragma unroll
+  for (int i = 6; i < 9; ++i) e[i] = u_of(__floats2half2_rn(m[i].r, m[i].i));
+}
+
+// the (1 -/+ gamma_mu) projection of the chiral basis (device_common.h, project) of
+// packed components s[3*spin + colour], as the operand pairs (x, y) of the products with
+// U (plus false) or U^dagger (plus true); G5I: gamma_5 is applied to s first
+template <bool G5I>
+__device__ __forceinline__ void project16(int mu, bool plus, const unsigned s[12], h2v x[2][3], h2v y[2][3]) {
+  auto ti = [](h2v v) { return h2v{-v.y, v.x}; };   // i v
+  // h = u + dp
+  auto put2 = [&](h2v u, h2v dp, h2v& hx, h2v& hy) {
+    if (!plus) {
+      hx = h2v{u.x, -u.y} + h2v{dp.x, -dp.y};
+      hy = h2v{u.y, u.x} + h2v{dp.y, dp.x};
+    } else {
+      hx = u + dp;
+      hy = h2v{u.y, -u.x} + h2v{dp.y, -dp.x};
+    }
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const h2v u0 = hv(s[c]), u1 = hv(s[3 + c]);
+    h2v d0 = hv(s[6 + c]), d1 = hv(s[9 + c]);
+    if (G5I) { d0 = -d0; d1 = -d1; }
+    switch (mu) {
+      case 0:
+        put2(u0, plus ? -d0 : d0, x[0][c], y[0][c]);
+        put2(u1, plus ? -d1 : d1, x[1][c], y[1][c]);
+        break;
+      case 1:
+        put2(u0, plus ? -ti(d1) : ti(d1), x[0][c], y[0][c]);
+        put2(u1, plus ? -ti(d0) : ti(d0), x[1][c], y[1][c]);
+        break;
+      case 2:
+        put2(u0, plus ? -d1 : d1, x[0][c], y[0][c]);
+        put2(u1, plus ? d0 : -d0, x[1][c], y[1][c]);
+        break;
+      default:
+        put2(u0, plus ? -ti(d0) : ti(d0), x[0][c], y[0][c]);
+        put2(u1, plus ? ti(d1) : -ti(d1), x[1][c], y[1][c]);
+        break;
+    }
+  }
+}
+
+// w = U h (dag false) or U^dagger h (dag true) for the link entries e[9] (row-major half2
+// words) and the operand pairs of one projected colour vector h
+__device__ __forceinline__ void su3_dot2(bool dag, const unsigned e[9], const h2v x[3], const h2v y[3],
+                                         cx<float> w[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    auto U = [&](int b) { return dag ? e[3 * b + a] : e[3 * a + b]; };
+    float re = dot2(U(0), x[0], 0.0f);
+    float im = dot2(U(0), y[0], 0.0f);
+    re = dot2(U(1), x[1], re);
+    im = dot2(U(1), y[1], im);
+    re = dot2(U(2), x[2], re);
+    im = dot2(U(2), y[2], im);
+    w[a] = {re, im};
+  }
+}
+
+// w = U h or U^dagger h (plus) of the projection of the packed spinor s
+template <bool G5I>
+__device__ __forceinline__ void hop16_term(int mu, bool plus, const unsigned e[9], const unsigned s[12],
+                                           cx<float> w[2][3]) {
+  h2v x[2][3], y[2][3];
+  project16<G5I>(mu, plus, s, x, y);
+  su3_dot2(plus, e, x[0], y[0], w[0]);
+  su3_dot2(plus, e, x[1], y[1], w[1]);
 }
 
 template <class R> __device__ __forceinline__ cx<arith_t<R>> get(const SiteR<R>& s, int c) {
