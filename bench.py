@@ -33,7 +33,7 @@ REAL = {"f64": 8, "f32": 4, "f16": 2}
 FLOP_PER_SITE = 1320      # hop of eq. 2 per output site and rhs (secondary figure)
 # hop mappings of the timed 12-rhs even-odd launches (one kernel per line, profile and
 # counter set); the full-size parity test sets the same ones
-HEADLINE_MAPS = {"f32": "slabd", "f64": "slab1w", "f16": "march2"}
+HEADLINE_MAPS = {"f32": "slabd", "f64": "slab1w", "f16": "slabd"}
 ROTATE = 3                # contexts the single-rhs operators rotate over
 
 

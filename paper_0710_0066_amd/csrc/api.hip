@@ -101,7 +101,7 @@ int sap_create(const sap_geom* g, sap_ctx** out) {
   if (hipMalloc((void**)&c->U64, nlink * sizeof(double2)) != hipSuccess ||
       hipMalloc((void**)&c->U64c, nlink2 * sizeof(double2)) != hipSuccess ||
       hipMalloc((void**)&c->U32, nlink2 * sizeof(float2)) != hipSuccess ||
-      hipMalloc((void**)&c->U16, nlink2 * sizeof(__half2)) != hipSuccess) {
+      hipMalloc((void**)&c->U16, (nlink2 + nlink) * sizeof(__half2)) != hipSuccess) {   // 2-row + 3-row
     sap_destroy(c);
     return sap_fail(nullptr, SAP_E_NOMEM, "cannot allocate the gauge copies");
   }

@@ -1226,7 +1226,7 @@ void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
 // FP16 output site j of parity p and rhs r: out = a x + b (g5) acc, zero on unselected
 // sites, stored as three quad words (non-temporal) divided by the site norm (the largest
 // component magnitude), and the norm. n2 (optional): += the squared norm of the values
-// before rounding to FP16.
+// before rounding to FP16 (summed over the site in FP32, added in FP64).
 __device__ __forceinline__ void store_out16(const Field<h16>& out, const Field<h16>& x, int r, int p, long long j,
                                             long long Vhp, bool sel, bool g5o, float a, float b,
                                             const cx<float> acc[4][3], double* n2) {
@@ -1248,7 +1248,7 @@ __device__ __forceinline__ void store_out16(const Field<h16>& out, const Field<h
       }
     }
   }
-  float m = 0.0f;
+  float m = 0.0f, s2 = 0.0f;
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -1263,8 +1263,9 @@ __device__ __forceinline__ void store_out16(const Field<h16>& out, const Field<h
       }
       v[k] = sel ? val : cx<float>{0.0f, 0.0f};
       m = fmaxf(m, fmaxf(fabsf(v[k].r), fabsf(v[k].i)));
-      if (n2) *n2 += (double)v[k].r * v[k].r + (double)v[k].i * v[k].i;
+      s2 = fmaf(v[k].r, v[k].r, fmaf(v[k].i, v[k].i, s2));
     }
+  if (n2) *n2 += (double)s2;
   const float inv = m > 0.0f ? 1.0f / m : 0.0f;
   __half2* ob = out.ptr + r * out.rs + p * out.ps + sidx<h16>(j, 0);
 #pragma unroll
@@ -1316,6 +1317,7 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
   constexpr bool F16 = std::is_same<SR, h16>::value;
   constexpr int NW = F16 ? 3 : 6;               // 16-byte words per site
   using LW = std::conditional_t<F16, unsigned, cx<float>>;   // a stored link entry
+  constexpr int NL = F16 ? 9 : 6;               // entries per link (FP16: the three-row copy)
   extern __shared__ char smem_raw[];
   const lds_ptr<f4v> lds = (lds_ptr<f4v>)smem_raw;   // FP16: the words' bits
   const lds_ptr<float> ldn = (lds_ptr<float>)(smem_raw + NW * kSlabdUnit * 16);   // FP16 norms
@@ -1441,16 +1443,16 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
   };
   auto fwd_on = [&](int x) { return !(lb && (x % lb) == lb - 1); };
   auto bwd_on = [&](int x) { return !(lb && (x % lb) == 0); };
-  // two stored rows of a link: U_mu at slice-local site sl of slice x, parity par (the
-  // FP32 copy: three pair words per link, 12 words per site; the FP16 copy: a quad and a
-  // pair of half2 entries)
-  auto link_raw = [&](int mu, int par, int x, int sl, LW raw[6]) {
+  // stored entries of a link: U_mu at slice-local site sl of slice x, parity par (FP32: the
+  // two rows of the FP32 copy, three pair words per link; FP16: the nine entries of the
+  // three-row FP16 copy, two quads and a single entry)
+  auto link_raw = [&](int mu, int par, int x, int sl, LW raw[NL]) {
     if constexpr (F16) {
-      const __half2* ub = A.U + par * 24 * Vhp + 6 * mu * TILE;
-      if constexpr (LIN) load_link16_words(ub + (long long)x * V3h * 24 + (sl >> 6) * (64 * 24), sl & 63, raw);
+      const __half2* ub = A.U + 48 * Vhp + par * 36 * Vhp + 9 * mu * TILE;
+      if constexpr (LIN) load_link16x3_words(ub + (long long)x * V3h * 36 + (sl >> 6) * (64 * 36), sl & 63, raw);
       else {
         const long long j = (long long)x * V3h + sl;
-        load_link16_words(ub + (j >> 6) * (64 * 24), (int)(j & 63), raw);
+        load_link16x3_words(ub + (j >> 6) * (64 * 36), (int)(j & 63), raw);
       }
     } else {
       const f4v* u = word((const f4v*)A.U + par * 12 * Vhp, x, sl, 12) + 192 * mu;
@@ -1464,14 +1466,13 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
   };
 
   // FP16: w = U h (plus false) or U^dagger h (plus true) of the projection of LDS slot k,
-  // in packed FP16 (hop16_term) with the link entries lw; returns the site norm of slot k
-  // (the factor the callers fold into the reconstruction)
-  auto term16 = [&](int mu, bool plus, int k, const LW lw[6], cx<R> w[2][3]) -> R {
+  // in packed FP16 (hop16_term) with the nine link entries lw of the three-row copy;
+  // returns the site norm of slot k (the factor the callers fold into the reconstruction)
+  auto term16 = [&](int mu, bool plus, int k, const LW lw[NL], cx<R> w[2][3]) -> R {
     if constexpr (F16) {
       unsigned e[9], sw[12];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) e[i] = lw[i];
-      third_row16(e);
+      for (int i = 0; i < 9; ++i) e[i] = lw[i];
       const R m = *(const volatile __attribute__((address_space(3))) float*)(ldn + k);
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
@@ -1535,7 +1536,7 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
     nacc[0] = nacc[1] = nacc[2] = 0.0;
   };
 
-  LW nxt[6];
+  LW nxt[NL], alt[NL];   // alt: FP16 only (odd spatial hops)
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -1631,7 +1632,7 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
           const int h3b = b ? lx3 : (lx3 == 0 ? L3h - 1 : lx3 - 1);
           // spatial hop i = 2 (mu - 1) + dir; the link of hop i + 1 is loaded before the
           // arithmetic of hop i
-          auto hop_link = [&](int i, LW raw[6]) {
+          auto hop_link = [&](int i, LW raw[NL]) {
             const int mu = 1 + i / 2;
             if (i & 1) link_raw(mu, q, x0, i >= 4 ? s - lx3 + h3b : s + dsn[i], raw);
             else link_raw(mu, p, x0, s, raw);
@@ -1642,13 +1643,18 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
             const int mu = 1 + i / 2, dir = i & 1;
             const int k = i >= 4 ? t - lx3 + (i == 4 ? h3f : h3b) : kn[i];
             if constexpr (F16) {
-              LW cur[6];
-#pragma unroll
-              for (int e = 0; e < 6; ++e) cur[e] = nxt[e];
-              if (i < 5) hop_link(i + 1, nxt);
-              else if (carry_next) link_raw(0, q, x0, s, nxt);
+              // the links of hops 0, 2, 4 in nxt and of 1, 3, 5 in alt, so that the next
+              // link is loaded into the other buffer without copying the current one
               cx<R> uh[2][3];
-              const R w = term16(mu, dir == 1, k, cur, uh);
+              R w;
+              if (i & 1) {
+                if (i < 5) hop_link(i + 1, nxt);
+                else if (carry_next) link_raw(0, q, x0, s, nxt);
+                w = term16(mu, dir == 1, k, alt, uh);
+              } else {
+                hop_link(i + 1, alt);
+                w = term16(mu, dir == 1, k, nxt, uh);
+              }
               recon(mu, dir == 1, uh, w);
             } else {
               cx<R> m[9], sp[4][3], h[2][3], uh[2][3];
@@ -1679,10 +1685,10 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
         // backward half-spinor of output x0 + 1 from slice x0
         if (carry_next) {
           if constexpr (F16) {
-            LW cur[6];
+            LW cur[NL];
             if (sel) {
 #pragma unroll
-              for (int e = 0; e < 6; ++e) cur[e] = nxt[e];
+              for (int e = 0; e < NL; ++e) cur[e] = nxt[e];
             } else {
               link_raw(0, q, x0, s, cur);
             }

@@ -146,7 +146,8 @@ struct sap_ctx {
   double2* U64;   // tiled gauge layout, 72*Vhp complex (whole links: forces, link updates)
   double2* U64c;  // two-row FP64 copy read by the hop kernels (48*Vhp complex)
   float2* U32;    // two-row FP32 copy
-  __half2* U16;   // two-row FP16 copy (all three kept in step with U64)
+  __half2* U16;   // two-row FP16 copy (48*Vhp), then the three-row FP16 copy (72*Vhp) the
+                  // LDS-staged FP16 hop reads (all copies kept in step with U64)
   std::string err;
   void* solver;   // solver workspace (solver.hip)
   void* forces;   // force / trajectory workspace (hmc.hip)

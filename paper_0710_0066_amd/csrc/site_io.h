@@ -72,6 +72,17 @@ __device__ __forceinline__ void load_link16_words(const __half2* t, int lane, un
   e[0] = q.x; e[1] = q.y; e[2] = q.z; e[3] = q.w; e[4] = d.x; e[5] = d.y;
 }
 
+// the nine entries of an FP16 link of the three-row copy as half2 words: t points at the
+// link's block of its tile row (48*Vhp + p*36*Vhp + (j / 64)*36*64 + 9 mu*64), lane =
+// j % 64 (two quads and a single entry; three loads)
+__device__ __forceinline__ void load_link16x3_words(const __half2* t, int lane, unsigned e[9]) {
+  const u4v q0 = *(const u4v*)(t + 4 * lane);
+  const u4v q1 = *(const u4v*)(t + 4 * TILE + 4 * lane);
+  e[0] = q0.x; e[1] = q0.y; e[2] = q0.z; e[3] = q0.w;
+  e[4] = q1.x; e[5] = q1.y; e[6] = q1.z; e[7] = q1.w;
+  e[8] = *(const unsigned*)(t + 8 * TILE + lane);
+}
+
 // e[6..8] = third row of the link from its stored rows e[0..5], rebuilt in FP32 (unitarity
 // and unit determinant) and rounded to FP16
 __device__ __forceinline__ void third_row16(unsigned e[9]) {
