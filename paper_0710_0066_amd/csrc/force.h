@@ -1,6 +1,7 @@
 // Launchers of the force / molecular-dynamics kernels (force.hip).
 #pragma once
 #include "internal.h"
+#include "link_copies.h"
 
 namespace sap {
 // F += c * Im tr(lambda^a Q) per link (c = -kappa * coef), W = M (lb = 0) or x0 blocks of lb
@@ -18,7 +19,9 @@ void launch_plaq_sum(const Geo& g, const double2* U, double* part, double* out, 
 void launch_su3_dev(const Geo& g, const double2* U, double* part, double* out, hipStream_t s);
 void launch_kinetic(const Geo& g, const double* P, double* part, double* out, hipStream_t s);
 void launch_norm2_full(const Geo& g, const double2* f, double* part, double* out, hipStream_t s);
-void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s,
+// U <- exp(dt P) U on every link (scaled per link by sx when given), also writing the
+// reduced copies lc of the updated links (write_link_copies)
+void launch_update_links(const Geo& g, double2* U, const LinkCopies& lc, const double* P, double dt, hipStream_t s,
                          const double* sx = nullptr);
 // mode 0: gamma5; 1: Pi (black-boundary projector, blocks of l0); 2: keep white blocks; 3: in - Pi in2.
 // outer > 0: Pi keeps only the boundary slices whose crossing hop exists in W_outer.

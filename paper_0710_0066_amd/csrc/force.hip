@@ -372,7 +372,7 @@ __device__ M3 reunitarize(const M3& U) {
 }
 
 // U_mu(x) <- exp(i dt P_mu(x)) U_mu(x), P = sum_a p^a lambda^a / 2
-__global__ __launch_bounds__(256) void k_update_links(Geo g, double2* U, const double* Pm, double dt0,
+__global__ __launch_bounds__(256) void k_update_links(Geo g, double2* U, LinkCopies lc, const double* Pm, double dt0,
                                                       const double* sx) {
   const int p = threadIdx.x >> 7;
   const long long j = (long long)blockIdx.x * 128 + (threadIdx.x & 127);
@@ -400,6 +400,11 @@ __global__ __launch_bounds__(256) void k_update_links(Geo g, double2* U, const d
     const M3 E = expm_ah(A);
     const M3 Un = reunitarize(mmul(E, load_U(U, g.Vhp, p, j, mu)));
     store_U(U, g.Vhp, p, j, mu, Un);
+    // the reduced copies of the hop kernels, from the new link in registers
+    double2 e[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) e[k] = make_double2(Un.m[k].r, Un.m[k].i);
+    write_link_copies(lc, g.Vhp, p, j, mu, e);
   }
 }
 
@@ -573,8 +578,9 @@ void launch_norm2_full(const Geo& g, const double2* f, double* part, double* out
   hipLaunchKernelGGL(k_norm2_full, dim3(site_blocks(g)), dim3(256), 0, s, g, f, part);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, (int)site_blocks(g), part, out);
 }
-void launch_update_links(const Geo& g, double2* U, const double* P, double dt, hipStream_t s, const double* sx) {
-  hipLaunchKernelGGL(k_update_links, dim3(site_blocks(g)), dim3(256), 0, s, g, U, P, dt, sx);
+void launch_update_links(const Geo& g, double2* U, const LinkCopies& lc, const double* P, double dt, hipStream_t s,
+                         const double* sx) {
+  hipLaunchKernelGGL(k_update_links, dim3(site_blocks(g)), dim3(256), 0, s, g, U, lc, P, dt, sx);
 }
 void launch_spin_op(const Geo& g, int mode, int l0, double2* out, const double2* in, const double2* in2,
                     hipStream_t s, int outer) {

@@ -321,6 +321,7 @@ int kinetic_host(sap_ctx* c, const double* P, double* K, hipStream_t s) {
 }
 
 void links_changed(sap_ctx* c, hipStream_t s) { launch_gauge_to_f32(c->g, c->U64c, c->U32, c->U16, c->U64, s); }
+LinkCopies copies_of(sap_ctx* c) { return LinkCopies{c->U64c, c->U32, c->U16}; }
 
 // ---- the two-level integrator --------------------------------------------------------
 struct Traj {
@@ -342,8 +343,7 @@ int kick_g(Traj& T, double dt) {
   return SAP_OK;
 }
 int move_links(Traj& T, double dt) {
-  launch_update_links(T.c->g, T.c->U64, fws(T.c)->mom, dt, T.s, T.sx);
-  links_changed(T.c, T.s);
+  launch_update_links(T.c->g, T.c->U64, copies_of(T.c), fws(T.c)->mom, dt, T.s, T.sx);   // copies too
   SAP_HIP_CHECK(T.c, hipGetLastError());
   return SAP_OK;
 }
@@ -426,8 +426,7 @@ int kick4(Traj4& T, int j, double dt) {
 }
 
 int move4(Traj4& T, double dt) {
-  launch_update_links(T.c->g, T.c->U64, fws(T.c)->mom, dt, T.s, T.sx);
-  links_changed(T.c, T.s);
+  launch_update_links(T.c->g, T.c->U64, copies_of(T.c), fws(T.c)->mom, dt, T.s, T.sx);   // copies too
   SAP_HIP_CHECK(T.c, hipGetLastError());
   return SAP_OK;
 }
@@ -590,8 +589,7 @@ int sap_update_links(sap_ctx* c, const double* p, double dt, void* stream) {
   if (!p) return sap_fail(c, SAP_E_ARG, "p is NULL");
   if (!c->have_gauge) return sap_fail(c, SAP_E_STATE, "no gauge field set");
   hipStream_t s = (hipStream_t)stream;
-  launch_update_links(c->g, c->U64, p, dt, s);
-  links_changed(c, s);
+  launch_update_links(c->g, c->U64, copies_of(c), p, dt, s);   // writes the reduced copies too
   SAP_HIP_CHECK(c, hipGetLastError());
   return SAP_OK;
 }

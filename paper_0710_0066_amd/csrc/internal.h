@@ -118,7 +118,9 @@ void launch_unpack_spinor(const Geo& g, double2* out, const typename vec2<R>::ty
                           int nrhs, hipStream_t s);
 void launch_pack_gauge(const Geo& g, double2* U64, float2* U32, const double2* in, hipStream_t s);
 void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStream_t s);
-// the two-row FP64, FP32 and FP16 link copies of the hop kernels from the FP64 links
+// the reduced link copies of the hop kernels from the FP64 links: two-row FP64, FP32 and
+// FP16 copies, then the three-row FP16 copy of the LDS-staged FP16 hop (layouts in
+// layout.hip)
 void launch_gauge_to_f32(const Geo& g, double2* U64c, float2* U32, __half2* U16, const double2* U64, hipStream_t s);
 void launch_pack_spinor16(const Geo& g, __half2* out, const double2* in, int nrhs, hipStream_t s);
 void launch_unpack_spinor16(const Geo& g, double2* out, const __half2* in, int nrhs, hipStream_t s);

@@ -2,6 +2,7 @@
 // array-of-structures complex128) and the library's even-odd structure-of-arrays
 // layout. One work-item per site (and rhs); not on the hot path.
 #include "internal.h"
+#include "link_copies.h"
 
 namespace sap {
 
@@ -92,36 +93,22 @@ __global__ void unpack_gauge_kernel(Geo g, double2* out, const double2* U64) {
 // pair (e = 4, 5, 8 bytes per lane):
 //   p*24*Vhp + (j / 64)*24*64 + 6 mu*64 + (e < 4 ? 4*(j % 64) + e : 256 + 2*(j % 64) + e - 4),
 // two loads per link. The LDS-staged FP16 hop, with one rhs per work-item, reads a
-// three-row copy instead (below) so that it does not rebuild the third row for every term.
-__global__ void gauge_to_f32_kernel(long long Vhp, double2* U64c, float2* U32, __half2* U16, const double2* U64) {
-  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= 48 * Vhp) return;
-  const long long p = k / (24 * Vhp), r = k - p * 24 * Vhp;
-  const long long tile = r / (24 * TILE), c = (r / TILE) % 24, lane = r % TILE;
-  const long long j = tile * TILE + lane;
-  const double2 v = U64[p * 36 * Vhp + tiled(j, (int)(9 * (c / 6) + c % 6), 36)];
-  U64c[k] = v;
-  U32[p * 24 * Vhp + tile * 24 * TILE + (c - (c & 1)) * TILE + 2 * lane + (c & 1)] = make_float2((float)v.x, (float)v.y);
-  const long long e = c % 6, mu = c / 6;
-  U16[p * 24 * Vhp + tile * 24 * TILE + 6 * mu * TILE + (e < 4 ? 4 * lane + e : 4 * TILE + 2 * lane + e - 4)] =
-      __floats2half2_rn((float)v.x, (float)v.y);
-}
-
-// the three-row FP16 copy after the two-row one (U16 + 48*Vhp): all nine entries of a link
-// of a tile row as two quads (e = 0..3, 4..7) and a single entry (e = 8),
+// three-row copy instead, so that it does not rebuild the third row for every term: after
+// the two-row copy (at U16 + 48*Vhp) it holds all nine entries of a link of a tile row as
+// two quads (e = 0..3, 4..7) and a single entry,
 //   p*36*Vhp + (j / 64)*36*64 + 9 mu*64 + (e < 4 ? 4*(j % 64) + e : e < 8 ? 256 + 4*(j % 64) + e - 4 : 512 + j % 64),
-// each entry rounded from the FP64 link (the third row is not rebuilt from rounded rows)
-__global__ void gauge_to_f16x3_kernel(long long Vhp, __half2* U16x3, const double2* U64) {
+// each entry rounded from the FP64 link (the third row is not rebuilt from rounded rows).
+// internal.h (write_link_copies) writes all copies of one link; this kernel runs it with
+// one work-item per link (site j fastest).
+__global__ void gauge_to_f32_kernel(long long Vhp, LinkCopies lc, const double2* U64) {
   const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= 72 * Vhp) return;
-  const long long p = k / (36 * Vhp), r = k - p * 36 * Vhp;
-  const long long tile = r / (36 * TILE), c = (r / TILE) % 36, lane = r % TILE;
-  const long long j = tile * TILE + lane;
-  const double2 v = U64[p * 36 * Vhp + tiled(j, (int)c, 36)];
-  const long long e = c % 9, mu = c / 9;
-  U16x3[p * 36 * Vhp + tile * 36 * TILE + 9 * mu * TILE +
-        (e < 4 ? 4 * lane + e : e < 8 ? 4 * TILE + 4 * lane + e - 4 : 8 * TILE + lane)] =
-      __floats2half2_rn((float)v.x, (float)v.y);
+  if (k >= 8 * Vhp) return;
+  const long long j = k % Vhp, r = k / Vhp;
+  const int mu = (int)(r % 4), p = (int)(r / 4);
+  double2 e[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) e[c] = U64[p * 36 * Vhp + tiled(j, 9 * mu + c, 36)];
+  write_link_copies(lc, Vhp, p, j, mu, e);
 }
 
 // FP16 spinor fields: components divided by the site norm (the largest component
@@ -204,10 +191,8 @@ void launch_unpack_gauge(const Geo& g, double2* out, const double2* U64, hipStre
   hipLaunchKernelGGL(unpack_gauge_kernel, dim3(nblk(2 * g.Vh, 128)), dim3(128), 0, s, g, out, U64);
 }
 void launch_gauge_to_f32(const Geo& g, double2* U64c, float2* U32, __half2* U16, const double2* U64, hipStream_t s) {
-  long long n = 48LL * g.Vhp;
-  hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, g.Vhp, U64c, U32, U16, U64);
-  n = 72LL * g.Vhp;
-  hipLaunchKernelGGL(gauge_to_f16x3_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, g.Vhp, U16 + 48 * g.Vhp, U64);
+  const long long n = 8LL * g.Vhp;   // links: 2 parities x Vhp sites x 4 directions
+  hipLaunchKernelGGL(gauge_to_f32_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, g.Vhp, LinkCopies{U64c, U32, U16}, U64);
 }
 void launch_pack_spinor16(const Geo& g, __half2* out, const double2* in, int nrhs, hipStream_t s) {
   long long n = 2 * g.Vh * nrhs;
