@@ -191,19 +191,52 @@ def test_solve_blocks_f16_inner_matches_oracle(gu, method, level, color):
 
 
 def test_f16_links_follow_gauge_updates(gu):
-    """The FP16 link copy is refreshed when the links change (set_gauge and the HMC link
-    update): apply_M in FP16 tracks the oracle on the new field."""
+    """The reduced link copies follow the links when they change. After set_gauge, FP16
+    apply_M tracks the oracle on the new field. After the HMC link update (which writes
+    the copies itself) and after a translation in x0 (the copy kernel), the even-odd hop
+    matches the oracle on the links read back in FP64: in FP16 with the LDS-staged mapping
+    (which reads the three-row FP16 copy) and with march2 (the two-row copy), in FP32 and
+    in FP64."""
+    import torch
     import paper_0710_0066_amd as sap
     L, l0, k = (8, 4, 4, 4), 4, 0.15
     U0 = synth.gauge_field(L, 0.5, 1113)
     U1 = synth.gauge_field(L, 0.5, 1114)
     psi = synth.gaussian_spinor(L, 2113)
-    ctx = gu.make_ctx(L, l0, k, U0)
+    ctx = gu.make_ctx(L, l0, k, U0, max_rhs=2)
     ctx.set_gauge(gu.dev(U1))
     fout = ctx.new_field(1, sap.SAP_F16)
     sap.apply_M(ctx, fout, gu.to_sap(ctx, psi, 1, sap.SAP_F16), 1, sap.SAP_F16)
     got = gu.from_sap(ctx, fout, 1, psi.shape, sap.SAP_F16)
     assert _err_vs_input(got, dirac.apply_M(U1, psi, k), psi) <= F16_TOL
+
+    par = lattice.parity(L)
+    psi2 = synth.gaussian_spinor(L, 2114, nrhs=2)
+    cases = [(sap.SAP_F16, 20, F16_TOL / 0.16), (sap.SAP_F16, 12, F16_TOL / 0.16),
+             (sap.SAP_F32, 20, F32_TOL / 0.16), (sap.SAP_F64, 12, 1e-12)]
+
+    def check_hops(step):
+        Uo = torch.zeros(U1.size, dtype=torch.complex128, device="cuda")
+        ctx.get_gauge(Uo)
+        U = Uo.cpu().numpy().reshape(U1.shape)
+        for prec, hop_map, tol in cases:
+            sap.sap_set_hop_map(ctx, 0, prec, 2, hop_map)
+            fin = gu.to_sap(ctx, psi2, 2, prec)
+            fo = ctx.new_field(2, prec)
+            for parity in (0, 1):
+                m_out = lattice.site_mask(L, par == parity)
+                ref = dirac.hop(U, psi2 * lattice.site_mask(L, par != parity)) * m_out
+                sap.apply_Dslash_eo(ctx, fo, fin, 2, parity, prec)
+                got = gu.from_sap(ctx, fo, 2, psi2.shape, prec) * m_out
+                assert _err_vs_input(got, ref, psi2) <= tol, (step, prec, hop_map, parity)
+
+    P = ctx.new_momenta()
+    g = torch.Generator(device="cpu").manual_seed(1115)
+    P.copy_(0.3 * torch.randn(P.numel(), generator=g, dtype=torch.float64))
+    sap.sap_update_links(ctx, P, 0.7)
+    check_hops("update")
+    sap.sap_shift_gauge(ctx, 1)
+    check_hops("shift")
 
 
 F32_TOL = 64 * 2.0 ** -24      # the same bound with FP32 rounding, plus FP32 accumulation
