@@ -1225,11 +1225,13 @@ void hop_slab_kernel(HopArgs<R> A, int TA, int TB) {
 
 // FP16 output site j of parity p and rhs r: out = a x + b (g5) acc, zero on unselected
 // sites, stored as three quad words (non-temporal) divided by the site norm (the largest
-// component magnitude), and the norm. n2 (optional): += the squared norm of the values
-// before rounding to FP16 (summed over the site in FP32, added in FP64).
+// component magnitude), and the norm. Fused reductions of the values before their
+// rounding to FP16 (summed over the site in FP32, added in FP64): RED 1: red[0] +=
+// ||out||^2; RED 3: red[0..2] += Re <out, x>, Im <out, x> (out conjugated), ||out||^2.
+template <int RED>
 __device__ __forceinline__ void store_out16(const Field<h16>& out, const Field<h16>& x, int r, int p, long long j,
                                             long long Vhp, bool sel, bool g5o, float a, float b,
-                                            const cx<float> acc[4][3], double* n2) {
+                                            const cx<float> acc[4][3], double red[3]) {
   cx<float> v[12];
   const bool wx = sel && x.ptr;
   float xq[24];
@@ -1248,7 +1250,7 @@ __device__ __forceinline__ void store_out16(const Field<h16>& out, const Field<h
       }
     }
   }
-  float m = 0.0f, s2 = 0.0f;
+  float m = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -1263,9 +1265,18 @@ __device__ __forceinline__ void store_out16(const Field<h16>& out, const Field<h
       }
       v[k] = sel ? val : cx<float>{0.0f, 0.0f};
       m = fmaxf(m, fmaxf(fabsf(v[k].r), fabsf(v[k].i)));
-      s2 = fmaf(v[k].r, v[k].r, fmaf(v[k].i, v[k].i, s2));
+      if (RED == 1 || RED == 3) s2 = fmaf(v[k].r, v[k].r, fmaf(v[k].i, v[k].i, s2));
+      if (RED == 3 && wx) {
+        s0 = fmaf(v[k].r, xq[2 * k], fmaf(v[k].i, xq[2 * k + 1], s0));
+        s1 = fmaf(v[k].r, xq[2 * k + 1], fmaf(-v[k].i, xq[2 * k], s1));
+      }
     }
-  if (n2) *n2 += (double)s2;
+  if (RED == 1) red[0] += (double)s2;
+  if (RED == 3) {
+    red[0] += (double)s0;
+    red[1] += (double)s1;
+    red[2] += (double)s2;
+  }
   const float inv = m > 0.0f ? 1.0f / m : 0.0f;
   __half2* ob = out.ptr + r * out.rs + p * out.ps + sidx<h16>(j, 0);
 #pragma unroll
@@ -1610,9 +1621,8 @@ void hop_slabd_kernel(HopArgs<SR> A, int TA, int TB) {
           }
         }
         if constexpr (F16) {
-          static_assert(!F16 || RED <= 1, "FP16 storage fuses the norm only");
-          store_out16(A.out, A.x, r0, p, (long long)xo * V3h + s, Vhp, hop_selected(A, xo), G5O, A.a, A.b, acc,
-                      nrm ? &nacc[0] : nullptr);
+          store_out16<RED>(A.out, A.x, r0, p, (long long)xo * V3h + s, Vhp, hop_selected(A, xo), G5O, A.a, A.b,
+                           acc, nacc);
         } else {
           V2* o = A.out.ptr + r0 * A.out.rs + p * A.out.ps;
           const V2* xv = A.x.ptr ? A.x.ptr + r0 * A.x.rs + p * A.x.ps : nullptr;
@@ -1852,13 +1862,12 @@ template <class R> static void launch_slabd(const HopArgs<R>& A, hipStream_t st)
   hipLaunchKernelGGL((hop_slabd_kernel<R, LIN, G5I, G5O, RED>), grid, blk, lds, st, A, TA, TB)
     // the fused reductions exist without gamma_5 on the input (the solvers' second half
     // hops; they set npart only there): the norm with and without gamma_5 on the output
-    // (CG), the dot product and norm without (BiCGstab, FP32 only)
-    constexpr bool f32 = std::is_same<R, float>::value;
+    // (CG), the dot product and norm without (BiCGstab)
 #define SAP_SLABD_G5(LIN)                                                                  \
   do {                                                                                     \
     if (A.npart && A.red == 1 && !A.g5_in && A.g5_out) SAP_SLABD(LIN, false, true, 1);     \
     else if (A.npart && A.red == 1 && !A.g5_in) SAP_SLABD(LIN, false, false, 1);           \
-    else if (f32 && A.npart && A.red == 3 && !A.g5_in && !A.g5_out) SAP_SLABD(LIN, false, false, f32 ? 3 : 0); \
+    else if (A.npart && A.red == 3 && !A.g5_in && !A.g5_out) SAP_SLABD(LIN, false, false, 3); \
     else if (A.g5_in && A.g5_out) SAP_SLABD(LIN, true, true, 0);                           \
     else if (A.g5_in) SAP_SLABD(LIN, true, false, 0);                                      \
     else if (A.g5_out) SAP_SLABD(LIN, false, true, 0);                                     \

@@ -68,7 +68,7 @@ template <class R> struct HopArgs {
   // optional (HOP_MAP_SLABD only): per-system partial reductions of the output over
   // systems (rhs, block of nlb slices), nslot partials per system (see slabd_norm_slots):
   //   red = 1: ||out||^2 at npart[sys * nslot + k];
-  //   red = 3 (FP32): (Re, Im <out, x>, ||out||^2) with out conjugated, at
+  //   red = 3: (Re, Im <out, x>, ||out||^2) with out conjugated, at
   //   npart[3 (sys * nslot + k) + i].
   double* npart = nullptr;
   int nlb = 0, nslot = 0, red = 0;

@@ -273,12 +273,11 @@ static int solve_impl(sap_ctx* c, double* x, const double* b, int nrhs, int lb, 
       fin_geom(SC, nsys, G.nchunk, w->partB, w->selected, w->target2, 1, st);
     }
     SAP_HIP_CHECK(c, hipGetLastError());
-    // the LDS-staged hop writes the reductions of its output itself: ||M_hat p||^2 and
-    // ||M_hat^dagger s||^2 (CG; FP32 and FP16 storage, FP16 summing the values before their
-    // rounding to FP16), <t, s> and ||t||^2 (BiCGstab, FP32 only, three values per slot)
+    // the LDS-staged hop (FP32 and FP16 storage) writes the reductions of its output
+    // itself: ||M_hat p||^2 and ||M_hat^dagger s||^2 (CG), <t, s> and ||t||^2 (BiCGstab,
+    // three values per slot); FP16 sums the values before their rounding to FP16
     int nslot = 0;
-    constexpr bool fused_cg = std::is_same<R, float>::value || std::is_same<R, h16>::value;
-    if ((std::is_same<R, float>::value || (fused_cg && method == SAP_CG)) &&
+    if ((std::is_same<R, float>::value || std::is_same<R, h16>::value) && method != SAP_GEOM &&
         hop_map_for(c, false, prec_of<R>(), nrhs) == HOP_MAP_SLABD) {
       nslot = slabd_norm_slots(c->g, lb ? lb : c->geom.L[0]);
       const size_t per = method == SAP_CG ? 1 : 3;
